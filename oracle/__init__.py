@@ -1,0 +1,154 @@
+"""Python face of the sequential CPU oracle (``wt_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, ``__graft_entry__.smoke()`` and the
+benchmark's ``cpu_baseline`` leg may import this package.  The GPU library
+never calls it, and it never calls the GPU library: the two share no code.
+
+The C source follows the paper's per-level construction (Section 3.1, the
+pwt algorithm run sequentially) and the query walks of Section 2.3; see the
+header of ``wt_oracle.c`` for the readings taken where the paper is loose.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "wt_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, EINVAL, ERANGE, ENOMEM, ENOTFOUND = 0, 1, 2, 3, 4
+
+
+def compile_oracle(force: bool = True) -> str:
+    """Compile the oracle with gcc -O2 (the paper's optimisation level)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        compile_oracle(force=False)
+        L = ctypes.CDLL(_LIB)
+        u32, u64, vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p
+        L.wto_levels.argtypes = [u32]
+        L.wto_levels.restype = u32
+        L.wto_words_per_level.argtypes = [u64]
+        L.wto_words_per_level.restype = u64
+        L.wto_rank_entries.argtypes = [u64]
+        L.wto_rank_entries.restype = u64
+        L.wto_rank_stride.argtypes = [u64]
+        L.wto_rank_stride.restype = u64
+        L.wto_build.argtypes = [vp, u64, u32, u32, vp, vp]
+        L.wto_build.restype = ctypes.c_int
+        L.wto_access.argtypes = [vp, u64, u32, u64, vp, vp, vp]
+        L.wto_access.restype = ctypes.c_int
+        L.wto_rank.argtypes = [vp, u64, u32, u32, u64, vp]
+        L.wto_rank.restype = ctypes.c_int
+        L.wto_select.argtypes = [vp, u64, u32, u32, u64, vp]
+        L.wto_select.restype = ctypes.c_int
+        L.wto_decode.argtypes = [vp, u64, u32, vp]
+        L.wto_decode.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def levels(sigma: int) -> int:
+    return int(lib().wto_levels(sigma))
+
+
+def words_per_level(n: int) -> int:
+    return int(lib().wto_words_per_level(n))
+
+
+def rank_entries(n: int) -> int:
+    return int(lib().wto_rank_entries(n))
+
+
+def rank_stride(n: int) -> int:
+    return int(lib().wto_rank_stride(n))
+
+
+@dataclass
+class OracleTree:
+    n: int
+    sigma: int
+    levels: int
+    bitmaps: np.ndarray        # (levels, words_per_level(n)) uint64
+    ranks: np.ndarray | None   # (levels, rank_stride(n)) uint64, or None
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def build(S: np.ndarray, sigma: int, with_ranks: bool = True) -> OracleTree:
+    """Sequential construction of every level (and rank directory)."""
+    S = np.ascontiguousarray(S)
+    width = S.dtype.itemsize
+    n = int(S.shape[0])
+    lv = levels(sigma)
+    B = np.zeros((lv, words_per_level(n)), dtype=np.uint64)
+    R = np.zeros((lv, rank_stride(n)), dtype=np.uint64) if with_ranks else None
+    rc = lib().wto_build(_ptr(S), n, sigma, width, _ptr(B), _ptr(R) if R is not None else None)
+    if rc != OK:
+        raise ValueError("oracle build failed with status %d" % rc)
+    return OracleTree(n, sigma, lv, B, R)
+
+
+def build_status(S: np.ndarray, sigma: int, width: int | None = None) -> int:
+    """Raw status of a build (for argument-validation tests)."""
+    S = np.ascontiguousarray(S)
+    n = int(S.shape[0])
+    lv = levels(max(sigma, 1))
+    B = np.zeros((max(lv, 1), words_per_level(n)), dtype=np.uint64)
+    return int(lib().wto_build(_ptr(S), n, sigma, width or S.dtype.itemsize, _ptr(B), None))
+
+
+def access(t: OracleTree, i: int):
+    """Returns (symbol, bits per level, in-node index per level)."""
+    sym = ctypes.c_uint32()
+    bits = np.zeros(max(t.levels, 1), dtype=np.uint32)
+    idx = np.zeros(max(t.levels, 1), dtype=np.uint64)
+    rc = lib().wto_access(_ptr(t.bitmaps), t.n, t.sigma, i, ctypes.byref(sym), _ptr(bits), _ptr(idx))
+    if rc != OK:
+        raise ValueError("access status %d" % rc)
+    return int(sym.value), bits[: t.levels].tolist(), [int(x) for x in idx[: t.levels]]
+
+
+def rank(t: OracleTree, c: int, i: int) -> int:
+    out = ctypes.c_uint64()
+    rc = lib().wto_rank(_ptr(t.bitmaps), t.n, t.sigma, c, i, ctypes.byref(out))
+    if rc != OK:
+        raise ValueError("rank status %d" % rc)
+    return int(out.value)
+
+
+def select(t: OracleTree, c: int, j: int):
+    """0-based position of the j-th (1-based) c, or None if there is none."""
+    out = ctypes.c_uint64()
+    rc = lib().wto_select(_ptr(t.bitmaps), t.n, t.sigma, c, j, ctypes.byref(out))
+    if rc == ENOTFOUND:
+        return None
+    if rc != OK:
+        raise ValueError("select status %d" % rc)
+    return int(out.value)
+
+
+def decode(t: OracleTree) -> np.ndarray:
+    out = np.zeros(t.n, dtype=np.uint32)
+    rc = lib().wto_decode(_ptr(t.bitmaps), t.n, t.sigma, _ptr(out))
+    if rc != OK:
+        raise ValueError("decode status %d" % rc)
+    return out

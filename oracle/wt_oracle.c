@@ -1,0 +1,285 @@
+/*
+ * Sequential CPU oracle for pointerless (one-bitmap-per-level) wavelet-tree
+ * construction.  TEST INFRASTRUCTURE ONLY: it is used by the tests, by the
+ * smoke check and by the benchmark's CPU-baseline leg, never by the library's
+ * product path.  It shares no code, header or table with the GPU library.
+ *
+ * What it follows (Fuentes-Sepulveda, Elejalde, Ferres, Seco, "Parallel
+ * Construction of Wavelet Trees on Multicore Architectures"):
+ *
+ *  - Section 2.3 (wavelet trees): access / rank / select, the balanced binary
+ *    tree whose node bitmaps mark with 0 the left half and with 1 the right
+ *    half of the node's alphabet range, and the one-pointer-per-level
+ *    representation where navigation is simulated with rank on each level's
+ *    n-bit bitmap.
+ *  - Section 3, Proposition 1: the node of symbol s at level i is s >> (l-i),
+ *    with l = ceil(lg sigma).
+ *  - Section 3.1, Algorithm pwt with every parfor replaced by a sequential
+ *    for (the paper's own sequential version): for each level, count the
+ *    symbols of every node, take the prefix sum of the counts to get the node
+ *    offsets, then sweep S in order writing the level bit of each symbol at
+ *    its node's running offset, and finally build the rank structure.
+ *
+ * Readings taken where the paper is loose (each is listed in the design
+ * notes): symbols are 0-based in [0, sigma); the bit test of the fill step is
+ * "bit (l-1-i) of S[j] is set"; the prefix sum is exclusive (node start
+ * offsets); non-power-of-two alphabets split by bit prefix over l bits;
+ * positions are 0-based; rank(c, i) counts [0, i); select(c, j) takes a
+ * 1-based j and returns a 0-based position.
+ *
+ * Conventions that the paper leaves open and that the library implements
+ * independently (parity of these two is unpinned by the paper):
+ *  - bitmap words are 64-bit, position p lives in word p/64 at bit p%64
+ *    (least significant bit first); each level owns W = round_up(ceil(n/64),
+ *    8) words, and every bit at a position >= n is zero;
+ *  - the rank directory of a level holds K = ceil(n/512) + 1 absolute
+ *    counts R[k] = number of ones in positions [0, min(512k, n)), stored as
+ *    64-bit integers in a slot of round_up(K, 8) entries whose padding
+ *    entries are zero.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define WTO_OK 0
+#define WTO_EINVAL 1
+#define WTO_ERANGE 2
+#define WTO_ENOMEM 3
+#define WTO_ENOTFOUND 4
+
+static uint64_t round_up(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
+
+/* Number of levels: the smallest l with 2^l >= sigma (integer loop, no log2). */
+uint32_t wto_levels(uint32_t sigma)
+{
+    uint32_t l = 0;
+    while ((1ull << l) < (uint64_t)sigma) l++;
+    return l;
+}
+
+uint64_t wto_words_per_level(uint64_t n) { return round_up((n + 63) / 64, 8); }
+uint64_t wto_rank_entries(uint64_t n) { return (n + 511) / 512 + 1; }
+uint64_t wto_rank_stride(uint64_t n) { return round_up(wto_rank_entries(n), 8); }
+
+static uint64_t sym_at(const void *S, uint32_t width, uint64_t j)
+{
+    if (width == 1) return ((const uint8_t *)S)[j];
+    if (width == 2) return ((const uint16_t *)S)[j];
+    return ((const uint32_t *)S)[j];
+}
+
+static int get_bit(const uint64_t *B, uint64_t p) { return (int)((B[p >> 6] >> (p & 63)) & 1u); }
+
+/*
+ * Build every level bitmap (and, when R != NULL, every rank directory).
+ * B holds l * wto_words_per_level(n) words, R holds l * wto_rank_stride(n)
+ * entries.  Returns WTO_ERANGE if some symbol is >= sigma.
+ */
+int wto_build(const void *S, uint64_t n, uint32_t sigma, uint32_t width,
+              uint64_t *B, uint64_t *R)
+{
+    if (sigma == 0 || (width != 1 && width != 2 && width != 4)) return WTO_EINVAL;
+    if (width < 4 && (uint64_t)sigma > (1ull << (8 * width))) return WTO_EINVAL;
+    for (uint64_t j = 0; j < n; j++)
+        if (sym_at(S, width, j) >= sigma) return WTO_ERANGE;
+
+    uint32_t l = wto_levels(sigma);
+    uint64_t W = wto_words_per_level(n);
+    uint64_t K = wto_rank_entries(n), KS = wto_rank_stride(n);
+    uint64_t maxnodes = l ? (1ull << (l - 1)) : 1;
+    uint64_t *C = (uint64_t *)malloc(maxnodes * sizeof(uint64_t));
+    if (!C) return WTO_ENOMEM;
+
+    for (uint32_t i = 0; i < l; i++) {
+        uint64_t nodes = 1ull << i;
+        uint32_t shift = l - i;            /* node of s at level i: s >> (l-i) */
+        uint64_t *Bi = B + (uint64_t)i * W;
+
+        /* count the symbols of every node of level i */
+        memset(C, 0, nodes * sizeof(uint64_t));
+        for (uint64_t j = 0; j < n; j++) C[sym_at(S, width, j) >> shift]++;
+
+        /* exclusive prefix sum: C[v] becomes the offset of node v */
+        uint64_t acc = 0;
+        for (uint64_t v = 0; v < nodes; v++) {
+            uint64_t c = C[v];
+            C[v] = acc;
+            acc += c;
+        }
+
+        /* fill: in input order, write bit (l-1-i) at the node's running offset */
+        memset(Bi, 0, W * sizeof(uint64_t));
+        for (uint64_t j = 0; j < n; j++) {
+            uint64_t s = sym_at(S, width, j);
+            uint64_t v = s >> shift;
+            uint64_t bit = (s >> (shift - 1)) & 1u;
+            uint64_t pos = C[v];
+            if (bit) Bi[pos >> 6] |= 1ull << (pos & 63);
+            C[v]++;
+        }
+
+        /* rank directory: ones before every multiple of 512, and the total */
+        if (R) {
+            uint64_t *Ri = R + (uint64_t)i * KS;
+            memset(Ri, 0, KS * sizeof(uint64_t));
+            uint64_t ones = 0;
+            for (uint64_t p = 0; p < n; p++) {
+                if ((p & 511) == 0) Ri[p >> 9] = ones;
+                ones += (uint64_t)get_bit(Bi, p);
+            }
+            Ri[K - 1] = ones;
+        }
+    }
+    free(C);
+    return WTO_OK;
+}
+
+/* ------------------------------------------------------------ queries ---- */
+/*
+ * Queries walk the levels as Section 2.3 describes for the one-pointer-per-
+ * level representation: the current node is a range [b, e) of the level's
+ * bitmap; its left child occupies, at the next level, the first
+ * zeros(b, e) positions of the same range and its right child the rest.
+ * rank on a bitmap is counted plainly, bit by bit.
+ */
+static uint64_t ones_in(const uint64_t *Bi, uint64_t a, uint64_t b)
+{
+    uint64_t c = 0;
+    for (uint64_t p = a; p < b; p++) c += (uint64_t)get_bit(Bi, p);
+    return c;
+}
+
+/*
+ * access(S, i): returns the symbol; trace_bits[k] receives the bit read at
+ * level k and trace_idx[k] the position inside the node at level k+1 that the
+ * walk moves to (the paper's "i = rank_b(B, i) - 1" values).
+ */
+int wto_access(const uint64_t *B, uint64_t n, uint32_t sigma, uint64_t i,
+               uint32_t *sym, uint32_t *trace_bits, uint64_t *trace_idx)
+{
+    if (i >= n) return WTO_EINVAL;
+    uint32_t l = wto_levels(sigma);
+    uint64_t W = wto_words_per_level(n);
+    uint64_t b = 0, e = n, p = i;      /* node range and absolute position */
+    uint32_t s = 0;
+    for (uint32_t k = 0; k < l; k++) {
+        const uint64_t *Bk = B + (uint64_t)k * W;
+        uint64_t zeros = (e - b) - ones_in(Bk, b, e);
+        int bit = get_bit(Bk, p);
+        uint64_t before_ones = ones_in(Bk, b, p);
+        uint64_t before = bit ? before_ones : (p - b) - before_ones;
+        if (bit) { b = b + zeros; }
+        else     { e = b + zeros; }
+        p = b + before;
+        s = (s << 1) | (uint32_t)bit;
+        if (trace_bits) trace_bits[k] = (uint32_t)bit;
+        if (trace_idx) trace_idx[k] = before;
+    }
+    *sym = s;
+    return WTO_OK;
+}
+
+/* rank(c, i): occurrences of c in S[0, i), i in [0, n]. */
+int wto_rank(const uint64_t *B, uint64_t n, uint32_t sigma, uint32_t c, uint64_t i,
+             uint64_t *out)
+{
+    if (c >= sigma || i > n) return WTO_EINVAL;
+    uint32_t l = wto_levels(sigma);
+    uint64_t W = wto_words_per_level(n);
+    uint64_t b = 0, e = n, cnt = i;    /* cnt: node symbols that precede i */
+    for (uint32_t k = 0; k < l; k++) {
+        const uint64_t *Bk = B + (uint64_t)k * W;
+        uint64_t zeros = (e - b) - ones_in(Bk, b, e);
+        uint64_t ones_before = ones_in(Bk, b, b + cnt);
+        if ((c >> (l - 1 - k)) & 1u) { cnt = ones_before; b = b + zeros; }
+        else                         { cnt = cnt - ones_before; e = b + zeros; }
+    }
+    *out = cnt;
+    return WTO_OK;
+}
+
+/* position of the m-th (1-based) bit equal to `bit` inside [b, e) */
+static int select_in(const uint64_t *Bk, uint64_t b, uint64_t e, int bit, uint64_t m,
+                     uint64_t *pos)
+{
+    uint64_t seen = 0;
+    for (uint64_t p = b; p < e; p++) {
+        if (get_bit(Bk, p) == bit && ++seen == m) { *pos = p; return WTO_OK; }
+    }
+    return WTO_ENOTFOUND;
+}
+
+/* select(c, j): 0-based position of the j-th (1-based) occurrence of c. */
+int wto_select(const uint64_t *B, uint64_t n, uint32_t sigma, uint32_t c, uint64_t j,
+               uint64_t *out)
+{
+    if (c >= sigma) return WTO_EINVAL;
+    uint32_t l = wto_levels(sigma);
+    uint64_t W = wto_words_per_level(n);
+    uint64_t bs[32], es[32];
+    uint64_t b = 0, e = n;
+    for (uint32_t k = 0; k < l; k++) {       /* top-down: node ranges of c */
+        const uint64_t *Bk = B + (uint64_t)k * W;
+        bs[k] = b; es[k] = e;
+        uint64_t zeros = (e - b) - ones_in(Bk, b, e);
+        if ((c >> (l - 1 - k)) & 1u) b = b + zeros; else e = b + zeros;
+    }
+    if (j == 0 || j > e - b) return WTO_ENOTFOUND;
+    uint64_t idx = j - 1;                    /* index inside the leaf */
+    for (uint32_t kk = l; kk-- > 0;) {       /* bottom-up: back to the parent */
+        const uint64_t *Bk = B + (uint64_t)kk * W;
+        int bit = (int)((c >> (l - 1 - kk)) & 1u);
+        uint64_t pos;
+        if (select_in(Bk, bs[kk], es[kk], bit, idx + 1, &pos) != WTO_OK) return WTO_ENOTFOUND;
+        idx = pos - bs[kk];
+    }
+    *out = idx;
+    return WTO_OK;
+}
+
+/*
+ * Forward decode: recover S from the bitmaps alone.  Node boundaries of each
+ * level are derived top-down from the zeros of the parent node; then each
+ * input position j is followed down the tree, taking at every level the next
+ * unread slot of its node (stability makes the j-th symbol of a node sit at
+ * the node start plus the number of earlier symbols of that node).
+ */
+int wto_decode(const uint64_t *B, uint64_t n, uint32_t sigma, uint32_t *out)
+{
+    uint32_t l = wto_levels(sigma);
+    uint64_t W = wto_words_per_level(n);
+    if (l == 0) { for (uint64_t j = 0; j < n; j++) out[j] = 0; return WTO_OK; }
+    /* start[k] has 2^k + 1 entries; cnt[k] has 2^k entries */
+    uint64_t total = (2ull << l);
+    uint64_t *start = (uint64_t *)calloc(total + l + 1, sizeof(uint64_t));
+    uint64_t *cnt = (uint64_t *)calloc(total, sizeof(uint64_t));
+    if (!start || !cnt) { free(start); free(cnt); return WTO_ENOMEM; }
+    uint64_t off[33];
+    uint64_t o = 0;
+    for (uint32_t k = 0; k <= l; k++) { off[k] = o; o += (1ull << k) + 1; }
+    start[off[0]] = 0; start[off[0] + 1] = n;
+    for (uint32_t k = 0; k < l; k++) {
+        const uint64_t *Bk = B + (uint64_t)k * W;
+        uint64_t nodes = 1ull << k;
+        for (uint64_t v = 0; v < nodes; v++) {
+            uint64_t b = start[off[k] + v], e = start[off[k] + v + 1];
+            uint64_t zeros = (e - b) - ones_in(Bk, b, e);
+            start[off[k + 1] + 2 * v] = b;
+            start[off[k + 1] + 2 * v + 1] = b + zeros;
+        }
+        start[off[k + 1] + 2 * nodes] = n;
+    }
+    uint64_t coff = 0, cof[33];
+    for (uint32_t k = 0; k < l; k++) { cof[k] = coff; coff += 1ull << k; }
+    for (uint64_t j = 0; j < n; j++) {
+        uint64_t v = 0;
+        for (uint32_t k = 0; k < l; k++) {
+            uint64_t pos = start[off[k] + v] + cnt[cof[k] + v]++;
+            v = 2 * v + (uint64_t)get_bit(B + (uint64_t)k * W, pos);
+        }
+        out[j] = (uint32_t)v;
+    }
+    free(start);
+    free(cnt);
+    return WTO_OK;
+}
