@@ -1,0 +1,164 @@
+/*
+ * wtree.h -- C ABI of the MI355X wavelet-tree construction library.
+ *
+ * Problem (Fuentes-Sepulveda et al., "Parallel Construction of Wavelet Trees
+ * on Multicore Architectures", Section 2.4 problem statement, Section 2.3
+ * definitions): given a sequence S of n symbols over the alphabet [0, sigma),
+ * build the pointerless wavelet tree -- one n-bit bitmap per level, l =
+ * ceil(lg sigma) levels -- in which level i lists, node after node in prefix
+ * order, bit (l-1-i) of every symbol, the symbols of a node (those sharing
+ * their top i bits, Proposition 1) keeping their input order.  Each level also
+ * gets a rank directory.  The construction runs on the GPU; queries are
+ * provided for verification and serving.
+ *
+ * Conventions (the paper does not fix them):
+ *  - symbols are 0-based, stored as unsigned 8-, 16- or 32-bit integers
+ *    (width 1, 2 or 4 bytes); 1 <= sigma <= min(2^(8*width), 2^24);
+ *  - non-power-of-two alphabets split by bit prefix over l bits (nodes whose
+ *    codes are >= sigma are simply empty);
+ *  - positions are 0-based; rank(c, i) counts occurrences in [0, i) for
+ *    i in [0, n]; select(c, j) takes a 1-based j and returns a 0-based
+ *    position;
+ *  - bitmap words are 64-bit, position p of a level sits in word p/64 at bit
+ *    p%64 (least significant bit first); each level owns
+ *    W = round_up(ceil(n/64), 8) words and every bit at a position >= n is 0;
+ *  - the rank directory of a level holds K = ceil(n/512) + 1 absolute 64-bit
+ *    counts R[k] = ones in positions [0, min(512k, n)) in a slot of
+ *    round_up(K, 8) entries whose padding entries are 0.
+ *
+ * Memory and ownership:
+ *  - every pointer named d_* is device memory of the current HIP device;
+ *  - the caller owns the input, the tree memory and the workspace, sized by
+ *    wt_footprint / wt_batch_footprint; the library owns only the small host
+ *    handle (wt_tree) returned by a build and released by wt_free;
+ *  - all work is enqueued on the given stream (a hipStream_t passed as
+ *    void*, NULL = the null stream) and is asynchronous: the input must stay
+ *    valid and unmodified until the stream has passed the build, and the
+ *    tree is complete once the stream has passed it;
+ *  - the workspace may be reused for another build once the stream has
+ *    passed the previous one; tree memory holds the finished tree;
+ *  - the input must be 16-byte aligned (any torch allocation is).
+ *
+ * Errors: every int-returning function returns a status below; no exception
+ * or abort crosses the ABI.  A symbol >= sigma is found on the device, after
+ * the call has returned: wt_tree_status reports it (WT_ERANGE) once the
+ * stream has passed the build; the bitmaps of such a build are unspecified.
+ */
+#ifndef WTREE_H
+#define WTREE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    WT_OK = 0,
+    WT_EINVAL = 1,     /* bad argument (null pointer, width, sigma, size, alignment) */
+    WT_ERANGE = 2,     /* some symbol is >= sigma */
+    WT_ENOMEM = 3,     /* tree or workspace smaller than the footprint */
+    WT_ENOTFOUND = 4,  /* select beyond the number of occurrences */
+    WT_EDEVICE = 5     /* a HIP runtime call failed */
+};
+
+#define WT_MAX_SIGMA (1u << 24)
+#define WT_MAX_N (1ull << 40)
+
+typedef struct wt_tree wt_tree; /* opaque host handle */
+
+typedef struct wt_desc {
+    uint64_t n;     /* number of symbols, 0 <= n < WT_MAX_N */
+    uint32_t sigma; /* alphabet size, 1 <= sigma <= WT_MAX_SIGMA */
+    uint32_t width; /* bytes per stored symbol: 1, 2 or 4 */
+} wt_desc;
+
+/*
+ * Bytes of tree memory and of workspace that wt_build needs for *desc.
+ * Pure host computation (no device call).
+ */
+int wt_footprint(const wt_desc *desc, uint64_t *tree_bytes, uint64_t *work_bytes);
+
+/*
+ * Build the wavelet tree of d_S (desc->n symbols of desc->width bytes) into
+ * d_tree (tree_bytes >= the footprint), using d_work (work_bytes >= the
+ * footprint) as scratch, on `stream`.  On WT_OK *out receives a new handle
+ * describing the tree (release it with wt_free); on error *out is NULL and
+ * nothing was enqueued.  Follows the per-level construction of Section 3.1
+ * (count, prefix sum, stable fill per level; Algorithm pwt) and the
+ * segment-count / offset-scan idea of Section 3.2 (Algorithm dd), organised
+ * for the GPU as described in the library's design notes.
+ */
+int wt_build(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t tree_bytes,
+             void *d_work, uint64_t work_bytes, void *stream, wt_tree **out);
+
+/*
+ * Workspace bytes that wt_build_batch needs for the m sequences descs[0..m).
+ * Tree memory of sequence q is its own wt_footprint tree_bytes.
+ */
+int wt_batch_footprint(uint32_t m, const wt_desc *descs, uint64_t *work_bytes);
+
+/*
+ * Build m independent trees in one batched launch sequence on `stream`.
+ * d_S[q], descs[q], d_trees[q] (of tree_bytes[q] bytes) describe sequence q;
+ * sequences may mix lengths, alphabets and widths.  out[q] receives the
+ * handle of tree q (each released with wt_free).  On error no handle is
+ * returned and nothing was enqueued.
+ */
+int wt_build_batch(uint32_t m, const void *const *d_S, const wt_desc *descs,
+                   void *const *d_trees, const uint64_t *tree_bytes, void *d_work,
+                   uint64_t work_bytes, void *stream, wt_tree **out);
+
+/*
+ * Waits for the stream of the build, then returns WT_OK, WT_ERANGE (some
+ * symbol >= sigma) or WT_EDEVICE.
+ */
+int wt_tree_status(const wt_tree *tree);
+
+/* Release the host handle (the caller's tree memory is untouched). */
+void wt_free(wt_tree *tree);
+
+/*
+ * Layout of a built tree: number of levels, device pointer to level 0's
+ * bitmap (level i starts words_per_level * i words later) and to level 0's
+ * rank directory (level i starts rank_stride * i entries later), and the
+ * number of meaningful rank entries per level (K = ceil(n/512) + 1).
+ */
+int wt_levels(const wt_tree *tree, uint32_t *levels, const uint64_t **d_bitmaps,
+              uint64_t *words_per_level, const uint64_t **d_ranks, uint64_t *rank_stride,
+              uint64_t *rank_entries);
+
+/*
+ * Batched queries (Section 2.3 access / rank / select, evaluated by walking
+ * the levels with rank and select on the bitmaps).  m queries, device
+ * arrays, enqueued on `stream` after whatever the stream already holds.
+ *  - access: d_sym[k] = S[d_i[k]];            d_i[k] >= n gives 0xFFFFFFFF
+ *  - rank:   d_r[k] = occurrences of d_c[k] in S[0, d_i[k]);  d_i[k] > n or
+ *            d_c[k] >= sigma gives UINT64_MAX
+ *  - select: d_pos[k] = 0-based position of the d_j[k]-th (1-based)
+ *            occurrence of d_c[k]; UINT64_MAX if there is none
+ */
+int wt_access_batch(const wt_tree *tree, const uint64_t *d_i, uint32_t *d_sym, uint64_t m,
+                    void *stream);
+int wt_rank_batch(const wt_tree *tree, const uint32_t *d_c, const uint64_t *d_i,
+                  uint64_t *d_r, uint64_t m, void *stream);
+int wt_select_batch(const wt_tree *tree, const uint32_t *d_c, const uint64_t *d_j,
+                    uint64_t *d_pos, uint64_t m, void *stream);
+
+/*
+ * Single queries for verification: they run the batched kernels on the
+ * build's stream and wait for the answer.  WT_EINVAL for i out of range or
+ * c >= sigma, WT_ENOTFOUND for a select with no such occurrence.
+ */
+int wt_access(const wt_tree *tree, uint64_t i, uint32_t *sym);
+int wt_rank(const wt_tree *tree, uint32_t c, uint64_t i, uint64_t *r);
+int wt_select(const wt_tree *tree, uint32_t c, uint64_t j, uint64_t *pos);
+
+/* Static text for a status code. */
+const char *wt_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WTREE_H */

@@ -1,0 +1,373 @@
+// Host runtime behind include/wtree.h: layouts, argument checks, launch
+// sequences, handles and query wrappers.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "wt_internal.h"
+#include "wtree.h"
+
+struct wt_tree {
+    wt::Layout L;
+    uint8_t *tree;         // caller's tree memory
+    hipStream_t stream;    // stream the build was enqueued on
+    int device;
+    uint64_t *d_query;     // lazily allocated scratch for the single queries
+};
+
+namespace wt {
+
+void make_layout(uint64_t n, uint32_t sigma, uint32_t width, Layout *L) {
+    memset(L, 0, sizeof(*L));
+    const uint32_t l = levels_for(sigma);
+    const uint32_t h = l < kTopBits ? l : kTopBits;
+    L->n = n;
+    L->sigma = sigma;
+    L->width = width;
+    L->levels = l;
+    L->top_bits = h;
+    L->words = round_up(ceil_div(n, 64), 8);
+    L->rank_entries = ceil_div(n, 512) + 1;
+    L->rank_stride = round_up(L->rank_entries, 8);
+    L->ntiles = ceil_div(n, kTile);
+
+    L->tree_bits_off = kHeaderBytes;
+    L->tree_ranks_off = L->tree_bits_off + (uint64_t)l * L->words * 8;
+    L->tree_bytes = L->tree_ranks_off + (uint64_t)l * L->rank_stride * 8;
+
+    uint64_t off = 0;
+    const uint64_t tbytes = round_up(n * width, 256);
+    L->ws_ta = off;
+    if (l >= 2) off += tbytes;
+    L->ws_tb = off;
+    if (l >= 3) off += tbytes;
+
+    L->ws_ctrl = off;
+    L->ws_tickets = off;
+    off += round_up((uint64_t)(l ? l : 1) * 4, 256);
+    L->ws_status = off;
+    off += round_up((uint64_t)l * L->ntiles * 8, 256);
+    L->ws_hist = off;
+    off += round_up((1ull << h) * 8, 256);
+    L->ws_ones = off;
+    uint64_t e = 0;
+    for (uint32_t i = h; i < l; i++) { L->ones_off[i] = e; e += 1ull << i; }
+    off += round_up(e * 8, 256);
+    L->ws_ctrl_bytes = off - L->ws_ctrl;
+
+    L->ws_zo = off;
+    e = 0;
+    for (uint32_t i = 0; i < l; i++) { L->zo_off[i] = e; e += 1ull << i; }
+    off += round_up(e * 16, 256);
+    L->ws_start = off;
+    e = 0;
+    for (uint32_t i = h; i < l; i++) { L->start_off[i] = e; e += (1ull << i) + 1; }
+    off += round_up(e * 8, 256);
+    L->ws_partials = off;
+    off += round_up(kMaxScanBlocks * 8, 256);
+    L->work_bytes = off;
+}
+
+// Enqueue every kernel of one build.  Arguments are already validated.
+static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, uint8_t *work,
+                                hipStream_t st) {
+    const uint32_t l = L.levels, h = L.top_bits;
+    uint32_t *tree_status = reinterpret_cast<uint32_t *>(tree);
+    uint64_t *bits = reinterpret_cast<uint64_t *>(tree + L.tree_bits_off);
+    uint64_t *ranks = reinterpret_cast<uint64_t *>(tree + L.tree_ranks_off);
+    uint32_t *tickets = reinterpret_cast<uint32_t *>(work + L.ws_tickets);
+    uint64_t *status = reinterpret_cast<uint64_t *>(work + L.ws_status);
+    unsigned long long *hist = reinterpret_cast<unsigned long long *>(work + L.ws_hist);
+    unsigned long long *ones = reinterpret_cast<unsigned long long *>(work + L.ws_ones);
+    ulonglong2 *zo = reinterpret_cast<ulonglong2 *>(work + L.ws_zo);
+    uint64_t *start = reinterpret_cast<uint64_t *>(work + L.ws_start);
+    uint64_t *partials = reinterpret_cast<uint64_t *>(work + L.ws_partials);
+
+    hipError_t err = launch_zero(work + L.ws_ctrl, L.ws_ctrl_bytes, tree_status, L.n == 0 ? ranks : nullptr,
+                                 (uint64_t)l * L.rank_stride, st);
+    if (err != hipSuccess || L.n == 0) return err;
+
+    HistArgs ha;
+    ha.S = S;
+    ha.hist = hist;
+    ha.tree_status = tree_status;
+    ha.n = L.n;
+    ha.sigma = L.sigma;
+    ha.symmask = l ? (uint32_t)((1ull << l) - 1) : 0u;
+    ha.hshift = l - h;
+    ha.nbins = 1u << h;
+    if ((err = launch_hist(ha, L.width, L.ntiles, st)) != hipSuccess) return err;
+    if (l == 0) return hipSuccess;
+
+    TopArgs ta;
+    ta.hist = hist;
+    ta.zo = zo;
+    ta.start_h = h < l ? start + L.start_off[h] : nullptr;
+    ta.n = L.n;
+    ta.h = h;
+    ta.levels = l;
+    for (uint32_t i = 0; i < 32; i++) ta.zo_off[i] = L.zo_off[i];
+    if ((err = launch_top(ta, st)) != hipSuccess) return err;
+
+    uint8_t *tbuf[2] = {work + L.ws_ta, work + L.ws_tb};
+    for (uint32_t i = 0; i < l; i++) {
+        if (i >= h) {
+            PlanArgs pa;
+            pa.start = start + L.start_off[i];
+            pa.ones = ones + L.ones_off[i];
+            pa.zo = zo + L.zo_off[i];
+            pa.start_next = (i + 1 < l) ? start + L.start_off[i + 1] : nullptr;
+            pa.partials = partials;
+            pa.nodes = 1ull << i;
+            pa.n = L.n;
+            if ((err = launch_plan(pa, st)) != hipSuccess) return err;
+        }
+        LevelArgs a;
+        a.tin = (i == 0) ? S : tbuf[(i - 1) & 1];  // T_i for i >= 1 alternates ta, tb
+        a.tout = (i + 1 < l) ? tbuf[i & 1] : nullptr;
+        a.bits = bits + (uint64_t)i * L.words;
+        a.ranks = ranks + (uint64_t)i * L.rank_stride;
+        a.zo = zo + L.zo_off[i];
+        a.ones_next = (i + 1 >= h && i + 1 < l) ? ones + L.ones_off[i + 1] : nullptr;
+        a.status = status + (uint64_t)i * L.ntiles;
+        a.ticket = tickets + i;
+        a.n = L.n;
+        a.words = L.words;
+        a.rank_entries = L.rank_entries;
+        a.rank_stride = L.rank_stride;
+        a.ntiles = L.ntiles;
+        a.levels = l;
+        a.level = i;
+        a.symmask = (uint32_t)((1ull << l) - 1);
+        if ((err = launch_level(a, L.width, st)) != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
+static int check_desc(const wt_desc *d) {
+    if (!d) return WT_EINVAL;
+    if (d->width != 1 && d->width != 2 && d->width != 4) return WT_EINVAL;
+    if (d->sigma == 0 || d->sigma > WT_MAX_SIGMA) return WT_EINVAL;
+    if (d->width < 4 && (uint64_t)d->sigma > (1ull << (8 * d->width))) return WT_EINVAL;
+    if (d->n >= WT_MAX_N) return WT_EINVAL;
+    return WT_OK;
+}
+
+static TreeView view_of(const wt_tree *t) {
+    TreeView v;
+    v.bits = reinterpret_cast<const uint64_t *>(t->tree + t->L.tree_bits_off);
+    v.ranks = reinterpret_cast<const uint64_t *>(t->tree + t->L.tree_ranks_off);
+    v.n = t->L.n;
+    v.words = t->L.words;
+    v.rank_entries = t->L.rank_entries;
+    v.rank_stride = t->L.rank_stride;
+    v.sigma = t->L.sigma;
+    v.levels = t->L.levels;
+    return v;
+}
+
+static wt_tree *new_handle(const Layout &L, void *tree, hipStream_t st) {
+    wt_tree *h = new (std::nothrow) wt_tree;
+    if (!h) return nullptr;
+    h->L = L;
+    h->tree = reinterpret_cast<uint8_t *>(tree);
+    h->stream = st;
+    h->device = 0;
+    (void)hipGetDevice(&h->device);
+    h->d_query = nullptr;
+    return h;
+}
+
+}  // namespace wt
+
+using namespace wt;
+
+extern "C" {
+
+int wt_footprint(const wt_desc *desc, uint64_t *tree_bytes, uint64_t *work_bytes) {
+    int rc = check_desc(desc);
+    if (rc != WT_OK) return rc;
+    Layout L;
+    make_layout(desc->n, desc->sigma, desc->width, &L);
+    if (tree_bytes) *tree_bytes = L.tree_bytes;
+    if (work_bytes) *work_bytes = L.work_bytes;
+    return WT_OK;
+}
+
+int wt_build(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t tree_bytes, void *d_work,
+             uint64_t work_bytes, void *stream, wt_tree **out) {
+    if (out) *out = nullptr;
+    int rc = check_desc(desc);
+    if (rc != WT_OK) return rc;
+    if (!out || !d_tree || !d_work || (desc->n > 0 && !d_S)) return WT_EINVAL;
+    if (((uintptr_t)d_S & 15) || ((uintptr_t)d_tree & 255) || ((uintptr_t)d_work & 255)) return WT_EINVAL;
+    Layout L;
+    make_layout(desc->n, desc->sigma, desc->width, &L);
+    if (tree_bytes < L.tree_bytes || work_bytes < L.work_bytes) return WT_ENOMEM;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    wt_tree *h = new_handle(L, d_tree, st);
+    if (!h) return WT_ENOMEM;
+    if (enqueue_build(d_S, L, reinterpret_cast<uint8_t *>(d_tree), reinterpret_cast<uint8_t *>(d_work), st) !=
+        hipSuccess) {
+        delete h;
+        return WT_EDEVICE;
+    }
+    *out = h;
+    return WT_OK;
+}
+
+int wt_batch_footprint(uint32_t m, const wt_desc *descs, uint64_t *work_bytes) {
+    if (m > 0 && !descs) return WT_EINVAL;
+    uint64_t total = 0;
+    for (uint32_t q = 0; q < m; q++) {
+        int rc = check_desc(&descs[q]);
+        if (rc != WT_OK) return rc;
+        Layout L;
+        make_layout(descs[q].n, descs[q].sigma, descs[q].width, &L);
+        total += round_up(L.work_bytes, 256);
+    }
+    if (work_bytes) *work_bytes = total ? total : 256;
+    return WT_OK;
+}
+
+int wt_build_batch(uint32_t m, const void *const *d_S, const wt_desc *descs, void *const *d_trees,
+                   const uint64_t *tree_bytes, void *d_work, uint64_t work_bytes, void *stream, wt_tree **out) {
+    if (!out || (m > 0 && (!d_S || !descs || !d_trees || !tree_bytes || !d_work))) return WT_EINVAL;
+    for (uint32_t q = 0; q < m; q++) out[q] = nullptr;
+    uint64_t need = 0;
+    int rc = wt_batch_footprint(m, descs, &need);
+    if (rc != WT_OK) return rc;
+    if (m > 0 && work_bytes < need) return WT_ENOMEM;
+    if ((uintptr_t)d_work & 255) return WT_EINVAL;
+    for (uint32_t q = 0; q < m; q++) {
+        if (!d_trees[q] || (descs[q].n > 0 && !d_S[q])) return WT_EINVAL;
+        if (((uintptr_t)d_S[q] & 15) || ((uintptr_t)d_trees[q] & 255)) return WT_EINVAL;
+        Layout L;
+        make_layout(descs[q].n, descs[q].sigma, descs[q].width, &L);
+        if (tree_bytes[q] < L.tree_bytes) return WT_ENOMEM;
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    uint8_t *work = reinterpret_cast<uint8_t *>(d_work);
+    uint64_t off = 0;
+    for (uint32_t q = 0; q < m; q++) {
+        Layout L;
+        make_layout(descs[q].n, descs[q].sigma, descs[q].width, &L);
+        wt_tree *h = new_handle(L, d_trees[q], st);
+        if (!h || enqueue_build(d_S[q], L, reinterpret_cast<uint8_t *>(d_trees[q]), work + off, st) != hipSuccess) {
+            delete h;
+            for (uint32_t r = 0; r < q; r++) { delete out[r]; out[r] = nullptr; }
+            return h ? WT_EDEVICE : WT_ENOMEM;
+        }
+        out[q] = h;
+        off += round_up(L.work_bytes, 256);
+    }
+    return WT_OK;
+}
+
+int wt_tree_status(const wt_tree *t) {
+    if (!t) return WT_EINVAL;
+    if (hipStreamSynchronize(t->stream) != hipSuccess) return WT_EDEVICE;
+    uint32_t flag = 0;
+    if (hipMemcpy(&flag, t->tree, sizeof(flag), hipMemcpyDeviceToHost) != hipSuccess) return WT_EDEVICE;
+    return (flag & 1u) ? WT_ERANGE : WT_OK;
+}
+
+void wt_free(wt_tree *t) {
+    if (!t) return;
+    if (t->d_query) (void)hipFree(t->d_query);
+    delete t;
+}
+
+int wt_levels(const wt_tree *t, uint32_t *levels, const uint64_t **d_bitmaps, uint64_t *words_per_level,
+              const uint64_t **d_ranks, uint64_t *rank_stride, uint64_t *rank_entries) {
+    if (!t) return WT_EINVAL;
+    if (levels) *levels = t->L.levels;
+    if (d_bitmaps) *d_bitmaps = reinterpret_cast<const uint64_t *>(t->tree + t->L.tree_bits_off);
+    if (words_per_level) *words_per_level = t->L.words;
+    if (d_ranks) *d_ranks = reinterpret_cast<const uint64_t *>(t->tree + t->L.tree_ranks_off);
+    if (rank_stride) *rank_stride = t->L.rank_stride;
+    if (rank_entries) *rank_entries = t->L.rank_entries;
+    return WT_OK;
+}
+
+int wt_access_batch(const wt_tree *t, const uint64_t *d_i, uint32_t *d_sym, uint64_t m, void *stream) {
+    if (!t || (m > 0 && (!d_i || !d_sym))) return WT_EINVAL;
+    return launch_access(view_of(t), d_i, d_sym, m, reinterpret_cast<hipStream_t>(stream)) == hipSuccess
+               ? WT_OK : WT_EDEVICE;
+}
+
+int wt_rank_batch(const wt_tree *t, const uint32_t *d_c, const uint64_t *d_i, uint64_t *d_r, uint64_t m,
+                  void *stream) {
+    if (!t || (m > 0 && (!d_c || !d_i || !d_r))) return WT_EINVAL;
+    return launch_rank(view_of(t), d_c, d_i, d_r, m, reinterpret_cast<hipStream_t>(stream)) == hipSuccess
+               ? WT_OK : WT_EDEVICE;
+}
+
+int wt_select_batch(const wt_tree *t, const uint32_t *d_c, const uint64_t *d_j, uint64_t *d_pos, uint64_t m,
+                    void *stream) {
+    if (!t || (m > 0 && (!d_c || !d_j || !d_pos))) return WT_EINVAL;
+    return launch_select(view_of(t), d_c, d_j, d_pos, m, reinterpret_cast<hipStream_t>(stream)) == hipSuccess
+               ? WT_OK : WT_EDEVICE;
+}
+
+// Single queries: argument 0 of the scratch holds the query, 2 the answer.
+static int single_query(const wt_tree *t, int kind, uint32_t c, uint64_t x, uint64_t *ans) {
+    wt_tree *h = const_cast<wt_tree *>(t);
+    if (!h->d_query && hipMalloc(reinterpret_cast<void **>(&h->d_query), 64) != hipSuccess) {
+        h->d_query = nullptr;
+        return WT_EDEVICE;
+    }
+    uint64_t host[4] = {x, (uint64_t)c, 0, 0};
+    if (hipMemcpyAsync(h->d_query, host, 32, hipMemcpyHostToDevice, h->stream) != hipSuccess) return WT_EDEVICE;
+    const TreeView v = view_of(t);
+    hipError_t err;
+    uint32_t *cptr = reinterpret_cast<uint32_t *>(h->d_query + 1);
+    if (kind == 0) err = launch_access(v, h->d_query, reinterpret_cast<uint32_t *>(h->d_query + 2), 1, h->stream);
+    else if (kind == 1) err = launch_rank(v, cptr, h->d_query, h->d_query + 2, 1, h->stream);
+    else err = launch_select(v, cptr, h->d_query, h->d_query + 2, 1, h->stream);
+    if (err != hipSuccess) return WT_EDEVICE;
+    if (hipMemcpyAsync(host, h->d_query, 32, hipMemcpyDeviceToHost, h->stream) != hipSuccess) return WT_EDEVICE;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return WT_EDEVICE;
+    *ans = kind == 0 ? (uint64_t)(uint32_t)host[2] : host[2];
+    return WT_OK;
+}
+
+int wt_access(const wt_tree *t, uint64_t i, uint32_t *sym) {
+    if (!t || !sym || i >= t->L.n) return WT_EINVAL;
+    uint64_t a = 0;
+    int rc = single_query(t, 0, 0, i, &a);
+    if (rc == WT_OK) *sym = (uint32_t)a;
+    return rc;
+}
+
+int wt_rank(const wt_tree *t, uint32_t c, uint64_t i, uint64_t *r) {
+    if (!t || !r || c >= t->L.sigma || i > t->L.n) return WT_EINVAL;
+    return single_query(t, 1, c, i, r);
+}
+
+int wt_select(const wt_tree *t, uint32_t c, uint64_t j, uint64_t *pos) {
+    if (!t || !pos || c >= t->L.sigma) return WT_EINVAL;
+    uint64_t a = 0;
+    int rc = single_query(t, 2, c, j, &a);
+    if (rc != WT_OK) return rc;
+    if (a == ~0ull) return WT_ENOTFOUND;
+    *pos = a;
+    return WT_OK;
+}
+
+const char *wt_strerror(int s) {
+    switch (s) {
+        case WT_OK: return "success";
+        case WT_EINVAL: return "invalid argument";
+        case WT_ERANGE: return "symbol out of range (>= sigma)";
+        case WT_ENOMEM: return "tree or workspace smaller than the footprint";
+        case WT_ENOTFOUND: return "no such occurrence";
+        case WT_EDEVICE: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

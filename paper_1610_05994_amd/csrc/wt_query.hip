@@ -1,0 +1,176 @@
+// Batched access / rank / select on a built pointerless wavelet tree.
+//
+// Section 2.3: queries walk the tree top-down; with one bitmap per level the
+// current node is a range [b, e) of the level, its left child is the first
+// zeros(b, e) positions of the same range at the next level and its right
+// child the rest, so every step needs rank on the level bitmap.  rank uses
+// the level's directory of absolute counts at multiples of 512 positions
+// plus popcounts of at most eight words; select binary-searches the
+// directory, then scans words.  One thread answers one query.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wt_internal.h"
+
+namespace wt {
+
+namespace {
+
+struct Level {
+    const uint64_t *B, *R;
+};
+
+__device__ __forceinline__ Level level_of(const TreeView &t, uint32_t k) {
+    return Level{t.bits + (uint64_t)k * t.words, t.ranks + (uint64_t)k * t.rank_stride};
+}
+
+// ones in positions [0, p), 0 <= p <= n
+__device__ __forceinline__ uint64_t rank1(const Level &L, uint64_t p) {
+    const uint64_t k = p >> 9;
+    uint64_t r = L.R[k];
+    const uint64_t w1 = p >> 6;
+    for (uint64_t w = k * 8; w < w1; w++) r += __popcll(L.B[w]);
+    if (p & 63) r += __popcll(L.B[w1] & ((1ull << (p & 63)) - 1ull));
+    return r;
+}
+
+__device__ __forceinline__ uint32_t select_in_word(uint64_t x, uint32_t r) {
+    for (uint32_t q = 0; q < r; q++) x &= x - 1;  // drop the r lowest set bits
+    return (uint32_t)__builtin_ctzll(x);
+}
+
+// position of the m-th (1-based) one; requires 1 <= m <= ones of the level
+__device__ uint64_t select1(const Level &L, uint64_t K, uint64_t nw, uint64_t m) {
+    uint64_t lo = 0, hi = K - 1;
+    while (lo < hi) {  // largest k with R[k] < m (R[0] = 0 < m)
+        const uint64_t mid = (lo + hi + 1) / 2;
+        if (L.R[mid] < m) lo = mid; else hi = mid - 1;
+    }
+    uint64_t r = L.R[lo], w = lo * 8;
+    while (w < nw) {  // nw = words holding positions < n
+        const uint64_t pc = __popcll(L.B[w]);
+        if (r + pc >= m) break;
+        r += pc;
+        w++;
+    }
+    if (w >= nw) return ~0ull;  // only for a corrupted directory
+    return w * 64 + select_in_word(L.B[w], (uint32_t)(m - r - 1));
+}
+
+// position of the m-th (1-based) zero; requires 1 <= m <= zeros in [0, n)
+__device__ uint64_t select0(const Level &L, uint64_t K, uint64_t n, uint64_t m) {
+    const uint64_t nw = (n + 63) / 64;
+    uint64_t lo = 0, hi = K - 1;
+    while (lo < hi) {  // largest k with zeros before min(512k, n) < m
+        const uint64_t mid = (lo + hi + 1) / 2;
+        const uint64_t p = mid * 512 < n ? mid * 512 : n;
+        if (p - L.R[mid] < m) lo = mid; else hi = mid - 1;
+    }
+    uint64_t r = lo * 512 - L.R[lo], w = lo * 8;
+    while (w < nw) {
+        const uint64_t pc = __popcll(~L.B[w]);
+        if (r + pc >= m) break;
+        r += pc;
+        w++;
+    }
+    if (w >= nw) return ~0ull;
+    return w * 64 + select_in_word(~L.B[w], (uint32_t)(m - r - 1));
+}
+
+__global__ void k_access(TreeView t, const uint64_t *qi, uint32_t *out, uint64_t m) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const uint64_t i = qi[q];
+    if (i >= t.n) { out[q] = 0xFFFFFFFFu; return; }
+    uint64_t b = 0, e = t.n, p = i;
+    uint32_t s = 0;
+    for (uint32_t k = 0; k < t.levels; k++) {
+        const Level L = level_of(t, k);
+        const uint64_t rb = rank1(L, b), re = rank1(L, e), rp = rank1(L, p);
+        const uint64_t zeros = (e - b) - (re - rb);
+        const uint32_t bit = (uint32_t)((L.B[p >> 6] >> (p & 63)) & 1ull);
+        uint64_t before;
+        if (bit) { before = rp - rb; b = b + zeros; }
+        else     { before = (p - b) - (rp - rb); e = b + zeros; }
+        p = b + before;
+        s = (s << 1) | bit;
+        if (p >= e || e > t.n) { out[q] = 0xFFFFFFFEu; return; }  // corrupted tree only
+    }
+    out[q] = s;
+}
+
+__global__ void k_rank(TreeView t, const uint32_t *qc, const uint64_t *qi, uint64_t *out, uint64_t m) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const uint32_t c = qc[q];
+    const uint64_t i = qi[q];
+    if (c >= t.sigma || i > t.n) { out[q] = ~0ull; return; }
+    uint64_t b = 0, e = t.n, cnt = i;
+    for (uint32_t k = 0; k < t.levels; k++) {
+        const Level L = level_of(t, k);
+        const uint64_t rb = rank1(L, b), re = rank1(L, e);
+        const uint64_t zeros = (e - b) - (re - rb);
+        const uint64_t ones_before = rank1(L, b + cnt) - rb;
+        if ((c >> (t.levels - 1 - k)) & 1u) { cnt = ones_before; b = b + zeros; }
+        else                                 { cnt = cnt - ones_before; e = b + zeros; }
+        if (b + cnt > e || e > t.n) { out[q] = ~1ull; return; }  // corrupted tree only
+    }
+    out[q] = cnt;
+}
+
+__global__ void k_select(TreeView t, const uint32_t *qc, const uint64_t *qj, uint64_t *out, uint64_t m) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const uint32_t c = qc[q];
+    const uint64_t j = qj[q];
+    if (c >= t.sigma) { out[q] = ~0ull; return; }
+    uint64_t bs[32];
+    uint64_t b = 0, e = t.n;
+    for (uint32_t k = 0; k < t.levels; k++) {  // node ranges of c, top-down
+        const Level L = level_of(t, k);
+        bs[k] = b;
+        const uint64_t rb = rank1(L, b), re = rank1(L, e);
+        const uint64_t zeros = (e - b) - (re - rb);
+        if ((c >> (t.levels - 1 - k)) & 1u) b = b + zeros; else e = b + zeros;
+        if (b > e || e > t.n) { out[q] = ~1ull; return; }  // corrupted tree only
+    }
+    if (j == 0 || j > e - b) { out[q] = ~0ull; return; }
+    uint64_t idx = j - 1;
+    for (uint32_t k = t.levels; k-- > 0;) {  // bottom-up back to S
+        const Level L = level_of(t, k);
+        const uint64_t bb = bs[k];
+        const uint64_t rb = rank1(L, bb);
+        uint64_t pos;
+        if ((c >> (t.levels - 1 - k)) & 1u) pos = select1(L, t.rank_entries, (t.n + 63) / 64, rb + idx + 1);
+        else pos = select0(L, t.rank_entries, t.n, (bb - rb) + idx + 1);
+        if (pos >= t.n) { out[q] = ~0ull; return; }
+        idx = pos - bb;
+    }
+    out[q] = idx;
+}
+
+inline uint32_t blocks_for(uint64_t m) { return (uint32_t)((m + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_access(const TreeView &t, const uint64_t *i, uint32_t *sym, uint64_t m, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_access, dim3(blocks_for(m)), dim3(256), 0, s, t, i, sym, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank(const TreeView &t, const uint32_t *c, const uint64_t *i, uint64_t *r, uint64_t m,
+                       hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rank, dim3(blocks_for(m)), dim3(256), 0, s, t, c, i, r, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const TreeView &t, const uint32_t *c, const uint64_t *j, uint64_t *pos, uint64_t m,
+                         hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_select, dim3(blocks_for(m)), dim3(256), 0, s, t, c, j, pos, m);
+    return hipGetLastError();
+}
+
+}  // namespace wt

@@ -1,0 +1,335 @@
+"""ctypes binding of libwtree.so (include/wtree.h).
+
+The functions ``wt_*`` below carry the same names and arguments as the C
+ABI and only marshal arguments; every step of a build or query runs in the
+HIP kernels of the library.  ``Tree``/``build`` add torch-allocated device
+memory and streams on top (PyTorch is used for memory and streams only).
+
+Loading fails loudly if the library has not been built: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libwtree.so")
+
+WT_OK, WT_EINVAL, WT_ERANGE, WT_ENOMEM, WT_ENOTFOUND, WT_EDEVICE = range(6)
+WT_MAX_SIGMA = 1 << 24
+
+EXPORTED = [
+    "wt_footprint", "wt_build", "wt_batch_footprint", "wt_build_batch", "wt_tree_status",
+    "wt_free", "wt_levels", "wt_access_batch", "wt_rank_batch", "wt_select_batch",
+    "wt_access", "wt_rank", "wt_select", "wt_strerror",
+]
+
+
+class WtError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (what or "wtree", strerror(status), status))
+
+
+class wt_desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("sigma", ctypes.c_uint32), ("width", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if libwtree.so is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libwtree.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    P = ctypes.POINTER
+    sig = {
+        "wt_footprint": ([P(wt_desc), P(u64), P(u64)], i32),
+        "wt_build": ([vp, P(wt_desc), vp, u64, vp, u64, vp, P(vp)], i32),
+        "wt_batch_footprint": ([u32, P(wt_desc), P(u64)], i32),
+        "wt_build_batch": ([u32, P(vp), P(wt_desc), P(vp), P(u64), vp, u64, vp, P(vp)], i32),
+        "wt_tree_status": ([vp], i32),
+        "wt_free": ([vp], None),
+        "wt_levels": ([vp, P(u32), P(vp), P(u64), P(vp), P(u64), P(u64)], i32),
+        "wt_access_batch": ([vp, vp, vp, u64, vp], i32),
+        "wt_rank_batch": ([vp, vp, vp, vp, u64, vp], i32),
+        "wt_select_batch": ([vp, vp, vp, vp, u64, vp], i32),
+        "wt_access": ([vp, u64, P(u32)], i32),
+        "wt_rank": ([vp, u32, u64, P(u64)], i32),
+        "wt_select": ([vp, u32, u64, P(u64)], i32),
+        "wt_strerror": ([i32], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+# ------------------------------------------------------------ raw C ABI ---
+
+def strerror(status: int) -> str:
+    return lib().wt_strerror(status).decode()
+
+
+def wt_footprint(n: int, sigma: int, width: int):
+    d = wt_desc(n, sigma, width)
+    tb, wb = ctypes.c_uint64(), ctypes.c_uint64()
+    rc = lib().wt_footprint(ctypes.byref(d), ctypes.byref(tb), ctypes.byref(wb))
+    return rc, tb.value, wb.value
+
+
+def wt_build(d_S: int, n: int, sigma: int, width: int, d_tree: int, tree_bytes: int, d_work: int,
+             work_bytes: int, stream: int):
+    d = wt_desc(n, sigma, width)
+    h = ctypes.c_void_p()
+    rc = lib().wt_build(d_S, ctypes.byref(d), d_tree, tree_bytes, d_work, work_bytes, stream, ctypes.byref(h))
+    return rc, h.value
+
+
+def wt_batch_footprint(descs):
+    arr = (wt_desc * len(descs))(*[wt_desc(*d) for d in descs])
+    wb = ctypes.c_uint64()
+    rc = lib().wt_batch_footprint(len(descs), arr, ctypes.byref(wb))
+    return rc, wb.value
+
+
+def wt_build_batch(d_S, descs, d_trees, tree_bytes, d_work: int, work_bytes: int, stream: int):
+    m = len(descs)
+    S = (ctypes.c_void_p * m)(*d_S)
+    D = (wt_desc * m)(*[wt_desc(*d) for d in descs])
+    T = (ctypes.c_void_p * m)(*d_trees)
+    TB = (ctypes.c_uint64 * m)(*tree_bytes)
+    out = (ctypes.c_void_p * m)()
+    rc = lib().wt_build_batch(m, S, D, T, TB, d_work, work_bytes, stream, out)
+    return rc, [out[q] for q in range(m)]
+
+
+def wt_tree_status(h: int) -> int:
+    return lib().wt_tree_status(h)
+
+
+def wt_free(h: int) -> None:
+    lib().wt_free(h)
+
+
+def wt_levels(h: int):
+    l, bp, wpl, rp, rs, re = (ctypes.c_uint32(), ctypes.c_void_p(), ctypes.c_uint64(), ctypes.c_void_p(),
+                              ctypes.c_uint64(), ctypes.c_uint64())
+    rc = lib().wt_levels(h, ctypes.byref(l), ctypes.byref(bp), ctypes.byref(wpl), ctypes.byref(rp),
+                         ctypes.byref(rs), ctypes.byref(re))
+    return rc, dict(levels=l.value, bitmaps=bp.value, words_per_level=wpl.value, ranks=rp.value,
+                    rank_stride=rs.value, rank_entries=re.value)
+
+
+def wt_access_batch(h: int, d_i: int, d_sym: int, m: int, stream: int) -> int:
+    return lib().wt_access_batch(h, d_i, d_sym, m, stream)
+
+
+def wt_rank_batch(h: int, d_c: int, d_i: int, d_r: int, m: int, stream: int) -> int:
+    return lib().wt_rank_batch(h, d_c, d_i, d_r, m, stream)
+
+
+def wt_select_batch(h: int, d_c: int, d_j: int, d_pos: int, m: int, stream: int) -> int:
+    return lib().wt_select_batch(h, d_c, d_j, d_pos, m, stream)
+
+
+def wt_access(h: int, i: int):
+    s = ctypes.c_uint32()
+    rc = lib().wt_access(h, i, ctypes.byref(s))
+    return rc, s.value
+
+
+def wt_rank(h: int, c: int, i: int):
+    r = ctypes.c_uint64()
+    rc = lib().wt_rank(h, c, i, ctypes.byref(r))
+    return rc, r.value
+
+
+def wt_select(h: int, c: int, j: int):
+    p = ctypes.c_uint64()
+    rc = lib().wt_select(h, c, j, ctypes.byref(p))
+    return rc, p.value
+
+
+# ------------------------------------------------- torch-backed helpers ---
+
+_TORCH_OF_WIDTH = {1: "uint8", 2: "int16", 4: "int32"}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _alloc(nbytes: int, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+class Tree:
+    """A built tree whose memory is a torch tensor; owns the C handle."""
+
+    def __init__(self, handle: int, tree_mem, work_mem, S, n: int, sigma: int, width: int, stream):
+        self.handle = handle
+        self.tree_mem = tree_mem
+        self.work_mem = work_mem   # kept alive until the build has finished
+        self.S = S
+        self.n, self.sigma, self.width = n, sigma, width
+        self.stream = stream
+        rc, info = wt_levels(handle)
+        if rc != WT_OK:
+            raise WtError(rc, "wt_levels")
+        self.info = info
+
+    @property
+    def levels(self) -> int:
+        return self.info["levels"]
+
+    def status(self) -> int:
+        return wt_tree_status(self.handle)
+
+    def check(self) -> None:
+        rc = self.status()
+        if rc != WT_OK:
+            raise WtError(rc, "build")
+
+    def release_workspace(self) -> None:
+        self.work_mem = None
+
+    def _region(self, ptr: int, count: int):
+        torch = _torch()
+        base = self.tree_mem.data_ptr()
+        off = ptr - base
+        flat = self.tree_mem[off: off + count * 8]
+        return flat.view(torch.int64)
+
+    def bitmaps_device(self):
+        """(levels, words_per_level) int64 view of the level bitmaps."""
+        l, W = self.levels, self.info["words_per_level"]
+        return self._region(self.info["bitmaps"], l * W).view(l, W)
+
+    def ranks_device(self):
+        l, K = self.levels, self.info["rank_stride"]
+        return self._region(self.info["ranks"], l * K).view(l, K)
+
+    def bitmaps(self) -> np.ndarray:
+        self.check()
+        return self.bitmaps_device().cpu().numpy().view(np.uint64)
+
+    def ranks(self) -> np.ndarray:
+        self.check()
+        return self.ranks_device().cpu().numpy().view(np.uint64)
+
+    def access(self, pos):
+        torch = _torch()
+        pos = torch.as_tensor(pos, dtype=torch.int64, device=self.tree_mem.device).contiguous()
+        out = torch.empty(pos.numel(), dtype=torch.int32, device=pos.device)
+        rc = wt_access_batch(self.handle, pos.data_ptr(), out.data_ptr(), pos.numel(), _stream_handle(self.stream))
+        if rc != WT_OK:
+            raise WtError(rc, "wt_access_batch")
+        return out
+
+    def rank(self, c, i):
+        torch = _torch()
+        dev = self.tree_mem.device
+        c = torch.as_tensor(c, dtype=torch.int32, device=dev).contiguous()
+        i = torch.as_tensor(i, dtype=torch.int64, device=dev).contiguous()
+        out = torch.empty(c.numel(), dtype=torch.int64, device=dev)
+        rc = wt_rank_batch(self.handle, c.data_ptr(), i.data_ptr(), out.data_ptr(), c.numel(),
+                           _stream_handle(self.stream))
+        if rc != WT_OK:
+            raise WtError(rc, "wt_rank_batch")
+        return out
+
+    def select(self, c, j):
+        torch = _torch()
+        dev = self.tree_mem.device
+        c = torch.as_tensor(c, dtype=torch.int32, device=dev).contiguous()
+        j = torch.as_tensor(j, dtype=torch.int64, device=dev).contiguous()
+        out = torch.empty(c.numel(), dtype=torch.int64, device=dev)
+        rc = wt_select_batch(self.handle, c.data_ptr(), j.data_ptr(), out.data_ptr(), c.numel(),
+                             _stream_handle(self.stream))
+        if rc != WT_OK:
+            raise WtError(rc, "wt_select_batch")
+        return out
+
+    def close(self) -> None:
+        if self.handle:
+            wt_free(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def to_device(S: np.ndarray, device="cuda"):
+    """Copy a numpy symbol array to the GPU (uint16/uint32 travel as int16/int32 views)."""
+    torch = _torch()
+    width = S.dtype.itemsize
+    view = {1: np.uint8, 2: np.int16, 4: np.int32}[width]
+    return torch.from_numpy(np.ascontiguousarray(S).view(view)).to(device)
+
+
+def build(S, sigma: int, width: int | None = None, stream=None, tree_mem=None, work_mem=None) -> Tree:
+    """Build the tree of a device tensor S (uint8 / int16 / int32 storage)."""
+    torch = _torch()
+    width = width or S.element_size()
+    n = S.numel()
+    rc, tb, wb = wt_footprint(n, sigma, width)
+    if rc != WT_OK:
+        raise WtError(rc, "wt_footprint")
+    dev = S.device
+    tree_mem = tree_mem if tree_mem is not None else _alloc(tb, dev)
+    work_mem = work_mem if work_mem is not None else _alloc(wb, dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    rc, h = wt_build(S.data_ptr() if n else 0, n, sigma, width, tree_mem.data_ptr(), tree_mem.numel(),
+                     work_mem.data_ptr(), work_mem.numel(), int(st.cuda_stream))
+    if rc != WT_OK:
+        raise WtError(rc, "wt_build")
+    return Tree(h, tree_mem, work_mem, S, n, sigma, width, st)
+
+
+def build_batch(Ss, sigmas, widths=None, stream=None):
+    """Build several trees with wt_build_batch; returns a list of Tree."""
+    torch = _torch()
+    m = len(Ss)
+    widths = widths or [S.element_size() for S in Ss]
+    descs = [(S.numel(), int(sg), int(w)) for S, sg, w in zip(Ss, sigmas, widths)]
+    dev = Ss[0].device
+    trees_mem, tbytes = [], []
+    for (n, sg, w) in descs:
+        rc, tb, _ = wt_footprint(n, sg, w)
+        if rc != WT_OK:
+            raise WtError(rc, "wt_footprint")
+        trees_mem.append(_alloc(tb, dev))
+        tbytes.append(trees_mem[-1].numel())
+    rc, wb = wt_batch_footprint(descs)
+    if rc != WT_OK:
+        raise WtError(rc, "wt_batch_footprint")
+    work = _alloc(wb, dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    rc, hs = wt_build_batch([S.data_ptr() if S.numel() else 0 for S in Ss], descs,
+                            [t.data_ptr() for t in trees_mem], tbytes, work.data_ptr(), work.numel(),
+                            int(st.cuda_stream))
+    if rc != WT_OK:
+        raise WtError(rc, "wt_build_batch")
+    return [Tree(h, tm, work, S, d[0], d[1], d[2], st) for h, tm, S, d in zip(hs, trees_mem, Ss, descs)]

@@ -1,0 +1,97 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+that include/wtree.h declares, and its host-only logic (footprints,
+argument validation, status strings) behaves as documented.  No call here
+reaches the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _wt():
+    from paper_1610_05994_amd import wtree
+    return wtree
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "wtree.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(wt_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    wt = _wt()
+    L = wt.lib()
+    names = _declared()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(wt.EXPORTED) == names
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    wt = _wt()
+    monkeypatch.setattr(wt, "_lib", None)
+    monkeypatch.setattr(wt, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        wt.lib()
+
+
+def test_footprint_matches_layout_convention():
+    wt = _wt()
+    for n, sigma, width in [(0, 1, 1), (1, 2, 1), (1 << 20, 256, 1), (1000, 1 << 20, 4), (4097, 20, 2)]:
+        rc, tb, wb = wt.wt_footprint(n, sigma, width)
+        assert rc == wt.WT_OK
+        l = max(0, (sigma - 1).bit_length())
+        W = ((n + 63) // 64 + 7) // 8 * 8
+        KS = ((n + 511) // 512 + 1 + 7) // 8 * 8
+        assert tb == 256 + 8 * l * (W + KS)
+        assert wb >= 256 and wb % 256 == 0
+
+
+@pytest.mark.parametrize("n,sigma,width", [(10, 0, 1), (10, 257, 1), (10, 70000, 2), (10, 4, 3),
+                                           (10, (1 << 24) + 1, 4), (1 << 40, 4, 1)])
+def test_footprint_rejects_bad_descriptors(n, sigma, width):
+    wt = _wt()
+    assert wt.wt_footprint(n, sigma, width)[0] == wt.WT_EINVAL
+
+
+def test_build_argument_checks_before_any_device_call():
+    wt = _wt()
+    rc, tb, wb = wt.wt_footprint(1000, 256, 1)
+    fake = 1 << 40  # never dereferenced: every case fails validation first
+    assert wt.wt_build(fake, 1000, 256, 1, 0, tb, fake, wb, 0)[0] == wt.WT_EINVAL
+    assert wt.wt_build(fake + 3, 1000, 256, 1, fake, tb, fake, wb, 0)[0] == wt.WT_EINVAL
+    assert wt.wt_build(fake, 1000, 256, 1, fake + 64, tb, fake, wb, 0)[0] == wt.WT_EINVAL
+    assert wt.wt_build(fake, 1000, 256, 1, fake, tb - 1, fake, wb, 0)[0] == wt.WT_ENOMEM
+    assert wt.wt_build(fake, 1000, 256, 1, fake, tb, fake, wb - 1, 0)[0] == wt.WT_ENOMEM
+    assert wt.wt_build(fake, 1000, 0, 1, fake, tb, fake, wb, 0)[0] == wt.WT_EINVAL
+    assert wt.wt_build(0, 1000, 256, 1, fake, tb, fake, wb, 0)[0] == wt.WT_EINVAL
+
+
+def test_batch_footprint_and_checks():
+    wt = _wt()
+    descs = [(1000, 4, 1), (5000, 1 << 16, 2)]
+    rc, wb = wt.wt_batch_footprint(descs)
+    assert rc == wt.WT_OK
+    singles = sum(wt.wt_footprint(*d)[2] for d in descs)
+    assert wb >= singles
+    assert wt.wt_batch_footprint([(10, 0, 1)])[0] == wt.WT_EINVAL
+    fake = 1 << 40
+    tbs = [wt.wt_footprint(*d)[1] for d in descs]
+    rc, hs = wt.wt_build_batch([fake, fake], descs, [fake, fake], tbs, fake, wb - 1, 0)
+    assert rc == wt.WT_ENOMEM and hs == [None, None]
+    rc, hs = wt.wt_build_batch([fake, fake], descs, [fake, fake], [tbs[0], tbs[1] - 8], fake, wb, 0)
+    assert rc == wt.WT_ENOMEM
+
+
+def test_status_strings():
+    wt = _wt()
+    assert wt.strerror(wt.WT_OK) == "success"
+    assert "sigma" in wt.strerror(wt.WT_ERANGE)
+    assert wt.strerror(99) == "unknown status"
+    assert wt.lib().wt_tree_status(None) == wt.WT_EINVAL
+    wt.lib().wt_free(None)
