@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Benchmark one wavelet-tree build on one MI355X.
+
+A step is one complete build (every kernel of wt_build: histogram, node
+tables, one pass per level with bitmaps, rank directory and next-level
+order) of one synthetic sequence that is already resident in HBM.  The
+default workload is n = 2^28 uint8 symbols, sigma = 256, with Zipf(1.1)
+symbol frequencies over a seeded permutation of the alphabet.
+
+Prints one JSON line: symbols/s of whole builds, the roofline of the
+dominant kernel (the level pass) from HIP events recorded on the build's
+stream around every launch in the timed region, and the sequential CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import wtgen  # noqa: E402
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "input symbols/s and % HBM roofline per wtree build; p50/p99 build latency served"
+
+WORKLOADS = {
+    "c1": "n=2^20 uint8 sigma=256 uniform",
+    "c2": "n=2^28 uint8 sigma=256 Zipf(1.1) over a seeded permutation of the alphabet",
+    "c3": "n=2^28 uint32 sigma=2^20 half uniform, half 64 Gaussian clusters (sd 2^10)",
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1610_05994_amd", "csrc", "wt_build.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM bytes per level launch from the committed rocprofv3 counter runs,
+    or None when the kernel source changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    ent = data.get(workload)
+    if not ent or ent.get("kernel_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_level_launch")
+
+
+def cpu_baseline(workload: str, lg: int, runs: int):
+    import oracle
+    S, sigma = wtgen.workload("%s@lg%d" % (workload, lg))
+    oracle.build(S[:4096], sigma)  # load + warm the library
+    times = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        oracle.build(S, sigma)
+        times.append(time.perf_counter() - t0)
+    med = statistics.median(times)
+    return {
+        "value": S.shape[0] / med,
+        "unit": "symbols/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "first-principles sequential oracle (gcc -O2, one thread) on n=2^%d symbols of the same "
+                  "generator and distribution, median of %d runs of %.2f s each, bitmaps + rank directories"
+                  % (lg, runs, med),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-lg", type=int, default=26)
+    ap.add_argument("--cpu-runs", type=int, default=3)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the build runs on a single MI355X and this "
+              "benchmark takes no multi-GPU configuration (--gpus 1).", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1610_05994_amd import wtree
+
+    dev = torch.device("cuda:0")
+    print("bench: generating workload %s" % args.workload, file=sys.stderr, flush=True)
+    S, sigma = wtgen.workload(args.workload)
+    n, width = S.shape[0], S.dtype.itemsize
+    dS = wtree.to_device(S, dev)
+    rc, tb, wb = wtree.wt_footprint(n, sigma, width)
+    assert rc == wtree.WT_OK
+    tree_mem = torch.empty(tb, dtype=torch.uint8, device=dev)
+    work_mem = torch.empty(wb, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+    sh = int(stream.cuda_stream)
+
+    if args.calib_copy_mib:
+        src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    def one_build():
+        rc, h = wtree.wt_build(dS.data_ptr(), n, sigma, width, tree_mem.data_ptr(), tb,
+                               work_mem.data_ptr(), wb, sh)
+        if rc != wtree.WT_OK:
+            raise wtree.WtError(rc, "wt_build")
+        return h
+
+    print("bench: warmup %d" % args.warmup, file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        wtree.wt_free(one_build())
+    torch.cuda.synchronize()
+
+    # sanity: the last warm-up tree decodes sampled positions back to S
+    h = one_build()
+    if wtree.wt_tree_status(h) != wtree.WT_OK:
+        raise RuntimeError("build reported an error")
+    pos = torch.from_numpy(np.random.Generator(np.random.PCG64(1)).integers(0, n, 4096)).to(dev)
+    sym = torch.empty(4096, dtype=torch.int32, device=dev)
+    assert wtree.wt_access_batch(h, pos.data_ptr(), sym.data_ptr(), 4096, sh) == wtree.WT_OK
+    torch.cuda.synchronize()
+    want = torch.from_numpy(S[pos.cpu().numpy()].astype(np.int64))
+    assert torch.equal(sym.cpu().to(torch.int64) & 0xFFFFFFFF, want), "sampled access mismatch"
+    wtree.wt_free(h)
+
+    print("bench: timing %d steps" % args.steps, file=sys.stderr, flush=True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    wtree.wt_prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        h = one_build()
+        ev[k][1].record(stream)
+        wtree.wt_free(h)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    recs = wtree.wt_prof_read()
+    wtree.wt_prof_enable(False)
+
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    step_ms = sorted(a.elapsed_time(b) for a, b in ev)
+    p50 = float(np.percentile(step_ms, 50))
+    p99 = float(np.percentile(step_ms, 99))
+    value = n / (ms_per_step / 1e3)
+
+    lvl = [r for r in recs if r["kernel"] == "level"]
+    lvl_ms = sum(r["ms"] for r in lvl)
+    lvl_bytes = sum(r["bytes"] for r in lvl)
+    launches = len(lvl)
+    achieved = lvl_bytes / (lvl_ms / 1e3) / 1e9 if lvl_ms > 0 else 0.0
+    fams = {}
+    for r in recs:
+        f = fams.setdefault(r["kernel"], {"launches": 0, "ms": 0.0})
+        f["launches"] += 1
+        f["ms"] += r["ms"]
+    for f in fams.values():
+        f["avg_us"] = round(f["ms"] * 1e3 / f["launches"], 2)
+        f["ms_per_step"] = round(f["ms"] / args.steps, 4)
+        del f["ms"]
+    traffic = load_traffic(args.workload)
+    levels = max(0, (sigma - 1).bit_length())
+    qmin = n * width + (tb - 256)  # read S once + write every bitmap word and rank entry once
+    qmin_gbps = qmin / (p50 / 1e3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "symbols/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {1: "u8", 2: "u16", 4: "u32"}[width],
+        "data": "synthetic",
+        "config": {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]), "n": n, "sigma": sigma,
+                   "width_bytes": width, "levels": levels, "seed": wtgen.SEED_BASE + int(args.workload[1]) - 1},
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": traffic,
+            "kernel": "k_level (one launch per tree level)",
+            "avg_launch_us": lvl_ms * 1e3 / max(launches, 1),
+            "algorithmic_bytes_per_launch": lvl_bytes / max(launches, 1),
+        },
+        "build_latency_ms": {"p50": p50, "p99": p99},
+        "compulsory_bytes": {"bytes": qmin, "gbps_at_p50": qmin_gbps, "frac_of_peak": qmin_gbps / HBM_PEAK_GBPS},
+        "kernels": fams,
+    }
+    if not args.no_cpu_baseline:
+        print("bench: CPU oracle baseline on n=2^%d" % args.cpu_sample_lg, file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_lg, args.cpu_runs)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

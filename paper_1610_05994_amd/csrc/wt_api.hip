@@ -5,10 +5,13 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
+#include <vector>
 
 #include "wt_internal.h"
 #include "wtree.h"
+#include "wtree_prof.h"
 
 struct wt_tree {
     wt::Layout L;
@@ -19,6 +22,54 @@ struct wt_tree {
 };
 
 namespace wt {
+
+// ------------------------------------------------------------- profiling --
+// While on, each enqueued kernel is bracketed by two events on its stream.
+struct ProfEntry {
+    wt_prof_rec rec;
+    hipEvent_t a, b;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfEntry> g_prof;
+static std::vector<hipEvent_t> g_event_pool;
+
+static hipEvent_t prof_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Opens a record; returns its index or -1 when profiling is off.
+static long prof_begin(hipStream_t st, const char *kernel, uint32_t level, uint32_t width, uint64_t n,
+                       uint64_t bytes) {
+    if (!g_prof_on) return -1;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    ProfEntry e;
+    memset(&e.rec, 0, sizeof(e.rec));
+    strncpy(e.rec.kernel, kernel, sizeof(e.rec.kernel) - 1);
+    e.rec.level = level;
+    e.rec.width = width;
+    e.rec.n = n;
+    e.rec.bytes = bytes;
+    e.a = prof_event();
+    e.b = prof_event();
+    if (!e.a || !e.b) return -1;
+    (void)hipEventRecord(e.a, st);
+    g_prof.push_back(e);
+    return (long)g_prof.size() - 1;
+}
+
+static void prof_end(long idx, hipStream_t st) {
+    if (idx < 0) return;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if ((size_t)idx < g_prof.size()) (void)hipEventRecord(g_prof[idx].b, st);
+}
 
 void make_layout(uint64_t n, uint32_t sigma, uint32_t width, Layout *L) {
     memset(L, 0, sizeof(*L));
@@ -32,7 +83,7 @@ void make_layout(uint64_t n, uint32_t sigma, uint32_t width, Layout *L) {
     L->words = round_up(ceil_div(n, 64), 8);
     L->rank_entries = ceil_div(n, 512) + 1;
     L->rank_stride = round_up(L->rank_entries, 8);
-    L->ntiles = ceil_div(n, kTile);
+    L->ntiles = ceil_div(n, tile_syms(width));
 
     L->tree_bits_off = kHeaderBytes;
     L->tree_ranks_off = L->tree_bits_off + (uint64_t)l * L->words * 8;
@@ -45,11 +96,12 @@ void make_layout(uint64_t n, uint32_t sigma, uint32_t width, Layout *L) {
     L->ws_tb = off;
     if (l >= 3) off += tbytes;
 
+    L->nsup = ceil_div(L->ntiles, kSup);
     L->ws_ctrl = off;
-    L->ws_tickets = off;
+    L->ws_tile_ones = off;
+    off += round_up((uint64_t)l * L->ntiles * 4, 256);
+    L->ws_done = off;
     off += round_up((uint64_t)(l ? l : 1) * 4, 256);
-    L->ws_status = off;
-    off += round_up((uint64_t)l * L->ntiles * 8, 256);
     L->ws_hist = off;
     off += round_up((1ull << h) * 8, 256);
     L->ws_ones = off;
@@ -58,6 +110,8 @@ void make_layout(uint64_t n, uint32_t sigma, uint32_t width, Layout *L) {
     off += round_up(e * 8, 256);
     L->ws_ctrl_bytes = off - L->ws_ctrl;
 
+    L->ws_sup = off;
+    off += round_up((uint64_t)l * L->nsup * 8, 256);
     L->ws_zo = off;
     e = 0;
     for (uint32_t i = 0; i < l; i++) { L->zo_off[i] = e; e += 1ull << i; }
@@ -78,28 +132,45 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
     uint32_t *tree_status = reinterpret_cast<uint32_t *>(tree);
     uint64_t *bits = reinterpret_cast<uint64_t *>(tree + L.tree_bits_off);
     uint64_t *ranks = reinterpret_cast<uint64_t *>(tree + L.tree_ranks_off);
-    uint32_t *tickets = reinterpret_cast<uint32_t *>(work + L.ws_tickets);
-    uint64_t *status = reinterpret_cast<uint64_t *>(work + L.ws_status);
+    uint32_t *tile_ones = reinterpret_cast<uint32_t *>(work + L.ws_tile_ones);
     unsigned long long *hist = reinterpret_cast<unsigned long long *>(work + L.ws_hist);
     unsigned long long *ones = reinterpret_cast<unsigned long long *>(work + L.ws_ones);
+    unsigned long long *sup = reinterpret_cast<unsigned long long *>(work + L.ws_sup);
+    uint32_t *done = reinterpret_cast<uint32_t *>(work + L.ws_done);
     ulonglong2 *zo = reinterpret_cast<ulonglong2 *>(work + L.ws_zo);
     uint64_t *start = reinterpret_cast<uint64_t *>(work + L.ws_start);
     uint64_t *partials = reinterpret_cast<uint64_t *>(work + L.ws_partials);
 
+    long pr = prof_begin(st, "zero", 0, L.width, L.n, L.ws_ctrl_bytes);
     hipError_t err = launch_zero(work + L.ws_ctrl, L.ws_ctrl_bytes, tree_status, L.n == 0 ? ranks : nullptr,
                                  (uint64_t)l * L.rank_stride, st);
+    prof_end(pr, st);
     if (err != hipSuccess || L.n == 0) return err;
 
-    HistArgs ha;
-    ha.S = S;
-    ha.hist = hist;
-    ha.tree_status = tree_status;
-    ha.n = L.n;
-    ha.sigma = L.sigma;
-    ha.symmask = l ? (uint32_t)((1ull << l) - 1) : 0u;
-    ha.hshift = l - h;
-    ha.nbins = 1u << h;
-    if ((err = launch_hist(ha, L.width, L.ntiles, st)) != hipSuccess) return err;
+    IngestArgs ia;
+    ia.S = S;
+    ia.hist = hist;
+    ia.tile_ones0 = l ? tile_ones : nullptr;
+    ia.tree_status = tree_status;
+    ia.n = L.n;
+    ia.ntiles = L.ntiles;
+    ia.sigma = L.sigma;
+    ia.symmask = l ? (uint32_t)((1ull << l) - 1) : 0u;
+    ia.hshift = l - h;
+    ia.nbins = 1u << h;
+    ia.copies = (kHistWords >> h) < 64 ? (kHistWords >> h) : 64;
+    ia.msb = l ? l - 1 : 0;
+    {
+        // contiguous tiles per ingest workgroup: ~2048 workgroups, a multiple
+        // of kWaves dividing kSup, so a workgroup stays inside one superchunk
+        uint64_t k = kWaves;
+        while (k < kSup && L.ntiles > 2048 * k) k <<= 1;
+        ia.tiles_per_block = k;
+    }
+    pr = prof_begin(st, "ingest", 0, L.width, L.n, L.n * L.width);
+    err = launch_ingest(ia, L.width, st);
+    prof_end(pr, st);
+    if (err != hipSuccess) return err;
     if (l == 0) return hipSuccess;
 
     TopArgs ta;
@@ -110,7 +181,10 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
     ta.h = h;
     ta.levels = l;
     for (uint32_t i = 0; i < 32; i++) ta.zo_off[i] = L.zo_off[i];
-    if ((err = launch_top(ta, st)) != hipSuccess) return err;
+    pr = prof_begin(st, "top", 0, L.width, L.n, 0);
+    err = launch_top(ta, st);
+    prof_end(pr, st);
+    if (err != hipSuccess) return err;
 
     uint8_t *tbuf[2] = {work + L.ws_ta, work + L.ws_tb};
     for (uint32_t i = 0; i < l; i++) {
@@ -123,17 +197,26 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
             pa.partials = partials;
             pa.nodes = 1ull << i;
             pa.n = L.n;
-            if ((err = launch_plan(pa, st)) != hipSuccess) return err;
+            pr = prof_begin(st, "plan", i, L.width, L.n, (1ull << i) * (8 + 16 + 8 + 16));
+            err = launch_plan(pa, st);
+            prof_end(pr, st);
+            if (err != hipSuccess) return err;
         }
+        unsigned long long *sup_i = sup + (uint64_t)i * L.nsup;
+        pr = prof_begin(st, "supsum", i, L.width, L.n, L.ntiles * 4 + L.nsup * 16);
+        err = launch_supsum(tile_ones + (uint64_t)i * L.ntiles, sup_i, done + i, L.ntiles, st);
+        prof_end(pr, st);
+        if (err != hipSuccess) return err;
         LevelArgs a;
         a.tin = (i == 0) ? S : tbuf[(i - 1) & 1];  // T_i for i >= 1 alternates ta, tb
         a.tout = (i + 1 < l) ? tbuf[i & 1] : nullptr;
         a.bits = bits + (uint64_t)i * L.words;
         a.ranks = ranks + (uint64_t)i * L.rank_stride;
         a.zo = zo + L.zo_off[i];
+        a.tile_ones = tile_ones + (uint64_t)i * L.ntiles;
+        a.sup = sup_i;
+        a.tile_ones_next = (i + 1 < l) ? tile_ones + (uint64_t)(i + 1) * L.ntiles : nullptr;
         a.ones_next = (i + 1 >= h && i + 1 < l) ? ones + L.ones_off[i + 1] : nullptr;
-        a.status = status + (uint64_t)i * L.ntiles;
-        a.ticket = tickets + i;
         a.n = L.n;
         a.words = L.words;
         a.rank_entries = L.rank_entries;
@@ -142,7 +225,11 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         a.levels = l;
         a.level = i;
         a.symmask = (uint32_t)((1ull << l) - 1);
-        if ((err = launch_level(a, L.width, st)) != hipSuccess) return err;
+        const uint64_t lbytes = L.n * L.width * (a.tout ? 2 : 1) + L.words * 8 + L.rank_stride * 8;
+        pr = prof_begin(st, "level", i, L.width, L.n, lbytes);
+        err = launch_level(a, L.width, st);
+        prof_end(pr, st);
+        if (err != hipSuccess) return err;
     }
     return hipSuccess;
 }
@@ -355,6 +442,31 @@ int wt_select(const wt_tree *t, uint32_t c, uint64_t j, uint64_t *pos) {
     if (rc != WT_OK) return rc;
     if (a == ~0ull) return WT_ENOTFOUND;
     *pos = a;
+    return WT_OK;
+}
+
+int wt_prof_enable(int on) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (auto &e : g_prof) {
+        g_event_pool.push_back(e.a);
+        g_event_pool.push_back(e.b);
+    }
+    g_prof.clear();
+    g_prof_on = on != 0;
+    return WT_OK;
+}
+
+int wt_prof_read(wt_prof_rec *out, uint64_t max, uint64_t *count) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (auto &e : g_prof) {
+        if (hipEventSynchronize(e.b) != hipSuccess) return WT_EDEVICE;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e.a, e.b) != hipSuccess) return WT_EDEVICE;
+        e.rec.ms = ms;
+    }
+    if (out)
+        for (uint64_t k = 0; k < max && k < g_prof.size(); k++) out[k] = g_prof[k].rec;
+    if (count) *count = g_prof.size();
     return WT_OK;
 }
 

@@ -15,19 +15,22 @@
 // position by position: a 64-position word is built by one workgroup from
 // 64 consecutive symbols and has exactly one writer (no atomics on bitmaps).
 //
-// One level pass over tiles of kTile symbols does, in a single read of T_i:
-//   * the bitmap words of the tile (one writer per word),
-//   * the tile's ones count, turned into the global rank of its first
-//     position by a decoupled look-back over tiles taken in ticket order
-//     (the device-wide exclusive scan of the segment counts),
+// Segments are tiles of kTile consecutive positions of T_i.  The ones count
+// of every tile of level i is known before level i runs: level 0's come from
+// the ingest pass, and the pass of level i-1, which knows where every symbol
+// lands in T_i, adds up the level-i bits per destination tile.  A small scan
+// turns them into the rank of each tile's first position, so a level pass
+// needs no inter-tile communication at all.  One level pass, in one read of
+// T_i, writes:
+//   * the bitmap words of the tile,
 //   * the rank directory entries at the multiples of 512 inside the tile,
 //   * the stable split into T_{i+1}: with O1(v) the ones before node v and
 //     rank1(p) the ones before position p,
 //       bit 0 at p  ->  p - rank1(p) + O1(v)
 //       bit 1 at p  ->  start_{i+1}(2v+1) - O1(v) + rank1(p)
 //     staged in LDS so that the global stores are aligned 16-byte chunks,
-//   * for levels beyond the first-pass histogram, the ones counts of the
-//     next level's nodes.
+//   * the ones of level i+1 per destination tile, and, for levels beyond
+//     the ingest histogram, per level-(i+1) node.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -37,21 +40,10 @@ namespace wt {
 
 namespace {
 
-constexpr uint64_t kFlagAgg = 1ull << 62;
-constexpr uint64_t kFlagPre = 2ull << 62;
-constexpr uint64_t kValMask = (1ull << 62) - 1;
-
 template <int W> struct ElemT;
 template <> struct ElemT<1> { typedef uint8_t T; };
 template <> struct ElemT<2> { typedef uint16_t T; };
 template <> struct ElemT<4> { typedef uint32_t T; };
-
-__device__ __forceinline__ uint64_t ld_acq(const uint64_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_rel(uint64_t *p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     const int lane = threadIdx.x & 63;
@@ -85,33 +77,64 @@ __device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
     return v;
 }
 
-// Load kEPT (=16) consecutive symbols starting at position pos.  Symbols at
-// positions >= n read as 0.  pos is a multiple of 16, so a full load is
-// 16-byte aligned for every width (buffers are 16-byte aligned).
+// Exclusive scan of one value per thread over the block (kThreads threads);
+// *total receives the sum.  Uses s_w (kWaves entries) and synchronises.
+__device__ __forceinline__ unsigned long long block_excl_scan64(unsigned long long v, unsigned long long *s_w,
+                                                                unsigned long long *total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long incl = wave_incl_scan64(v);
+    if (lane == 63) s_w[wv] = incl;
+    __syncthreads();
+    unsigned long long off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) {
+        off += (w < wv) ? s_w[w] : 0ull;
+        tot += s_w[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + incl - v;
+}
+
+// Symbol e (0 <= e < 16/W) of a 16-byte chunk.
 template <int W>
-__device__ __forceinline__ int load16(const void *src, uint64_t pos, uint64_t n, uint32_t (&x)[16]) {
+__device__ __forceinline__ uint32_t chunk_elem(const uint4 &v, int e) {
+    const uint32_t d4[4] = {v.x, v.y, v.z, v.w};
+    const uint32_t d = d4[(e * W) >> 2];
+    return (W == 4) ? d : ((d >> (8 * ((e * W) & 3))) & ((1u << (8 * W)) - 1u));
+}
+
+// Symbol k (0 <= k < 64/W) of one thread's 64 bytes.
+template <int W>
+__device__ __forceinline__ uint32_t raw_elem(const uint4 (&raw)[4], int k) {
+    return chunk_elem<W>(raw[k / (16 / W)], k % (16 / W));
+}
+
+// Load the 64/W symbols of one thread starting at position pos (a multiple
+// of 64/W, so full loads are 16-byte aligned).  Positions >= n read as 0;
+// returns the number of symbols below n.
+template <int W>
+__device__ __forceinline__ int load64(const void *src, uint64_t pos, uint64_t n, uint4 (&raw)[4]) {
     typedef typename ElemT<W>::T T;
+    constexpr int E = 64 / W;
     const T *s = reinterpret_cast<const T *>(src);
-    if (pos + 16 <= n) {
+    if (pos + E <= n) {
         const uint4 *p = reinterpret_cast<const uint4 *>(s + pos);
 #pragma unroll
-        for (int q = 0; q < W; q++) {
-            uint4 v = p[q];
-            uint32_t d4[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int d = 0; d < 4; d++) {
-#pragma unroll
-                for (int e = 0; e < 4 / W; e++) {
-                    uint32_t val = (W == 4) ? d4[d] : ((d4[d] >> (8 * W * e)) & ((1u << (8 * W)) - 1u));
-                    x[q * (16 / W) + d * (4 / W) + e] = val;
-                }
-            }
-        }
-        return 16;
+        for (int q = 0; q < 4; q++) raw[q] = p[q];
+        return E;
     }
-    int nval = pos < n ? (int)(n - pos) : 0;
+    const int nval = pos < n ? (int)(n - pos) : 0;
+    uint32_t d[16];
 #pragma unroll
-    for (int k = 0; k < 16; k++) x[k] = (k < nval) ? (uint32_t)s[pos + k] : 0u;
+    for (int q = 0; q < 16; q++) d[q] = 0;
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+        const uint32_t v = (k < nval) ? (uint32_t)s[pos + k] : 0u;
+        d[(k * W) >> 2] |= (W == 4) ? v : (v << (8 * ((k * W) & 3)));
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) raw[q] = make_uint4(d[4 * q], d[4 * q + 1], d[4 * q + 2], d[4 * q + 3]);
     return nval;
 }
 
@@ -127,33 +150,59 @@ __global__ void k_zero(uint64_t *p, uint64_t words, uint32_t *tree_status, uint6
     if (blockIdx.x == 0 && threadIdx.x == 0) *tree_status = 0;
 }
 
-// ----------------------------------------------- validation + histogram ---
-// Reads S once: flags symbols >= sigma and counts the top min(l, kTopBits)
-// bits of every symbol (the node counts of the first levels, Algorithm pwt's
-// counting step hoisted out of the level loop).
+// ---------------------------------------------------------------- ingest --
+// Reads S once: flags symbols >= sigma, counts the top min(l, kTopBits) bits
+// of every symbol (the node counts of the first levels: Algorithm pwt's
+// counting step, hoisted out of the level loop) and the ones of level 0 (the
+// most significant bit) in every tile.  Each bin lives in a.copies LDS
+// copies picked by lane, so the hot bins of skewed data do not serialise.
 
 template <int W>
-__global__ __launch_bounds__(kThreads) void k_hist(HistArgs a) {
-    __shared__ uint32_t s_h[1u << kTopBits];
-    for (uint32_t b = threadIdx.x; b < a.nbins; b += kThreads) s_h[b] = 0;
+__global__ __launch_bounds__(kThreads) void k_ingest(IngestArgs a) {
+    constexpr int E = 64 / W;
+    constexpr uint64_t TILE = tile_syms(W);
+    __shared__ uint32_t s_h[kHistWords];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const uint32_t copy = (uint32_t)lane % a.copies;
+    for (uint32_t b = tid; b < a.nbins * a.copies; b += kThreads) s_h[b] = 0;
     __syncthreads();
+    // this workgroup's tiles: [t0, t1), all inside one superchunk; wave wv
+    // takes every kWaves-th of them
+    const uint64_t t0 = (uint64_t)blockIdx.x * a.tiles_per_block;
+    const uint64_t t1 = (t0 + a.tiles_per_block < a.ntiles) ? t0 + a.tiles_per_block : a.ntiles;
     bool bad = false;
-    const uint64_t step = (uint64_t)gridDim.x * kThreads * kEPT;
-    for (uint64_t pos = ((uint64_t)blockIdx.x * kThreads + threadIdx.x) * kEPT; pos < a.n; pos += step) {
-        uint32_t x[16];
-        int nval = load16<W>(a.S, pos, a.n, x);
+    uint64_t t = t0 + wv;
+    uint4 raw[4], nxt[4];
+    int nval = (t < t1) ? load64<W>(a.S, t * TILE + (uint64_t)lane * E, a.n, raw) : 0;
+    for (; t < t1; t += kWaves) {
+        int nval_n = 0;
+        if (t + kWaves < t1) nval_n = load64<W>(a.S, (t + kWaves) * TILE + (uint64_t)lane * E, a.n, nxt);
+        uint32_t ones = 0;
 #pragma unroll
-        for (int k = 0; k < 16; k++) {
+        for (int k = 0; k < E; k++) {
             if (k < nval) {
-                bad |= x[k] >= a.sigma;
-                atomicAdd(&s_h[(x[k] & a.symmask) >> a.hshift], 1u);
+                const uint32_t x = raw_elem<W>(raw, k);
+                bad |= x >= a.sigma;
+                const uint32_t xm = x & a.symmask;
+                atomicAdd(&s_h[(xm >> a.hshift) * a.copies + copy], 1u);
+                ones += (xm >> a.msb) & 1u;
             }
         }
+        if (a.tile_ones0) {
+            ones = wave_sum32(ones);
+            if (lane == 0) a.tile_ones0[t] = ones;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) raw[q] = nxt[q];
+        nval = nval_n;
     }
-    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(a.tree_status, 1u);
+    if (__any(bad) && lane == 0) atomicOr(a.tree_status, 1u);
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < a.nbins; b += kThreads)
-        if (s_h[b]) atomicAdd(&a.hist[b], (unsigned long long)s_h[b]);
+    for (uint32_t b = tid; b < a.nbins; b += kThreads) {
+        uint32_t c = 0;
+        for (uint32_t q = 0; q < a.copies; q++) c += s_h[b * a.copies + q];
+        if (c) atomicAdd(&a.hist[b], (unsigned long long)c);
+    }
 }
 
 // ----------------------------------------- node tables of the top levels --
@@ -165,27 +214,34 @@ __global__ __launch_bounds__(kThreads) void k_hist(HistArgs a) {
 
 __global__ __launch_bounds__(kThreads) void k_top(TopArgs a) {
     __shared__ unsigned long long P[(1u << kTopBits) + 1];
+    __shared__ unsigned long long s_w[kWaves];
     const uint32_t nb = 1u << a.h;
-    if (threadIdx.x == 0) {
-        unsigned long long acc = 0;
-        for (uint32_t b = 0; b < nb; b++) {
-            P[b] = acc;
-            acc += a.hist[b];
-        }
-        P[nb] = acc;
+    const uint32_t tid = threadIdx.x;
+    unsigned long long carry = 0;
+    for (uint32_t b0 = 0; b0 < nb; b0 += kThreads) {
+        unsigned long long tot;
+        const uint32_t b = b0 + tid;
+        const unsigned long long ex = block_excl_scan64(b < nb ? a.hist[b] : 0ull, s_w, &tot);
+        if (b < nb) P[b] = carry + ex;
+        carry += tot;
     }
+    if (tid == 0) P[nb] = carry;
     __syncthreads();
     for (uint32_t i = 0; i < a.h; i++) {
         const uint32_t s = a.h - i - 1;  // prefix length i+1 -> shift into H's bins
-        ulonglong2 *zo = a.zo + a.zo_off[i];
-        for (uint32_t v = threadIdx.x; v < (1u << i); v += kThreads) {
-            unsigned long long o1 = 0;
-            for (uint32_t u = 0; u < v; u++) o1 += P[(2 * u + 2) << s] - P[(2 * u + 1) << s];
-            zo[v] = make_ulonglong2(o1, P[(2 * v + 1) << s] - o1);
+        unsigned long long o1c = 0;
+        for (uint32_t v0 = 0; v0 < (1u << i); v0 += kThreads) {
+            const uint32_t v = v0 + tid;
+            const bool live = v < (1u << i);
+            const unsigned long long ones = live ? P[(2 * v + 2) << s] - P[(2 * v + 1) << s] : 0ull;
+            unsigned long long t2;
+            const unsigned long long o1 = o1c + block_excl_scan64(ones, s_w, &t2);
+            if (live) a.zo[a.zo_off[i] + v] = make_ulonglong2(o1, P[(2 * v + 1) << s] - o1);
+            o1c += t2;
         }
     }
     if (a.start_h)
-        for (uint32_t v = threadIdx.x; v <= nb; v += kThreads) a.start_h[v] = P[v];
+        for (uint32_t v = tid; v <= nb; v += kThreads) a.start_h[v] = P[v];
 }
 
 // ------------------------------------------ node tables of deeper levels --
@@ -195,7 +251,7 @@ __global__ __launch_bounds__(kThreads) void k_top(TopArgs a) {
 //   start_{i+1}(2v) = start_i(v), start_{i+1}(2v+1) = start_i(v+1) - ones_i(v).
 
 __global__ __launch_bounds__(kThreads) void k_plan_reduce(PlanArgs a) {
-    __shared__ unsigned long long s_w[kThreads / 64];
+    __shared__ unsigned long long s_w[kWaves];
     const uint64_t b0 = (uint64_t)blockIdx.x * kScanChunk;
     unsigned long long sum = 0;
     for (uint64_t k = b0 + threadIdx.x; k < b0 + kScanChunk && k < a.nodes; k += kThreads) sum += a.ones[k];
@@ -204,24 +260,32 @@ __global__ __launch_bounds__(kThreads) void k_plan_reduce(PlanArgs a) {
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
-        for (int w = 0; w < kThreads / 64; w++) t += s_w[w];
+        for (int w = 0; w < kWaves; w++) t += s_w[w];
         a.partials[blockIdx.x] = t;
     }
 }
 
 __global__ __launch_bounds__(kThreads) void k_plan_partials(PlanArgs a, uint64_t nblocks) {
-    if (threadIdx.x == 0) {
-        unsigned long long acc = 0;
-        for (uint64_t b = 0; b < nblocks; b++) {
-            unsigned long long v = a.partials[b];
-            a.partials[b] = acc;
-            acc += v;
+    // nblocks <= kMaxScanBlocks: a few consecutive entries per thread
+    __shared__ unsigned long long s_w[kWaves];
+    const uint64_t per = ceil_div(nblocks, kThreads);
+    const uint64_t k0 = threadIdx.x * per;
+    unsigned long long sum = 0;
+    for (uint64_t q = 0; q < per; q++)
+        if (k0 + q < nblocks) sum += a.partials[k0 + q];
+    unsigned long long tot;
+    unsigned long long off = block_excl_scan64(sum, s_w, &tot);
+    for (uint64_t q = 0; q < per; q++) {
+        if (k0 + q < nblocks) {
+            const unsigned long long v = a.partials[k0 + q];
+            a.partials[k0 + q] = off;
+            off += v;
         }
     }
 }
 
 __global__ __launch_bounds__(kThreads) void k_plan_apply(PlanArgs a, int use_partials) {
-    __shared__ unsigned long long s_w[kThreads / 64];
+    __shared__ unsigned long long s_w[kWaves];
     const uint64_t b0 = (uint64_t)blockIdx.x * kScanChunk;
     const uint64_t per = kScanChunk / kThreads;  // 16 consecutive entries per thread
     const uint64_t k0 = b0 + threadIdx.x * per;
@@ -232,12 +296,8 @@ __global__ __launch_bounds__(kThreads) void k_plan_apply(PlanArgs a, int use_par
         loc[q] = (k0 + q < a.nodes) ? a.ones[k0 + q] : 0ull;
         tsum += loc[q];
     }
-    unsigned long long incl = wave_incl_scan64(tsum);
-    if ((threadIdx.x & 63) == 63) s_w[threadIdx.x >> 6] = incl;
-    __syncthreads();
-    unsigned long long off = use_partials ? a.partials[blockIdx.x] : 0ull;
-    for (int w = 0; w < (int)(threadIdx.x >> 6); w++) off += s_w[w];
-    unsigned long long o1 = off + incl - tsum;
+    unsigned long long tot;
+    unsigned long long o1 = block_excl_scan64(tsum, s_w, &tot) + (use_partials ? a.partials[blockIdx.x] : 0ull);
 #pragma unroll
     for (uint64_t q = 0; q < per; q++) {
         const uint64_t v = k0 + q;
@@ -255,129 +315,166 @@ __global__ __launch_bounds__(kThreads) void k_plan_apply(PlanArgs a, int use_par
     if (a.start_next && blockIdx.x == 0 && threadIdx.x == 0) a.start_next[2 * a.nodes] = a.n;
 }
 
-// ----------------------------------------------------------- level pass ---
+// ------------------------------------------------------ superchunk scan --
+// sup[c] = ones in all tiles before superchunk c (kSup tiles each).
+// Workgroup c sums its superchunk's tile counts; the last workgroup to finish
+// (counted on *done) turns the sums into exclusive prefixes in place.
 
-// Decoupled look-back over the tiles (taken in ticket order, so every
-// predecessor is resident or finished): returns the number of ones in all
-// tiles before tile t.  Executed by one full wave.
-__device__ __forceinline__ unsigned long long lookback(uint64_t *status, uint64_t t, uint32_t agg) {
-    const int lane = threadIdx.x & 63;
-    if (t == 0) {
-        if (lane == 0) st_rel(&status[0], kFlagPre | (uint64_t)agg);
-        return 0;
+__global__ __launch_bounds__(kThreads) void k_supsum(const uint32_t *tile_ones, unsigned long long *sup,
+                                                     uint32_t *done, uint64_t ntiles) {
+    __shared__ unsigned long long s_w[kWaves];
+    __shared__ uint32_t s_last;
+    const uint32_t tid = threadIdx.x;
+    const uint64_t t = (uint64_t)blockIdx.x * kSup + tid;
+    const uint32_t v = wave_sum32(t < ntiles ? tile_ones[t] : 0u);
+    if ((tid & 63) == 0) s_w[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long tot = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; w++) tot += s_w[w];
+        sup[blockIdx.x] = tot;
+        __threadfence();  // publish the sum before counting this workgroup done
+        s_last = (atomicAdd(done, 1u) == gridDim.x - 1) ? 1u : 0u;
     }
-    if (lane == 0) st_rel(&status[t], kFlagAgg | (uint64_t)agg);
-    unsigned long long excl = 0;
-    int64_t j = (int64_t)t - 1;
-    while (true) {
-        const int64_t idx = j - lane;
-        uint64_t s = kFlagPre;  // before tile 0: a prefix of zero
-        if (idx >= 0) {
-            do {
-                s = ld_acq(&status[idx]);
-            } while ((s >> 62) == 0);
-        }
-        const unsigned long long pm = __ballot((s >> 62) == 2);
-        if (pm) {
-            const int first = __builtin_ctzll(pm);
-            excl += wave_sum64(lane <= first ? (s & kValMask) : 0ull);
-            break;
-        }
-        excl += wave_sum64(s & kValMask);
-        j -= 64;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();  // see every other workgroup's sum
+    const uint64_t nsup = gridDim.x;
+    unsigned long long carry = 0;
+    for (uint64_t c0 = 0; c0 < nsup; c0 += kThreads) {
+        const uint64_t c = c0 + tid;
+        const unsigned long long x = (c < nsup) ? __hip_atomic_load(&sup[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+        unsigned long long tot;
+        const unsigned long long ex = block_excl_scan64(x, s_w, &tot);
+        if (c < nsup) sup[c] = carry + ex;
+        carry += tot;
     }
-    if (lane == 0) st_rel(&status[t], kFlagPre | (excl + agg));
-    return excl;
 }
 
+// ----------------------------------------------------------- level pass ---
+
+template <int E> struct MaskT { typedef uint32_t T; };
+template <> struct MaskT<64> { typedef uint64_t T; };
+
+// Orders this wave's LDS accesses (a wave's LDS operations execute in order).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Level bits (bit sh) of one lane's E symbols, symbol k at bit k.
+template <int W>
+__device__ __forceinline__ typename MaskT<64 / W>::T level_bits(const uint4 (&raw)[4], uint32_t sh) {
+    typedef typename MaskT<64 / W>::T M;
+    M mb = 0;
+    const uint32_t d[16] = {raw[0].x, raw[0].y, raw[0].z, raw[0].w, raw[1].x, raw[1].y, raw[1].z, raw[1].w,
+                            raw[2].x, raw[2].y, raw[2].z, raw[2].w, raw[3].x, raw[3].y, raw[3].z, raw[3].w};
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+        if (W == 1) {
+            // gather bit sh of the four bytes into a nibble (no carries: the
+            // sixteen partial products land on distinct bits)
+            const uint32_t nib = (((d[q] >> sh) & 0x01010101u) * 0x10204080u) >> 28;
+            mb |= (M)nib << (4 * q);
+        } else if (W == 2) {
+            const uint32_t two = ((d[q] >> sh) & 1u) | (((d[q] >> (16 + sh)) & 1u) << 1);
+            mb |= (M)two << (2 * q);
+        } else {
+            mb |= (M)((d[q] >> sh) & 1u) << q;
+        }
+    }
+    return mb;
+}
+
+// One level pass.  Every wave owns one tile of TILE consecutive positions of
+// T_i (each lane 64 bytes = E symbols); there is no workgroup barrier.
 template <int W>
 __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
     typedef typename ElemT<W>::T T;
-    constexpr int CH = 16 / W;  // symbols per 16-byte chunk
+    constexpr int E = 64 / W;                 // symbols per lane
+    constexpr int CH = 16 / W;                // symbols per 16-byte chunk
+    constexpr uint64_t TILE = tile_syms(W);   // 64 * E
+    typedef typename MaskT<E>::T M;
+    // per wave: staging of the split (zeros at [a0, a0+Z), ones at [a1, a1+O)
+    // with a1 + O <= TILE + 3*CH - 3), or, for tiles spanning several nodes,
+    // next-level counters per (node, bit, destination-tile parity)
+    constexpr uint32_t kStageBytes = (uint32_t)(TILE + 4 * CH) * W;
+    constexpr uint32_t kCntBytes = 2u * 4u * kNodeCap * 4u;
+    constexpr uint32_t kWaveBytes = (kStageBytes > kCntBytes ? kStageBytes : kCntBytes);
+    __shared__ __align__(16) uint8_t s_all[kWaves * kWaveBytes];
 
-    __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_vfirst, s_vlast;
-    __shared__ unsigned long long s_prefix;
-    __shared__ uint32_t s_wtot[kThreads / 64];
-    __shared__ uint32_t s_red[2][kThreads / 64];
-    __shared__ uint16_t s_m16[kThreads];
-    // zeros at [a0, a0+Z), ones at [a1, a1+O): a1 + O <= kTile + 3*CH - 3
-    __shared__ __align__(16) T s_stage[kTile + 4 * CH];
-    __shared__ uint32_t s_cnt[2 * kNodeCap];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t t = (uint64_t)blockIdx.x * kWaves + wv;
+    if (t >= a.ntiles) return;  // whole wave
+    T *s_stage = reinterpret_cast<T *>(s_all + wv * kWaveBytes);
+    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_all + wv * kWaveBytes);
+    uint32_t *s_tix = s_cnt + 4 * kNodeCap;
 
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
-    __syncthreads();
-    const uint64_t t = s_tile;
-    if (t >= a.ntiles) return;  // tickets are zeroed per build, so never taken
-    const uint64_t base = t * kTile;
-    const uint64_t pos0 = base + (uint64_t)tid * kEPT;
-    const uint64_t nvalid = (a.n - base < kTile) ? a.n - base : kTile;  // base < n
-
-    uint32_t x[16];
-    const int nval = load16<W>(a.tin, pos0, a.n, x);
     const uint32_t sh = a.levels - 1 - a.level;  // bit of this level
     const uint32_t nsh = a.levels - a.level;     // node shift (Proposition 1)
-    uint32_t mb = 0;
-#pragma unroll
-    for (int k = 0; k < 16; k++) {
-        x[k] &= a.symmask;  // keeps every node index in range even for bad input
-        mb |= ((x[k] >> sh) & 1u) << k;
-    }
+    const uint64_t base = t * TILE;
+    const uint64_t pos0 = base + (uint64_t)lane * E;
+    const uint64_t nvalid = (a.n - base < TILE) ? a.n - base : TILE;  // base < n
 
-    // node span of the tile (T_i is sorted by node)
-    if (tid == 0) s_vfirst = x[0] >> nsh;
+    uint4 raw[4];
+    const int nval = load64<W>(a.tin, pos0, a.n, raw);
+    // ones before the tile: superchunk prefix + earlier tiles of the superchunk
+    uint32_t pv = 0;
     {
-        const uint64_t last = nvalid - 1;
-        if ((uint64_t)tid == last / kEPT) {
-            const int kl = (int)(last % kEPT);
-            uint32_t xv = 0;
+        const uint64_t q = t - t % kSup + 4 * (uint64_t)lane;
 #pragma unroll
-            for (int k = 0; k < 16; k++) xv = (k == kl) ? x[k] : xv;
-            s_vlast = xv >> nsh;
+        for (int d = 0; d < 4; d++)
+            if (q + d < t) pv += a.tile_ones[q + d];
+    }
+    unsigned long long prefix = a.sup[t / kSup];
+
+    const M mb = level_bits<W>(raw, sh);
+    const uint32_t pc = (E == 64) ? (uint32_t)__popcll((uint64_t)mb) : (uint32_t)__popc((uint32_t)mb);
+    const uint32_t incl = wave_incl_scan(pc);
+    const uint32_t agg = __shfl(incl, 63, 64);
+    prefix += wave_sum32(pv);
+    const uint32_t lr1 = incl - pc;  // ones in the tile before this lane
+    const unsigned long long r_lane = prefix + lr1;
+
+    // bitmap words: 64 / E consecutive lanes form one word
+    {
+        uint64_t wd = (uint64_t)mb;
+#pragma unroll
+        for (int d = 1; d < 64 / E; d++) wd |= (uint64_t)__shfl_down((uint32_t)mb, d, 64) << (d * E);
+        if ((lane % (64 / E)) == 0) {
+            const uint64_t widx = pos0 / 64;
+            if (widx < a.words) a.bits[widx] = wd;
         }
     }
-
-    s_m16[tid] = (uint16_t)mb;
-    const uint32_t pc = __popc(mb);
-    const uint32_t incl = wave_incl_scan(pc);
-    if (lane == 63) s_wtot[wv] = incl;
-    __syncthreads();
-
-    uint32_t agg = 0;
-#pragma unroll
-    for (int w = 0; w < kThreads / 64; w++) agg += s_wtot[w];
-
-    if (wv == 0) {
-        // bitmap words: word q of the tile = 4 threads x 16 bits
-        const uint64_t wd = (uint64_t)s_m16[4 * lane] | ((uint64_t)s_m16[4 * lane + 1] << 16) |
-                            ((uint64_t)s_m16[4 * lane + 2] << 32) | ((uint64_t)s_m16[4 * lane + 3] << 48);
-        const uint64_t widx = base / 64 + lane;
-        if (widx < a.words) a.bits[widx] = wd;
-        const unsigned long long ex = lookback(a.status, t, agg);
-        if (lane == 0) s_prefix = ex;
-    }
-    __syncthreads();
-    const unsigned long long prefix = s_prefix;
-    uint32_t wex = 0;
-    for (int w = 0; w < wv; w++) wex += s_wtot[w];
-    const uint32_t lr1_thread = wex + incl - pc;  // ones in the tile before this thread
-    const unsigned long long r_thread = prefix + lr1_thread;
-
-    // rank directory: entry k = ones before position 512k (every 32nd thread)
-    if ((tid & 31) == 0) {
+    // rank directory: entry k = ones before position 512k
+    if ((pos0 & 511) == 0) {
         const uint64_t k = pos0 >> 9;
-        if (k < a.rank_stride) a.ranks[k] = (k < a.rank_entries) ? r_thread : 0ull;
+        if (k < a.rank_stride) a.ranks[k] = (k < a.rank_entries) ? r_lane : 0ull;
     }
-    if (t == a.ntiles - 1 && tid < 8) {  // entries past the last tile
-        const uint64_t k = (base + kTile) / 512 + tid;
+    if (t == a.ntiles - 1 && lane < 8) {  // entries past the last tile
+        const uint64_t k = (base + TILE) / 512 + lane;
         if (k < a.rank_stride) a.ranks[k] = (k < a.rank_entries) ? prefix + agg : 0ull;
     }
 
     if (a.tout == nullptr) return;  // last level: no next order, no counts
 
+    // node span of the tile (T_i is sorted by node)
+    const uint32_t vf = __shfl((raw_elem<W>(raw, 0) & a.symmask) >> nsh, 0, 64);
+    uint32_t vl;
+    {
+        const uint64_t last = nvalid - 1;
+        const int kl = (int)(last % E);
+        uint32_t xv = 0;
+#pragma unroll
+        for (int k = 0; k < E; k++) xv = (k == kl) ? raw_elem<W>(raw, k) : xv;
+        vl = __shfl((xv & a.symmask) >> nsh, (int)(last / E), 64);
+    }
+
     T *tout = reinterpret_cast<T *>(a.tout);
-    const uint32_t vf = s_vfirst, vl = s_vlast;
+    const bool counting = a.tile_ones_next != nullptr;
+    const uint32_t sh2 = sh - 1;  // bit of the next level (when counting)
     if (vf == vl) {
         // Single node: zeros keep their order at g0.., ones at g1...
         const ulonglong2 zo = a.zo[vf];
@@ -387,86 +484,119 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
         const uint32_t a0 = (uint32_t)(g0 % CH);
         const uint32_t r1 = (uint32_t)round_up(a0 + Z, CH);
         const uint32_t a1 = r1 + (uint32_t)(g1 % CH);
+        uint32_t zc = a0 + (uint32_t)lane * E - lr1;  // next zero slot of this lane
+        uint32_t oc = a1 + lr1;                       // next one slot of this lane
 #pragma unroll
-        for (int k = 0; k < 16; k++) {
+        for (int k = 0; k < E; k++) {
             if (k < nval) {
-                const uint32_t lr1 = lr1_thread + __popc(mb & ((1u << k) - 1u));
-                const uint32_t lidx = (uint32_t)tid * kEPT + k;
-                if ((mb >> k) & 1u) s_stage[a1 + lr1] = (T)x[k];
-                else s_stage[a0 + (lidx - lr1)] = (T)x[k];
+                const uint32_t b = (uint32_t)(mb >> k) & 1u;
+                s_stage[b ? oc : zc] = (T)(raw_elem<W>(raw, k) & a.symmask);
+                oc += b;
+                zc += 1u - b;
             }
         }
-        __syncthreads();
+        wave_sync();
+        // next-level ones per (run, destination-tile parity): a run holds at
+        // most TILE symbols, so it touches at most two consecutive tiles
+        uint32_t c4[4] = {0u, 0u, 0u, 0u};
+        uint32_t d4[4] = {0u, 0u, 0u, 0u};
         const uint32_t nch = (a1 + (uint32_t)O + CH - 1) / CH;
-        for (uint32_t c = tid; c < nch; c += kThreads) {
+        for (uint32_t c = lane; c < nch; c += 64) {
             const uint32_t s = c * CH;
-            uint64_t gb;
-            uint32_t lo, hi;
-            if (s < r1) { gb = g0 - a0; lo = a0; hi = a0 + (uint32_t)Z; }
-            else        { gb = g1 - a1; lo = a1; hi = a1 + (uint32_t)O; }
+            const uint32_t region = s < r1 ? 0u : 1u;
+            const uint64_t gb = region ? g1 - a1 : g0 - a0;
+            const uint32_t lo = region ? a1 : a0;
+            const uint32_t hi = region ? a1 + (uint32_t)O : a0 + (uint32_t)Z;
+            const uint4 v = *reinterpret_cast<const uint4 *>(&s_stage[s]);
             // (destinations beyond n only arise from inconsistent tables; they
             // are dropped rather than written)
             if (s >= lo && s + CH <= hi && gb + s + CH <= a.n) {
-                *reinterpret_cast<uint4 *>(tout + (gb + s)) = *reinterpret_cast<const uint4 *>(&s_stage[s]);
+                *reinterpret_cast<uint4 *>(tout + (gb + s)) = v;
             } else {
 #pragma unroll
                 for (int e = 0; e < CH; e++)
-                    if (s + e >= lo && s + e < hi && gb + s + e < a.n) tout[gb + s + e] = s_stage[s + e];
+                    if (s + e >= lo && s + e < hi && gb + s + e < a.n) tout[gb + s + e] = (T)chunk_elem<W>(v, e);
+            }
+            if (counting) {
+                uint32_t ones = 0;
+#pragma unroll
+                for (int e = 0; e < CH; e++)
+                    ones += (s + e >= lo && s + e < hi) ? ((chunk_elem<W>(v, e) >> sh2) & 1u) : 0u;
+                if (ones) {
+                    const uint64_t dt = (gb + s) / TILE;  // 16-byte chunks never straddle tiles
+                    const uint32_t key = region * 2 + (uint32_t)(dt & 1);
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        if (q == (int)key) { c4[q] += ones; d4[q] = (uint32_t)dt; }
+                    }
+                }
             }
         }
-    } else {
-        // Several nodes: every symbol goes straight to its destination.
+        if (!counting) return;
 #pragma unroll
-        for (int k = 0; k < 16; k++) {
-            if (k < nval) {
-                const uint32_t v = x[k] >> nsh;
-                const ulonglong2 zo = a.zo[v];
-                const unsigned long long r1 = r_thread + __popc(mb & ((1u << k) - 1u));
-                const uint64_t p = pos0 + k;
-                const uint64_t dst = ((mb >> k) & 1u) ? zo.y + r1 : p - r1 + zo.x;
-                if (dst < a.n) tout[dst] = (T)x[k];
+        for (int q = 0; q < 4; q++) {
+            const uint32_t tot = wave_sum32(c4[q]);
+            if (tot) {
+                const unsigned long long m = __ballot(c4[q] != 0);
+                const uint32_t dt = __shfl(d4[q], __builtin_ctzll(m), 64);
+                if (lane == 0) {
+                    atomicAdd(&a.tile_ones_next[dt], tot);
+                    if (a.ones_next) atomicAdd(&a.ones_next[2ull * vf + (q >> 1)], (unsigned long long)tot);
+                }
+            }
+        }
+        return;
+    }
+
+    // Several nodes: every symbol goes straight to its destination.
+    const bool lds_counts = counting && (vl - vf < kNodeCap);
+    if (lds_counts) {
+        for (uint32_t q = lane; q < 4 * (vl - vf + 1); q += 64) s_cnt[q] = 0;
+        wave_sync();
+    }
+    unsigned long long r1 = r_lane;
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+        if (k < nval) {
+            const uint32_t x = raw_elem<W>(raw, k) & a.symmask;
+            const uint32_t v = x >> nsh;
+            const ulonglong2 zo = a.zo[v];
+            const uint64_t p = pos0 + k;
+            const uint32_t b = (uint32_t)(mb >> k) & 1u;
+            const uint64_t dst = b ? zo.y + r1 : p - r1 + zo.x;
+            r1 += b;
+            if (dst < a.n) {
+                tout[dst] = (T)x;
+                if (counting && ((x >> sh2) & 1u)) {
+                    const uint64_t dt = dst / TILE;
+                    if (lds_counts && v - vf <= vl - vf) {
+                        const uint32_t key = 4 * (v - vf) + 2 * b + (uint32_t)(dt & 1);
+                        atomicAdd(&s_cnt[key], 1u);
+                        s_tix[key] = (uint32_t)dt;
+                    } else {
+                        atomicAdd(&a.tile_ones_next[dt], 1u);
+                        if (a.ones_next) atomicAdd(&a.ones_next[2ull * v + b], 1ull);
+                    }
+                }
             }
         }
     }
-
-    if (a.ones_next == nullptr) return;
-
-    // Ones of the next level, per next-level node 2v + bit.
-    const uint32_t sh2 = sh - 1;
-    uint32_t mb2 = 0;
-#pragma unroll
-    for (int k = 0; k < 16; k++) mb2 |= ((x[k] >> sh2) & 1u) << k;  // invalid symbols are 0
-    if (vf == vl) {
-        uint32_t c0 = wave_sum32(__popc(~mb & mb2 & 0xffffu));
-        uint32_t c1 = wave_sum32(__popc(mb & mb2));
-        if (lane == 0) { s_red[0][wv] = c0; s_red[1][wv] = c1; }
-        __syncthreads();
-        if (tid == 0) {
-            uint32_t t0 = 0, t1 = 0;
-            for (int w = 0; w < kThreads / 64; w++) { t0 += s_red[0][w]; t1 += s_red[1][w]; }
-            if (t0) atomicAdd(&a.ones_next[2ull * vf], (unsigned long long)t0);
-            if (t1) atomicAdd(&a.ones_next[2ull * vf + 1], (unsigned long long)t1);
+    if (lds_counts) {
+        wave_sync();
+        for (uint32_t q = lane; q < 4 * (vl - vf + 1); q += 64) {
+            const uint32_t c = s_cnt[q];
+            if (c) {
+                const uint32_t dt = s_tix[q];
+                atomicAdd(&a.tile_ones_next[dt], c);
+                if (a.ones_next) atomicAdd(&a.ones_next[2ull * (vf + q / 4) + ((q >> 1) & 1u)], (unsigned long long)c);
+            }
         }
-    } else if (vl - vf < kNodeCap) {
-        const uint32_t nc = 2 * (vl - vf + 1);
-        for (uint32_t q = tid; q < nc; q += kThreads) s_cnt[q] = 0;
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 16; k++)
-            if (k < nval && ((mb2 >> k) & 1u) && (x[k] >> nsh) - vf <= vl - vf)
-                atomicAdd(&s_cnt[2 * ((x[k] >> nsh) - vf) + ((mb >> k) & 1u)], 1u);
-        __syncthreads();
-        for (uint32_t q = tid; q < nc; q += kThreads)
-            if (s_cnt[q]) atomicAdd(&a.ones_next[2ull * vf + q], (unsigned long long)s_cnt[q]);
-    } else {
-#pragma unroll
-        for (int k = 0; k < 16; k++)
-            if (k < nval && ((mb2 >> k) & 1u))
-                atomicAdd(&a.ones_next[2ull * (x[k] >> nsh) + ((mb >> k) & 1u)], 1ull);
     }
 }
 
 }  // namespace
+
+
 
 // ------------------------------------------------------------- launchers --
 
@@ -486,11 +616,11 @@ hipError_t launch_zero(void *p, uint64_t bytes, uint32_t *tree_status, uint64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_hist(const HistArgs &a, uint32_t width, uint64_t ntiles, hipStream_t s) {
-    const uint32_t g = grid_for(ntiles, 1, 2048);
-    if (width == 1) hipLaunchKernelGGL(k_hist<1>, dim3(g), dim3(kThreads), 0, s, a);
-    else if (width == 2) hipLaunchKernelGGL(k_hist<2>, dim3(g), dim3(kThreads), 0, s, a);
-    else hipLaunchKernelGGL(k_hist<4>, dim3(g), dim3(kThreads), 0, s, a);
+hipError_t launch_ingest(const IngestArgs &a, uint32_t width, hipStream_t s) {
+    const uint32_t g = (uint32_t)ceil_div(a.ntiles, a.tiles_per_block);
+    if (width == 1) hipLaunchKernelGGL(k_ingest<1>, dim3(g), dim3(kThreads), 0, s, a);
+    else if (width == 2) hipLaunchKernelGGL(k_ingest<2>, dim3(g), dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL(k_ingest<4>, dim3(g), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -509,8 +639,15 @@ hipError_t launch_plan(const PlanArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_supsum(const uint32_t *tile_ones, unsigned long long *sup, uint32_t *done, uint64_t ntiles,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_supsum, dim3((uint32_t)ceil_div(ntiles, kSup)), dim3(kThreads), 0, s, tile_ones, sup, done,
+                       ntiles);
+    return hipGetLastError();
+}
+
 hipError_t launch_level(const LevelArgs &a, uint32_t width, hipStream_t s) {
-    const dim3 g((uint32_t)a.ntiles);
+    const dim3 g((uint32_t)ceil_div(a.ntiles, kWaves));
     if (width == 1) hipLaunchKernelGGL(k_level<1>, g, dim3(kThreads), 0, s, a);
     else if (width == 2) hipLaunchKernelGGL(k_level<2>, g, dim3(kThreads), 0, s, a);
     else hipLaunchKernelGGL(k_level<4>, g, dim3(kThreads), 0, s, a);

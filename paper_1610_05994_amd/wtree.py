@@ -24,7 +24,7 @@ WT_MAX_SIGMA = 1 << 24
 EXPORTED = [
     "wt_footprint", "wt_build", "wt_batch_footprint", "wt_build_batch", "wt_tree_status",
     "wt_free", "wt_levels", "wt_access_batch", "wt_rank_batch", "wt_select_batch",
-    "wt_access", "wt_rank", "wt_select", "wt_strerror",
+    "wt_access", "wt_rank", "wt_select", "wt_strerror", "wt_prof_enable", "wt_prof_read",
 ]
 
 
@@ -36,6 +36,11 @@ class WtError(RuntimeError):
 
 class wt_desc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("sigma", ctypes.c_uint32), ("width", ctypes.c_uint32)]
+
+
+class wt_prof_rec(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_char * 32), ("level", ctypes.c_uint32), ("width", ctypes.c_uint32),
+                ("n", ctypes.c_uint64), ("bytes", ctypes.c_uint64), ("ms", ctypes.c_float)]
 
 
 _lib = None
@@ -66,6 +71,8 @@ def lib():
         "wt_rank": ([vp, u32, u64, P(u64)], i32),
         "wt_select": ([vp, u32, u64, P(u64)], i32),
         "wt_strerror": ([i32], ctypes.c_char_p),
+        "wt_prof_enable": ([i32], i32),
+        "wt_prof_read": ([P(wt_prof_rec), u64, P(u64)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -159,6 +166,24 @@ def wt_select(h: int, c: int, j: int):
     p = ctypes.c_uint64()
     rc = lib().wt_select(h, c, j, ctypes.byref(p))
     return rc, p.value
+
+
+def wt_prof_enable(on: bool) -> int:
+    return lib().wt_prof_enable(1 if on else 0)
+
+
+def wt_prof_read():
+    """Waits for the recorded events; returns a list of per-launch dicts."""
+    cnt = ctypes.c_uint64()
+    rc = lib().wt_prof_read(None, 0, ctypes.byref(cnt))
+    if rc != WT_OK:
+        raise WtError(rc, "wt_prof_read")
+    arr = (wt_prof_rec * max(1, cnt.value))()
+    rc = lib().wt_prof_read(arr, cnt.value, ctypes.byref(cnt))
+    if rc != WT_OK:
+        raise WtError(rc, "wt_prof_read")
+    return [dict(kernel=r.kernel.decode(), level=r.level, width=r.width, n=r.n, bytes=r.bytes, ms=r.ms)
+            for r in arr[: cnt.value]]
 
 
 # ------------------------------------------------- torch-backed helpers ---
