@@ -90,6 +90,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-lg", type=int, default=26)
     ap.add_argument("--cpu-runs", type=int, default=3)
+    ap.add_argument("--input-cache", default="",
+                    help="directory to keep the generated input between runs (.npy)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -106,7 +108,17 @@ def main() -> int:
 
     dev = torch.device("cuda:0")
     print("bench: generating workload %s" % args.workload, file=sys.stderr, flush=True)
-    S, sigma = wtgen.workload(args.workload)
+    S, sigma = None, None
+    if args.input_cache:
+        path = os.path.join(args.input_cache, "%s.npy" % args.workload)
+        if os.path.exists(path):
+            S = np.load(path)
+            sigma = {"c1": 256, "c2": 256, "c3": 1 << 20}[args.workload]
+    if S is None:
+        S, sigma = wtgen.workload(args.workload)
+        if args.input_cache:
+            os.makedirs(args.input_cache, exist_ok=True)
+            np.save(os.path.join(args.input_cache, "%s.npy" % args.workload), S)
     n, width = S.shape[0], S.dtype.itemsize
     dS = wtree.to_device(S, dev)
     rc, tb, wb = wtree.wt_footprint(n, sigma, width)

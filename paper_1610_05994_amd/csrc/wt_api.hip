@@ -74,16 +74,15 @@ static void prof_end(long idx, hipStream_t st) {
 void make_layout(uint64_t n, uint32_t sigma, uint32_t width, Layout *L) {
     memset(L, 0, sizeof(*L));
     const uint32_t l = levels_for(sigma);
-    const uint32_t h = l < kTopBits ? l : kTopBits;
     L->n = n;
     L->sigma = sigma;
     L->width = width;
     L->levels = l;
-    L->top_bits = h;
     L->words = round_up(ceil_div(n, 64), 8);
     L->rank_entries = ceil_div(n, 512) + 1;
     L->rank_stride = round_up(L->rank_entries, 8);
     L->ntiles = ceil_div(n, tile_syms(width));
+    L->nsup = ceil_div(L->ntiles, kSup);
 
     L->tree_bits_off = kHeaderBytes;
     L->tree_ranks_off = L->tree_bits_off + (uint64_t)l * L->words * 8;
@@ -96,29 +95,26 @@ void make_layout(uint64_t n, uint32_t sigma, uint32_t width, Layout *L) {
     L->ws_tb = off;
     if (l >= 3) off += tbytes;
 
-    L->nsup = ceil_div(L->ntiles, kSup);
     L->ws_ctrl = off;
     L->ws_tile_ones = off;
     off += round_up((uint64_t)l * L->ntiles * 4, 256);
-    L->ws_done = off;
-    off += round_up((uint64_t)(l ? l : 1) * 4, 256);
-    L->ws_hist = off;
-    off += round_up((1ull << h) * 8, 256);
     L->ws_ones = off;
     uint64_t e = 0;
-    for (uint32_t i = h; i < l; i++) { L->ones_off[i] = e; e += 1ull << i; }
+    for (uint32_t i = 0; i < l; i++) { L->ones_off[i] = e; e += level_slots(i) << i; }
     off += round_up(e * 8, 256);
     L->ws_ctrl_bytes = off - L->ws_ctrl;
 
     L->ws_sup = off;
     off += round_up((uint64_t)l * L->nsup * 8, 256);
+    L->ws_supsum = off;
+    off += round_up((L->nsup ? L->nsup : 1) * 8, 256);
     L->ws_zo = off;
     e = 0;
     for (uint32_t i = 0; i < l; i++) { L->zo_off[i] = e; e += 1ull << i; }
     off += round_up(e * 16, 256);
     L->ws_start = off;
     e = 0;
-    for (uint32_t i = h; i < l; i++) { L->start_off[i] = e; e += (1ull << i) + 1; }
+    for (uint32_t i = 0; i < l; i++) { L->start_off[i] = e; e += (1ull << i) + 1; }
     off += round_up(e * 8, 256);
     L->ws_partials = off;
     off += round_up(kMaxScanBlocks * 8, 256);
@@ -128,15 +124,14 @@ void make_layout(uint64_t n, uint32_t sigma, uint32_t width, Layout *L) {
 // Enqueue every kernel of one build.  Arguments are already validated.
 static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, uint8_t *work,
                                 hipStream_t st) {
-    const uint32_t l = L.levels, h = L.top_bits;
+    const uint32_t l = L.levels;
     uint32_t *tree_status = reinterpret_cast<uint32_t *>(tree);
     uint64_t *bits = reinterpret_cast<uint64_t *>(tree + L.tree_bits_off);
     uint64_t *ranks = reinterpret_cast<uint64_t *>(tree + L.tree_ranks_off);
     uint32_t *tile_ones = reinterpret_cast<uint32_t *>(work + L.ws_tile_ones);
-    unsigned long long *hist = reinterpret_cast<unsigned long long *>(work + L.ws_hist);
+    unsigned long long *supsum = reinterpret_cast<unsigned long long *>(work + L.ws_supsum);
     unsigned long long *ones = reinterpret_cast<unsigned long long *>(work + L.ws_ones);
     unsigned long long *sup = reinterpret_cast<unsigned long long *>(work + L.ws_sup);
-    uint32_t *done = reinterpret_cast<uint32_t *>(work + L.ws_done);
     ulonglong2 *zo = reinterpret_cast<ulonglong2 *>(work + L.ws_zo);
     uint64_t *start = reinterpret_cast<uint64_t *>(work + L.ws_start);
     uint64_t *partials = reinterpret_cast<uint64_t *>(work + L.ws_partials);
@@ -149,22 +144,20 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
 
     IngestArgs ia;
     ia.S = S;
-    ia.hist = hist;
     ia.tile_ones0 = l ? tile_ones : nullptr;
+    ia.ones0 = ones;
+    ia.start0 = l ? start : nullptr;
     ia.tree_status = tree_status;
     ia.n = L.n;
     ia.ntiles = L.ntiles;
+    ia.slots0 = level_slots(0);
     ia.sigma = L.sigma;
-    ia.symmask = l ? (uint32_t)((1ull << l) - 1) : 0u;
-    ia.hshift = l - h;
-    ia.nbins = 1u << h;
-    ia.copies = (kHistWords >> h) < 64 ? (kHistWords >> h) : 64;
+    ia.check = (L.width < 4 && (uint64_t)L.sigma == (1ull << (8 * L.width))) ? 0u : 1u;
     ia.msb = l ? l - 1 : 0;
     {
-        // contiguous tiles per ingest workgroup: ~2048 workgroups, a multiple
-        // of kWaves dividing kSup, so a workgroup stays inside one superchunk
+        // contiguous tiles per ingest workgroup: ~2048 workgroups
         uint64_t k = kWaves;
-        while (k < kSup && L.ntiles > 2048 * k) k <<= 1;
+        while (L.ntiles > 2048 * k) k <<= 1;
         ia.tiles_per_block = k;
     }
     pr = prof_begin(st, "ingest", 0, L.width, L.n, L.n * L.width);
@@ -173,40 +166,37 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
     if (err != hipSuccess) return err;
     if (l == 0) return hipSuccess;
 
-    TopArgs ta;
-    ta.hist = hist;
-    ta.zo = zo;
-    ta.start_h = h < l ? start + L.start_off[h] : nullptr;
-    ta.n = L.n;
-    ta.h = h;
-    ta.levels = l;
-    for (uint32_t i = 0; i < 32; i++) ta.zo_off[i] = L.zo_off[i];
-    pr = prof_begin(st, "top", 0, L.width, L.n, 0);
-    err = launch_top(ta, st);
-    prof_end(pr, st);
-    if (err != hipSuccess) return err;
-
     uint8_t *tbuf[2] = {work + L.ws_ta, work + L.ws_tb};
     for (uint32_t i = 0; i < l; i++) {
-        if (i >= h) {
-            PlanArgs pa;
-            pa.start = start + L.start_off[i];
-            pa.ones = ones + L.ones_off[i];
-            pa.zo = zo + L.zo_off[i];
-            pa.start_next = (i + 1 < l) ? start + L.start_off[i + 1] : nullptr;
-            pa.partials = partials;
-            pa.nodes = 1ull << i;
-            pa.n = L.n;
-            pr = prof_begin(st, "plan", i, L.width, L.n, (1ull << i) * (8 + 16 + 8 + 16));
+        PlanArgs pa;
+        pa.start = start + L.start_off[i];
+        pa.ones = ones + L.ones_off[i];
+        pa.zo = zo + L.zo_off[i];
+        pa.start_next = (i + 1 < l) ? start + L.start_off[i + 1] : nullptr;
+        pa.partials = partials;
+        pa.nodes = 1ull << i;
+        pa.slots = level_slots(i);
+        pa.n = L.n;
+        const bool big = pa.nodes > kScanChunk;  // one counter slot there
+        if (big) {
+            pr = prof_begin(st, "plan", i, L.width, L.n, pa.nodes * (8 + 16 + 8 + 16));
             err = launch_plan(pa, st);
             prof_end(pr, st);
             if (err != hipSuccess) return err;
         }
-        unsigned long long *sup_i = sup + (uint64_t)i * L.nsup;
-        pr = prof_begin(st, "supsum", i, L.width, L.n, L.ntiles * 4 + L.nsup * 16);
-        err = launch_supsum(tile_ones + (uint64_t)i * L.ntiles, sup_i, done + i, L.ntiles, st);
+        PrepArgs pp;
+        pp.tile_ones = tile_ones + (uint64_t)i * L.ntiles;
+        pp.supsum = supsum;
+        pp.sup = sup + (uint64_t)i * L.nsup;
+        pp.ntiles = L.ntiles;
+        pp.nsup = L.nsup;
+        pp.plan = pa;
+        pp.plan_here = big ? 0u : 1u;
+        pr = prof_begin(st, "prep", i, L.width, L.n, L.ntiles * 4 + L.nsup * 16);
+        err = launch_prep(pp, st);
         prof_end(pr, st);
         if (err != hipSuccess) return err;
+
         LevelArgs a;
         a.tin = (i == 0) ? S : tbuf[(i - 1) & 1];  // T_i for i >= 1 alternates ta, tb
         a.tout = (i + 1 < l) ? tbuf[i & 1] : nullptr;
@@ -214,9 +204,11 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         a.ranks = ranks + (uint64_t)i * L.rank_stride;
         a.zo = zo + L.zo_off[i];
         a.tile_ones = tile_ones + (uint64_t)i * L.ntiles;
-        a.sup = sup_i;
+        a.sup = sup + (uint64_t)i * L.nsup;
         a.tile_ones_next = (i + 1 < l) ? tile_ones + (uint64_t)(i + 1) * L.ntiles : nullptr;
-        a.ones_next = (i + 1 >= h && i + 1 < l) ? ones + L.ones_off[i + 1] : nullptr;
+        a.ones_next = (i + 1 < l) ? ones + L.ones_off[i + 1] : nullptr;
+        a.nodes_next = 2ull << i;
+        a.slots_next = level_slots(i + 1);
         a.n = L.n;
         a.words = L.words;
         a.rank_entries = L.rank_entries;

@@ -29,8 +29,9 @@
 //       bit 0 at p  ->  p - rank1(p) + O1(v)
 //       bit 1 at p  ->  start_{i+1}(2v+1) - O1(v) + rank1(p)
 //     staged in LDS so that the global stores are aligned 16-byte chunks,
-//   * the ones of level i+1 per destination tile, and, for levels beyond
-//     the ingest histogram, per level-(i+1) node.
+//   * the ones of level i+1 per destination tile and per level-(i+1) node
+//     (the node sizes of the next level: Algorithm pwt's counting step,
+//     done for level i+1 while level i is split).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -151,208 +152,9 @@ __global__ void k_zero(uint64_t *p, uint64_t words, uint32_t *tree_status, uint6
 }
 
 // ---------------------------------------------------------------- ingest --
-// Reads S once: flags symbols >= sigma, counts the top min(l, kTopBits) bits
-// of every symbol (the node counts of the first levels: Algorithm pwt's
-// counting step, hoisted out of the level loop) and the ones of level 0 (the
-// most significant bit) in every tile.  Each bin lives in a.copies LDS
-// copies picked by lane, so the hot bins of skewed data do not serialise.
-
-template <int W>
-__global__ __launch_bounds__(kThreads) void k_ingest(IngestArgs a) {
-    constexpr int E = 64 / W;
-    constexpr uint64_t TILE = tile_syms(W);
-    __shared__ uint32_t s_h[kHistWords];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const uint32_t copy = (uint32_t)lane % a.copies;
-    for (uint32_t b = tid; b < a.nbins * a.copies; b += kThreads) s_h[b] = 0;
-    __syncthreads();
-    // this workgroup's tiles: [t0, t1), all inside one superchunk; wave wv
-    // takes every kWaves-th of them
-    const uint64_t t0 = (uint64_t)blockIdx.x * a.tiles_per_block;
-    const uint64_t t1 = (t0 + a.tiles_per_block < a.ntiles) ? t0 + a.tiles_per_block : a.ntiles;
-    bool bad = false;
-    uint64_t t = t0 + wv;
-    uint4 raw[4], nxt[4];
-    int nval = (t < t1) ? load64<W>(a.S, t * TILE + (uint64_t)lane * E, a.n, raw) : 0;
-    for (; t < t1; t += kWaves) {
-        int nval_n = 0;
-        if (t + kWaves < t1) nval_n = load64<W>(a.S, (t + kWaves) * TILE + (uint64_t)lane * E, a.n, nxt);
-        uint32_t ones = 0;
-#pragma unroll
-        for (int k = 0; k < E; k++) {
-            if (k < nval) {
-                const uint32_t x = raw_elem<W>(raw, k);
-                bad |= x >= a.sigma;
-                const uint32_t xm = x & a.symmask;
-                atomicAdd(&s_h[(xm >> a.hshift) * a.copies + copy], 1u);
-                ones += (xm >> a.msb) & 1u;
-            }
-        }
-        if (a.tile_ones0) {
-            ones = wave_sum32(ones);
-            if (lane == 0) a.tile_ones0[t] = ones;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; q++) raw[q] = nxt[q];
-        nval = nval_n;
-    }
-    if (__any(bad) && lane == 0) atomicOr(a.tree_status, 1u);
-    __syncthreads();
-    for (uint32_t b = tid; b < a.nbins; b += kThreads) {
-        uint32_t c = 0;
-        for (uint32_t q = 0; q < a.copies; q++) c += s_h[b * a.copies + q];
-        if (c) atomicAdd(&a.hist[b], (unsigned long long)c);
-    }
-}
-
-// ----------------------------------------- node tables of the top levels --
-// From the histogram H of the top h bits (P = exclusive prefix sum of H):
-//   node v of level i < h starts at P[v << (h-i)],
-//   its ones are the symbols of prefix 2v+1 at level i+1,
-//   O1(v) = ones of the nodes before v,
-//   zo(v) = (O1(v), start of node 2v+1 at level i+1 - O1(v)).
-
-__global__ __launch_bounds__(kThreads) void k_top(TopArgs a) {
-    __shared__ unsigned long long P[(1u << kTopBits) + 1];
-    __shared__ unsigned long long s_w[kWaves];
-    const uint32_t nb = 1u << a.h;
-    const uint32_t tid = threadIdx.x;
-    unsigned long long carry = 0;
-    for (uint32_t b0 = 0; b0 < nb; b0 += kThreads) {
-        unsigned long long tot;
-        const uint32_t b = b0 + tid;
-        const unsigned long long ex = block_excl_scan64(b < nb ? a.hist[b] : 0ull, s_w, &tot);
-        if (b < nb) P[b] = carry + ex;
-        carry += tot;
-    }
-    if (tid == 0) P[nb] = carry;
-    __syncthreads();
-    for (uint32_t i = 0; i < a.h; i++) {
-        const uint32_t s = a.h - i - 1;  // prefix length i+1 -> shift into H's bins
-        unsigned long long o1c = 0;
-        for (uint32_t v0 = 0; v0 < (1u << i); v0 += kThreads) {
-            const uint32_t v = v0 + tid;
-            const bool live = v < (1u << i);
-            const unsigned long long ones = live ? P[(2 * v + 2) << s] - P[(2 * v + 1) << s] : 0ull;
-            unsigned long long t2;
-            const unsigned long long o1 = o1c + block_excl_scan64(ones, s_w, &t2);
-            if (live) a.zo[a.zo_off[i] + v] = make_ulonglong2(o1, P[(2 * v + 1) << s] - o1);
-            o1c += t2;
-        }
-    }
-    if (a.start_h)
-        for (uint32_t v = tid; v <= nb; v += kThreads) a.start_h[v] = P[v];
-}
-
-// ------------------------------------------ node tables of deeper levels --
-// For level i with node starts start_i and ones counts ones_i:
-//   O1 = exclusive scan of ones_i,
-//   zo_i(v) = (O1(v), start_i(v+1) - ones_i(v) - O1(v)),
-//   start_{i+1}(2v) = start_i(v), start_{i+1}(2v+1) = start_i(v+1) - ones_i(v).
-
-__global__ __launch_bounds__(kThreads) void k_plan_reduce(PlanArgs a) {
-    __shared__ unsigned long long s_w[kWaves];
-    const uint64_t b0 = (uint64_t)blockIdx.x * kScanChunk;
-    unsigned long long sum = 0;
-    for (uint64_t k = b0 + threadIdx.x; k < b0 + kScanChunk && k < a.nodes; k += kThreads) sum += a.ones[k];
-    sum = wave_sum64(sum);
-    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = sum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int w = 0; w < kWaves; w++) t += s_w[w];
-        a.partials[blockIdx.x] = t;
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void k_plan_partials(PlanArgs a, uint64_t nblocks) {
-    // nblocks <= kMaxScanBlocks: a few consecutive entries per thread
-    __shared__ unsigned long long s_w[kWaves];
-    const uint64_t per = ceil_div(nblocks, kThreads);
-    const uint64_t k0 = threadIdx.x * per;
-    unsigned long long sum = 0;
-    for (uint64_t q = 0; q < per; q++)
-        if (k0 + q < nblocks) sum += a.partials[k0 + q];
-    unsigned long long tot;
-    unsigned long long off = block_excl_scan64(sum, s_w, &tot);
-    for (uint64_t q = 0; q < per; q++) {
-        if (k0 + q < nblocks) {
-            const unsigned long long v = a.partials[k0 + q];
-            a.partials[k0 + q] = off;
-            off += v;
-        }
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void k_plan_apply(PlanArgs a, int use_partials) {
-    __shared__ unsigned long long s_w[kWaves];
-    const uint64_t b0 = (uint64_t)blockIdx.x * kScanChunk;
-    const uint64_t per = kScanChunk / kThreads;  // 16 consecutive entries per thread
-    const uint64_t k0 = b0 + threadIdx.x * per;
-    unsigned long long loc[kScanChunk / kThreads];
-    unsigned long long tsum = 0;
-#pragma unroll
-    for (uint64_t q = 0; q < per; q++) {
-        loc[q] = (k0 + q < a.nodes) ? a.ones[k0 + q] : 0ull;
-        tsum += loc[q];
-    }
-    unsigned long long tot;
-    unsigned long long o1 = block_excl_scan64(tsum, s_w, &tot) + (use_partials ? a.partials[blockIdx.x] : 0ull);
-#pragma unroll
-    for (uint64_t q = 0; q < per; q++) {
-        const uint64_t v = k0 + q;
-        if (v < a.nodes) {
-            const unsigned long long ones = loc[q];
-            const uint64_t s_next = a.start[v + 1];
-            a.zo[v] = make_ulonglong2(o1, s_next - ones - o1);
-            if (a.start_next) {
-                a.start_next[2 * v] = a.start[v];
-                a.start_next[2 * v + 1] = s_next - ones;
-            }
-            o1 += ones;
-        }
-    }
-    if (a.start_next && blockIdx.x == 0 && threadIdx.x == 0) a.start_next[2 * a.nodes] = a.n;
-}
-
-// ------------------------------------------------------ superchunk scan --
-// sup[c] = ones in all tiles before superchunk c (kSup tiles each).
-// Workgroup c sums its superchunk's tile counts; the last workgroup to finish
-// (counted on *done) turns the sums into exclusive prefixes in place.
-
-__global__ __launch_bounds__(kThreads) void k_supsum(const uint32_t *tile_ones, unsigned long long *sup,
-                                                     uint32_t *done, uint64_t ntiles) {
-    __shared__ unsigned long long s_w[kWaves];
-    __shared__ uint32_t s_last;
-    const uint32_t tid = threadIdx.x;
-    const uint64_t t = (uint64_t)blockIdx.x * kSup + tid;
-    const uint32_t v = wave_sum32(t < ntiles ? tile_ones[t] : 0u);
-    if ((tid & 63) == 0) s_w[tid >> 6] = v;
-    __syncthreads();
-    if (tid == 0) {
-        unsigned long long tot = 0;
-#pragma unroll
-        for (int w = 0; w < kWaves; w++) tot += s_w[w];
-        sup[blockIdx.x] = tot;
-        __threadfence();  // publish the sum before counting this workgroup done
-        s_last = (atomicAdd(done, 1u) == gridDim.x - 1) ? 1u : 0u;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();  // see every other workgroup's sum
-    const uint64_t nsup = gridDim.x;
-    unsigned long long carry = 0;
-    for (uint64_t c0 = 0; c0 < nsup; c0 += kThreads) {
-        const uint64_t c = c0 + tid;
-        const unsigned long long x = (c < nsup) ? __hip_atomic_load(&sup[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
-        unsigned long long tot;
-        const unsigned long long ex = block_excl_scan64(x, s_w, &tot);
-        if (c < nsup) sup[c] = carry + ex;
-        carry += tot;
-    }
-}
-
-// ----------------------------------------------------------- level pass ---
+// Reads S once: flags symbols >= sigma, and counts the ones of level 0 (the
+// most significant of the l bits) per tile and in total.  Every later
+// node count is produced by the level pass before it.
 
 template <int E> struct MaskT { typedef uint32_t T; };
 template <> struct MaskT<64> { typedef uint64_t T; };
@@ -388,6 +190,234 @@ __device__ __forceinline__ typename MaskT<64 / W>::T level_bits(const uint4 (&ra
     return mb;
 }
 
+// Stable split of one lane's symbols into LDS: zeros to zc, zc+1, ...,
+// ones to oc, oc+1, ...  kFull: all E symbols are valid (no guards).
+template <int W, bool kFull>
+__device__ __forceinline__ void stage_split(typename ElemT<W>::T *s_stage, const uint4 (&raw)[4],
+                                            typename MaskT<64 / W>::T mb, uint32_t zc, uint32_t oc, int nval) {
+    typedef typename ElemT<W>::T T;
+    constexpr int E = 64 / W;
+    const uint32_t d[16] = {raw[0].x, raw[0].y, raw[0].z, raw[0].w, raw[1].x, raw[1].y, raw[1].z, raw[1].w,
+                            raw[2].x, raw[2].y, raw[2].z, raw[2].w, raw[3].x, raw[3].y, raw[3].z, raw[3].w};
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+        if (kFull || k < nval) {
+            const uint32_t b = (uint32_t)(mb >> k) & 1u;
+            // slot = b ? oc : zc, as one 24-bit multiply-add (slots < 2^24)
+            const uint32_t slot = __umul24(b, oc - zc) + zc;
+            // the store keeps the low W bytes of x (or, for the third byte of
+            // a dword, the d16_hi form picks it), so no masking is needed
+            uint32_t x;
+            if (W == 4) x = d[k];
+            else if (W == 2) x = (k & 1) ? (d[k >> 1] >> 16) : d[k >> 1];
+            else x = ((k & 3) == 1 || (k & 3) == 3) ? (d[k >> 2] >> 8) : d[k >> 2];
+            if (W == 1 && (k & 3) >= 2) x >>= 16;
+            s_stage[slot] = (T)x;
+            oc += b;
+            zc += b ^ 1u;
+        }
+    }
+}
+
+// Number of symbols of a 16-byte chunk whose bit sh2 is set.
+template <int W>
+__device__ __forceinline__ uint32_t chunk_bit_count(const uint4 &v, uint32_t sh2) {
+    const uint32_t lowbits = (W == 1) ? 0x01010101u : (W == 2) ? 0x00010001u : 1u;
+    return __popc((v.x >> sh2) & lowbits) + __popc((v.y >> sh2) & lowbits) + __popc((v.z >> sh2) & lowbits) +
+           __popc((v.w >> sh2) & lowbits);
+}
+
+template <int W>
+__global__ __launch_bounds__(kThreads) void k_ingest(IngestArgs a) {
+    constexpr int E = 64 / W;
+    constexpr uint64_t TILE = tile_syms(W);
+    const int lane = threadIdx.x & 63;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.start0) {
+        a.start0[0] = 0;
+        a.start0[1] = a.n;
+    }
+    // this workgroup's tiles: [t0, t1); wave wv takes every kWaves-th one
+    const uint64_t t0 = (uint64_t)blockIdx.x * a.tiles_per_block;
+    const uint64_t t1 = (t0 + a.tiles_per_block < a.ntiles) ? t0 + a.tiles_per_block : a.ntiles;
+    bool bad = false;
+    unsigned long long ones_acc = 0;
+    uint64_t t = t0 + wv;
+    uint4 raw[4], nxt[4];
+    int nval = (t < t1) ? load64<W>(a.S, t * TILE + (uint64_t)lane * E, a.n, raw) : 0;
+    for (; t < t1; t += kWaves) {
+        int nval_n = 0;
+        if (t + kWaves < t1) nval_n = load64<W>(a.S, (t + kWaves) * TILE + (uint64_t)lane * E, a.n, nxt);
+        if (a.check) {
+#pragma unroll
+            for (int k = 0; k < E; k++) bad |= (k < nval) && (raw_elem<W>(raw, k) >= a.sigma);
+        }
+        if (a.tile_ones0) {
+            // symbols past n load as 0, so they add no ones
+            const typename MaskT<E>::T mb = level_bits<W>(raw, a.msb);
+            const uint32_t ones =
+                wave_sum32((E == 64) ? (uint32_t)__popcll((uint64_t)mb) : (uint32_t)__popc((uint32_t)mb));
+            if (lane == 0) a.tile_ones0[t] = ones;
+            ones_acc += ones;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) raw[q] = nxt[q];
+        nval = nval_n;
+    }
+    if (__any(bad) && lane == 0) atomicOr(a.tree_status, 1u);
+    if (a.tile_ones0 && lane == 0 && ones_acc)
+        atomicAdd(&a.ones0[((uint64_t)blockIdx.x * kWaves + wv) % a.slots0], ones_acc);
+}
+
+// ----------------------------------------------------------- node tables --
+// For level i with node starts start_i and ones counts ones_i (the sum of
+// the counter slots):
+//   O1 = exclusive scan of ones_i (ones before each node),
+//   zo_i(v) = (O1(v), start_i(v+1) - ones_i(v) - O1(v)),
+//   start_{i+1}(2v) = start_i(v), start_{i+1}(2v+1) = start_i(v+1) - ones_i(v).
+// Small levels are done by one workgroup of k_prep; levels above kScanChunk
+// nodes (one counter slot) by k_plan_reduce / _partials / _apply.
+
+// Node tables for entries [b0, b0 + kScanChunk) given the ones before b0;
+// ov[v] holds the ones of node v.
+__device__ __forceinline__ void plan_chunk(const PlanArgs &a, const unsigned long long *ov, uint64_t b0,
+                                           unsigned long long before) {
+    __shared__ unsigned long long s_w[kWaves];
+    const uint64_t per = kScanChunk / kThreads;  // 16 consecutive entries per thread
+    const uint64_t k0 = b0 + threadIdx.x * per;
+    unsigned long long loc[kScanChunk / kThreads];
+    unsigned long long tsum = 0;
+#pragma unroll
+    for (uint64_t q = 0; q < per; q++) {
+        loc[q] = (k0 + q < a.nodes) ? ov[k0 + q] : 0ull;
+        tsum += loc[q];
+    }
+    unsigned long long tot;
+    unsigned long long o1 = block_excl_scan64(tsum, s_w, &tot) + before;
+#pragma unroll
+    for (uint64_t q = 0; q < per; q++) {
+        const uint64_t v = k0 + q;
+        if (v < a.nodes) {
+            const unsigned long long ones = loc[q];
+            const uint64_t s_next = a.start[v + 1];
+            a.zo[v] = make_ulonglong2(o1, s_next - ones - o1);
+            if (a.start_next) {
+                a.start_next[2 * v] = a.start[v];
+                a.start_next[2 * v + 1] = s_next - ones;
+            }
+            o1 += ones;
+        }
+    }
+    if (a.start_next && b0 == 0 && threadIdx.x == 0) a.start_next[2 * a.nodes] = a.n;
+}
+
+__global__ __launch_bounds__(kThreads) void k_plan_reduce(PlanArgs a) {
+    __shared__ unsigned long long s_w[kWaves];
+    const uint64_t b0 = (uint64_t)blockIdx.x * kScanChunk;
+    unsigned long long sum = 0;
+    for (uint64_t k = b0 + threadIdx.x; k < b0 + kScanChunk && k < a.nodes; k += kThreads) sum += a.ones[k];
+    sum = wave_sum64(sum);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kWaves; w++) t += s_w[w];
+        a.partials[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_plan_partials(PlanArgs a, uint64_t nblocks) {
+    // nblocks <= kMaxScanBlocks: a few consecutive entries per thread
+    __shared__ unsigned long long s_w[kWaves];
+    const uint64_t per = ceil_div(nblocks, kThreads);
+    const uint64_t k0 = threadIdx.x * per;
+    unsigned long long sum = 0;
+    for (uint64_t q = 0; q < per; q++)
+        if (k0 + q < nblocks) sum += a.partials[k0 + q];
+    unsigned long long tot;
+    unsigned long long off = block_excl_scan64(sum, s_w, &tot);
+    for (uint64_t q = 0; q < per; q++) {
+        if (k0 + q < nblocks) {
+            const unsigned long long v = a.partials[k0 + q];
+            a.partials[k0 + q] = off;
+            off += v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_plan_apply(PlanArgs a) {
+    plan_chunk(a, a.ones, (uint64_t)blockIdx.x * kScanChunk, a.partials[blockIdx.x]);
+}
+
+// ------------------------------------------------------ per-level prep ---
+// k_supsum: workgroup c adds up the kSup tile counts of superchunk c.
+// k_prep (one workgroup): sup[c] = ones in all tiles before superchunk c,
+// and, for levels of at most kScanChunk nodes, the level's node tables.
+
+__global__ __launch_bounds__(kThreads) void k_supsum(PrepArgs a) {
+    __shared__ uint32_t s_w[kWaves];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t t = (uint64_t)blockIdx.x * kSup + tid;
+    const uint32_t v = wave_sum32(t < a.ntiles ? a.tile_ones[t] : 0u);
+    if ((tid & 63) == 0) s_w[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long tot = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; w++) tot += s_w[w];
+        a.supsum[blockIdx.x] = tot;
+    }
+}
+
+// Sum of the counter slots q = g, g + step, ... of node v (loads batched).
+__device__ __forceinline__ unsigned long long slot_sum(const unsigned long long *ones, uint64_t nodes,
+                                                       uint64_t slots, uint64_t v, uint64_t g, uint64_t step) {
+    unsigned long long c = 0;
+    uint64_t q = g;
+    for (; q + 7 * step < slots; q += 8 * step) {
+        unsigned long long x[8];
+#pragma unroll
+        for (int r = 0; r < 8; r++) x[r] = ones[(q + r * step) * nodes + v];
+#pragma unroll
+        for (int r = 0; r < 8; r++) c += x[r];
+    }
+    for (; q < slots; q += step) c += ones[q * nodes + v];
+    return c;
+}
+
+__global__ __launch_bounds__(kThreads) void k_prep(PrepArgs a) {
+    __shared__ unsigned long long s_w[kWaves];
+    __shared__ unsigned long long s_n[kScanChunk];
+    const uint32_t tid = threadIdx.x;
+    unsigned long long carry = 0;
+    for (uint64_t c0 = 0; c0 < a.nsup; c0 += kThreads) {
+        const uint64_t c = c0 + tid;
+        const unsigned long long v = (c < a.nsup) ? a.supsum[c] : 0ull;
+        unsigned long long tot;
+        const unsigned long long ex = block_excl_scan64(v, s_w, &tot);
+        if (c < a.nsup) a.sup[c] = carry + ex;
+        carry += tot;
+    }
+    if (!a.plan_here) return;
+    // add up the node counter slots (nodes <= kScanChunk), then scan
+    const PlanArgs &p = a.plan;
+    for (uint64_t v = tid; v < p.nodes; v += kThreads) s_n[v] = 0;
+    __syncthreads();
+    if (p.nodes >= kThreads) {
+        for (uint64_t v = tid; v < p.nodes; v += kThreads) s_n[v] = slot_sum(p.ones, p.nodes, p.slots, v, 0, 1);
+    } else {
+        // kThreads / nodes threads per node, then one LDS add per thread
+        const uint64_t groups = kThreads / p.nodes;
+        const uint64_t v = tid % p.nodes, g = tid / p.nodes;
+        const unsigned long long c = slot_sum(p.ones, p.nodes, p.slots, v, g, groups);
+        if (c) atomicAdd(&s_n[v], c);
+    }
+    __syncthreads();
+    plan_chunk(p, s_n, 0, 0ull);
+}
+
+// ----------------------------------------------------------- level pass ---
+
 // One level pass.  Every wave owns one tile of TILE consecutive positions of
 // T_i (each lane 64 bytes = E symbols); there is no workgroup barrier.
 template <int W>
@@ -405,7 +435,8 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
     constexpr uint32_t kWaveBytes = (kStageBytes > kCntBytes ? kStageBytes : kCntBytes);
     __shared__ __align__(16) uint8_t s_all[kWaves * kWaveBytes];
 
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t t = (uint64_t)blockIdx.x * kWaves + wv;
     if (t >= a.ntiles) return;  // whole wave
     T *s_stage = reinterpret_cast<T *>(s_all + wv * kWaveBytes);
@@ -433,7 +464,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
     const M mb = level_bits<W>(raw, sh);
     const uint32_t pc = (E == 64) ? (uint32_t)__popcll((uint64_t)mb) : (uint32_t)__popc((uint32_t)mb);
     const uint32_t incl = wave_incl_scan(pc);
-    const uint32_t agg = __shfl(incl, 63, 64);
+    const uint32_t agg = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
     prefix += wave_sum32(pv);
     const uint32_t lr1 = incl - pc;  // ones in the tile before this lane
     const unsigned long long r_lane = prefix + lr1;
@@ -461,9 +492,13 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
     if (a.tout == nullptr) return;  // last level: no next order, no counts
 
     // node span of the tile (T_i is sorted by node)
-    const uint32_t vf = __shfl((raw_elem<W>(raw, 0) & a.symmask) >> nsh, 0, 64);
+    const bool full = (nvalid == TILE);  // every tile but a ragged last one
+    const uint32_t vf =
+        __builtin_amdgcn_readfirstlane(__shfl((raw_elem<W>(raw, 0) & a.symmask) >> nsh, 0, 64));
     uint32_t vl;
-    {
+    if (full) {
+        vl = __shfl((raw_elem<W>(raw, E - 1) & a.symmask) >> nsh, 63, 64);
+    } else {
         const uint64_t last = nvalid - 1;
         const int kl = (int)(last % E);
         uint32_t xv = 0;
@@ -471,10 +506,12 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
         for (int k = 0; k < E; k++) xv = (k == kl) ? raw_elem<W>(raw, k) : xv;
         vl = __shfl((xv & a.symmask) >> nsh, (int)(last / E), 64);
     }
+    vl = __builtin_amdgcn_readfirstlane(vl);
 
     T *tout = reinterpret_cast<T *>(a.tout);
     const bool counting = a.tile_ones_next != nullptr;
     const uint32_t sh2 = sh - 1;  // bit of the next level (when counting)
+    unsigned long long *ones_next = a.ones_next + (t % a.slots_next) * a.nodes_next;
     if (vf == vl) {
         // Single node: zeros keep their order at g0.., ones at g1...
         const ulonglong2 zo = a.zo[vf];
@@ -484,17 +521,10 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
         const uint32_t a0 = (uint32_t)(g0 % CH);
         const uint32_t r1 = (uint32_t)round_up(a0 + Z, CH);
         const uint32_t a1 = r1 + (uint32_t)(g1 % CH);
-        uint32_t zc = a0 + (uint32_t)lane * E - lr1;  // next zero slot of this lane
-        uint32_t oc = a1 + lr1;                       // next one slot of this lane
-#pragma unroll
-        for (int k = 0; k < E; k++) {
-            if (k < nval) {
-                const uint32_t b = (uint32_t)(mb >> k) & 1u;
-                s_stage[b ? oc : zc] = (T)(raw_elem<W>(raw, k) & a.symmask);
-                oc += b;
-                zc += 1u - b;
-            }
-        }
+        const uint32_t zc = a0 + (uint32_t)lane * E - lr1;  // first zero slot of this lane
+        const uint32_t oc = a1 + lr1;                       // first one slot of this lane
+        if (full) stage_split<W, true>(s_stage, raw, mb, zc, oc, nval);
+        else stage_split<W, false>(s_stage, raw, mb, zc, oc, nval);
         wave_sync();
         // next-level ones per (run, destination-tile parity): a run holds at
         // most TILE symbols, so it touches at most two consecutive tiles
@@ -508,27 +538,28 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
             const uint32_t lo = region ? a1 : a0;
             const uint32_t hi = region ? a1 + (uint32_t)O : a0 + (uint32_t)Z;
             const uint4 v = *reinterpret_cast<const uint4 *>(&s_stage[s]);
+            uint32_t ones = 0;
             // (destinations beyond n only arise from inconsistent tables; they
             // are dropped rather than written)
             if (s >= lo && s + CH <= hi && gb + s + CH <= a.n) {
                 *reinterpret_cast<uint4 *>(tout + (gb + s)) = v;
+                if (counting) ones = chunk_bit_count<W>(v, sh2);
             } else {
 #pragma unroll
-                for (int e = 0; e < CH; e++)
-                    if (s + e >= lo && s + e < hi && gb + s + e < a.n) tout[gb + s + e] = (T)chunk_elem<W>(v, e);
-            }
-            if (counting) {
-                uint32_t ones = 0;
-#pragma unroll
-                for (int e = 0; e < CH; e++)
-                    ones += (s + e >= lo && s + e < hi) ? ((chunk_elem<W>(v, e) >> sh2) & 1u) : 0u;
-                if (ones) {
-                    const uint64_t dt = (gb + s) / TILE;  // 16-byte chunks never straddle tiles
-                    const uint32_t key = region * 2 + (uint32_t)(dt & 1);
-#pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        if (q == (int)key) { c4[q] += ones; d4[q] = (uint32_t)dt; }
+                for (int e = 0; e < CH; e++) {
+                    if (s + e >= lo && s + e < hi && gb + s + e < a.n) {
+                        const uint32_t x = chunk_elem<W>(v, e);
+                        tout[gb + s + e] = (T)x;
+                        ones += (x >> sh2) & 1u;
                     }
+                }
+            }
+            if (counting && ones) {
+                const uint64_t dt = (gb + s) / TILE;  // 16-byte chunks never straddle tiles
+                const uint32_t key = region * 2 + (uint32_t)(dt & 1);
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    if (q == (int)key) { c4[q] += ones; d4[q] = (uint32_t)dt; }
                 }
             }
         }
@@ -541,7 +572,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
                 const uint32_t dt = __shfl(d4[q], __builtin_ctzll(m), 64);
                 if (lane == 0) {
                     atomicAdd(&a.tile_ones_next[dt], tot);
-                    if (a.ones_next) atomicAdd(&a.ones_next[2ull * vf + (q >> 1)], (unsigned long long)tot);
+                    atomicAdd(&ones_next[2ull * vf + (q >> 1)], (unsigned long long)tot);
                 }
             }
         }
@@ -575,7 +606,7 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
                         s_tix[key] = (uint32_t)dt;
                     } else {
                         atomicAdd(&a.tile_ones_next[dt], 1u);
-                        if (a.ones_next) atomicAdd(&a.ones_next[2ull * v + b], 1ull);
+                        atomicAdd(&ones_next[2ull * v + b], 1ull);
                     }
                 }
             }
@@ -588,15 +619,13 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
             if (c) {
                 const uint32_t dt = s_tix[q];
                 atomicAdd(&a.tile_ones_next[dt], c);
-                if (a.ones_next) atomicAdd(&a.ones_next[2ull * (vf + q / 4) + ((q >> 1) & 1u)], (unsigned long long)c);
+                atomicAdd(&ones_next[2ull * (vf + q / 4) + ((q >> 1) & 1u)], (unsigned long long)c);
             }
         }
     }
 }
 
 }  // namespace
-
-
 
 // ------------------------------------------------------------- launchers --
 
@@ -624,25 +653,17 @@ hipError_t launch_ingest(const IngestArgs &a, uint32_t width, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_top(const TopArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_top, dim3(1), dim3(kThreads), 0, s, a);
+hipError_t launch_prep(const PrepArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_supsum, dim3((uint32_t)a.nsup), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(k_prep, dim3(1), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_plan(const PlanArgs &a, hipStream_t s) {
     const uint64_t nb = ceil_div(a.nodes, kScanChunk);
-    if (nb > 1) {
-        hipLaunchKernelGGL(k_plan_reduce, dim3((uint32_t)nb), dim3(kThreads), 0, s, a);
-        hipLaunchKernelGGL(k_plan_partials, dim3(1), dim3(kThreads), 0, s, a, nb);
-    }
-    hipLaunchKernelGGL(k_plan_apply, dim3((uint32_t)nb), dim3(kThreads), 0, s, a, nb > 1 ? 1 : 0);
-    return hipGetLastError();
-}
-
-hipError_t launch_supsum(const uint32_t *tile_ones, unsigned long long *sup, uint32_t *done, uint64_t ntiles,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_supsum, dim3((uint32_t)ceil_div(ntiles, kSup)), dim3(kThreads), 0, s, tile_ones, sup, done,
-                       ntiles);
+    hipLaunchKernelGGL(k_plan_reduce, dim3((uint32_t)nb), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(k_plan_partials, dim3(1), dim3(kThreads), 0, s, a, nb);
+    hipLaunchKernelGGL(k_plan_apply, dim3((uint32_t)nb), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 
