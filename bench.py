@@ -36,6 +36,8 @@ WORKLOADS = {
     "c1": "n=2^20 uint8 sigma=256 uniform",
     "c2": "n=2^28 uint8 sigma=256 Zipf(1.1) over a seeded permutation of the alphabet",
     "c3": "n=2^28 uint32 sigma=2^20 half uniform, half 64 Gaussian clusters (sd 2^10)",
+    "c4": "4096 sequences, n = 2^U with U ~ U[10, 22], sigma from {4, 20, 256, 2^16} "
+          "(u8/u8/u8/u16), uniform symbols; one batched build",
 }
 
 
@@ -106,6 +108,8 @@ def main() -> int:
 
     from paper_1610_05994_amd import wtree
 
+    if args.workload == "c4":
+        return bench_batch(args)
     dev = torch.device("cuda:0")
     print("bench: generating workload %s" % args.workload, file=sys.stderr, flush=True)
     S, sigma = None, None
@@ -232,6 +236,115 @@ def main() -> int:
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline on n=2^%d" % args.cpu_sample_lg, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_lg, args.cpu_runs)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_batch(args) -> int:
+    """Batched build of many uneven sequences vs one build call per sequence."""
+    import torch
+
+    from paper_1610_05994_amd import wtree
+
+    dev = torch.device("cuda:0")
+    m = int(os.environ.get("WT_BENCH_BATCH", "4096"))
+    print("bench: generating %d sequences" % m, file=sys.stderr, flush=True)
+    specs = wtgen.batch_specs(m, wtgen.SEED_BASE + 3)
+    Ss = wtgen.batch_inputs(specs)
+    total = sum(d["n"] for d in specs)
+    dS = [wtree.to_device(S, dev) for S in Ss]
+    descs = [(d["n"], d["sigma"], d["width"]) for d in specs]
+    trees, tbytes = [], []
+    max_work = 256
+    for d in descs:
+        rc, tb, wb = wtree.wt_footprint(*d)
+        trees.append(torch.empty(tb, dtype=torch.uint8, device=dev))
+        tbytes.append(tb)
+        max_work = max(max_work, wb)
+    rc, bw = wtree.wt_batch_footprint(descs)
+    assert rc == wtree.WT_OK
+    work = torch.empty(bw, dtype=torch.uint8, device=dev)
+    work1 = torch.empty(max_work, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+    sh = int(stream.cuda_stream)
+    sptr = [x.data_ptr() for x in dS]
+    tptr = [x.data_ptr() for x in trees]
+
+    def batched():
+        rc, hs = wtree.wt_build_batch(sptr, descs, tptr, tbytes, work.data_ptr(), bw, sh)
+        if rc != wtree.WT_OK:
+            raise wtree.WtError(rc, "wt_build_batch")
+        return hs
+
+    def one_by_one():
+        hs = []
+        for q, d in enumerate(descs):
+            rc, h = wtree.wt_build(sptr[q], d[0], d[1], d[2], tptr[q], tbytes[q], work1.data_ptr(), max_work, sh)
+            if rc != wtree.WT_OK:
+                raise wtree.WtError(rc, "wt_build")
+            hs.append(h)
+        return hs
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            for h in fn():
+                wtree.wt_free(h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for h in fn():
+                wtree.wt_free(h)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    print("bench: batched", file=sys.stderr, flush=True)
+    wtree.wt_prof_enable(True)
+    ms_batch = timed(batched, args.steps, args.warmup)
+    recs = wtree.wt_prof_read()
+    wtree.wt_prof_enable(False)
+    # sanity: sampled positions of a few trees decode back to their sequences
+    hs = batched()
+    torch.cuda.synchronize()
+    for q in range(0, m, max(1, m // 16)):
+        n = descs[q][0]
+        if n == 0:
+            continue
+        assert wtree.wt_tree_status(hs[q]) == wtree.WT_OK
+        pos = torch.from_numpy(np.random.Generator(np.random.PCG64(q)).integers(0, n, 64)).to(dev)
+        sym = torch.empty(64, dtype=torch.int32, device=dev)
+        assert wtree.wt_access_batch(hs[q], pos.data_ptr(), sym.data_ptr(), 64, sh) == wtree.WT_OK
+        torch.cuda.synchronize()
+        want = torch.from_numpy(Ss[q][pos.cpu().numpy()].astype(np.int64))
+        assert torch.equal(sym.cpu().to(torch.int64) & 0xFFFFFFFF, want), "batched access mismatch"
+    for h in hs:
+        wtree.wt_free(h)
+    print("bench: one build call per sequence", file=sys.stderr, flush=True)
+    ms_single = timed(one_by_one, max(1, args.steps // 4), 1)
+
+    lvl = [r for r in recs if r["kernel"] == "batch_level"]
+    lvl_ms = sum(r["ms"] for r in lvl)
+    lvl_bytes = sum(r["bytes"] for r in lvl)
+    achieved = lvl_bytes / (lvl_ms / 1e3) / 1e9 if lvl_ms > 0 else 0.0
+    out = {
+        "metric": METRIC,
+        "value": total / (ms_batch / 1e3),
+        "unit": "symbols/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_batch,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8/u16",
+        "data": "synthetic",
+        "config": {"workload": "c4: " + WORKLOADS["c4"], "sequences": m, "total_symbols": total},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "level phase of the batched build (supsum + prep + level pass, all sequences)"},
+        "one_call_per_sequence": {"ms": ms_single, "symbols_per_s": total / (ms_single / 1e3),
+                                  "batched_speedup": ms_single / ms_batch},
+    }
     print(json.dumps(out), flush=True)
     return 0
 

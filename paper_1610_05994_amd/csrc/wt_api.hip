@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -260,6 +261,84 @@ static wt_tree *new_handle(const Layout &L, void *tree, hipStream_t st) {
     return h;
 }
 
+// Batched-build workspace: job descriptors, block maps, then one workspace
+// slice per sequence.
+struct BatchPlan {
+    std::vector<Layout> L;
+    std::vector<uint32_t> order[3];  // per width class (1, 2, 4 bytes): sequences by levels, descending
+    uint64_t jobs_off, map_off[3], sup_off[3], slices_off, total;
+    std::vector<uint64_t> slice;     // workspace offset of each sequence's slice
+    uint64_t blocks[3], sups[3];
+};
+
+static int width_class(uint32_t w) { return w == 1 ? 0 : (w == 2 ? 1 : 2); }
+
+static int plan_batch(uint32_t m, const wt_desc *descs, BatchPlan *P) {
+    P->L.resize(m);
+    for (uint32_t q = 0; q < m; q++) {
+        int rc = check_desc(&descs[q]);
+        if (rc != WT_OK) return rc;
+        make_layout(descs[q].n, descs[q].sigma, descs[q].width, &P->L[q]);
+        P->order[width_class(descs[q].width)].push_back(q);
+    }
+    uint64_t off = round_up((uint64_t)m * sizeof(BatchJob), 256);
+    P->jobs_off = 0;
+    for (int c = 0; c < 3; c++) {
+        std::vector<uint32_t> &o = P->order[c];
+        std::stable_sort(o.begin(), o.end(), [&](uint32_t x, uint32_t y) { return P->L[x].levels > P->L[y].levels; });
+        uint64_t nb = 0, ns = 0;
+        for (uint32_t q : o) {
+            nb += ceil_div(P->L[q].ntiles, kWaves);
+            ns += P->L[q].nsup;
+        }
+        P->blocks[c] = nb;
+        P->sups[c] = ns;
+        P->map_off[c] = off;
+        off += round_up((nb ? nb : 1) * 4, 256);
+        P->sup_off[c] = off;
+        off += round_up((ns ? ns : 1) * 4, 256);
+    }
+    P->slices_off = off;
+    P->slice.resize(m);
+    for (uint32_t q = 0; q < m; q++) {
+        P->slice[q] = off;
+        off += round_up(P->L[q].work_bytes, 256);
+    }
+    P->total = off;
+    return WT_OK;
+}
+
+static BatchJob make_job(const Layout &L, const void *S, void *tree, uint8_t *work) {
+    BatchJob j;
+    memset(&j, 0, sizeof(j));
+    j.S = S;
+    j.tree = reinterpret_cast<uint8_t *>(tree);
+    j.work = work;
+    j.n = L.n;
+    j.words = L.words;
+    j.rank_entries = L.rank_entries;
+    j.rank_stride = L.rank_stride;
+    j.ntiles = L.ntiles;
+    j.nsup = L.nsup;
+    j.tree_bits_off = L.tree_bits_off;
+    j.tree_ranks_off = L.tree_ranks_off;
+    j.ws_ta = L.ws_ta;
+    j.ws_tb = L.ws_tb;
+    j.ws_ctrl = L.ws_ctrl;
+    j.ws_ctrl_bytes = L.ws_ctrl_bytes;
+    j.ws_tile_ones = L.ws_tile_ones;
+    j.ws_ones = L.ws_ones;
+    j.ws_sup = L.ws_sup;
+    j.ws_supsum = L.ws_supsum;
+    j.ws_zo = L.ws_zo;
+    j.ws_start = L.ws_start;
+    j.sigma = L.sigma;
+    j.width = L.width;
+    j.levels = L.levels;
+    j.check = (L.width < 4 && (uint64_t)L.sigma == (1ull << (8 * L.width))) ? 0u : 1u;
+    return j;
+}
+
 }  // namespace wt
 
 using namespace wt;
@@ -300,15 +379,10 @@ int wt_build(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t tree_b
 
 int wt_batch_footprint(uint32_t m, const wt_desc *descs, uint64_t *work_bytes) {
     if (m > 0 && !descs) return WT_EINVAL;
-    uint64_t total = 0;
-    for (uint32_t q = 0; q < m; q++) {
-        int rc = check_desc(&descs[q]);
-        if (rc != WT_OK) return rc;
-        Layout L;
-        make_layout(descs[q].n, descs[q].sigma, descs[q].width, &L);
-        total += round_up(L.work_bytes, 256);
-    }
-    if (work_bytes) *work_bytes = total ? total : 256;
+    BatchPlan P;
+    int rc = plan_batch(m, descs, &P);
+    if (rc != WT_OK) return rc;
+    if (work_bytes) *work_bytes = P.total;
     return WT_OK;
 }
 
@@ -316,32 +390,94 @@ int wt_build_batch(uint32_t m, const void *const *d_S, const wt_desc *descs, voi
                    const uint64_t *tree_bytes, void *d_work, uint64_t work_bytes, void *stream, wt_tree **out) {
     if (!out || (m > 0 && (!d_S || !descs || !d_trees || !tree_bytes || !d_work))) return WT_EINVAL;
     for (uint32_t q = 0; q < m; q++) out[q] = nullptr;
-    uint64_t need = 0;
-    int rc = wt_batch_footprint(m, descs, &need);
+    if (m == 0) return WT_OK;
+    BatchPlan P;
+    int rc = plan_batch(m, descs, &P);
     if (rc != WT_OK) return rc;
-    if (m > 0 && work_bytes < need) return WT_ENOMEM;
+    if (work_bytes < P.total) return WT_ENOMEM;
     if ((uintptr_t)d_work & 255) return WT_EINVAL;
     for (uint32_t q = 0; q < m; q++) {
         if (!d_trees[q] || (descs[q].n > 0 && !d_S[q])) return WT_EINVAL;
         if (((uintptr_t)d_S[q] & 15) || ((uintptr_t)d_trees[q] & 255)) return WT_EINVAL;
-        Layout L;
-        make_layout(descs[q].n, descs[q].sigma, descs[q].width, &L);
-        if (tree_bytes[q] < L.tree_bytes) return WT_ENOMEM;
+        if (tree_bytes[q] < P.L[q].tree_bytes) return WT_ENOMEM;
     }
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     uint8_t *work = reinterpret_cast<uint8_t *>(d_work);
-    uint64_t off = 0;
+
+    // job descriptors, class by class (levels descending inside a class)
+    std::vector<BatchJob> jobs;
+    jobs.reserve(m);
+    uint32_t first[3];
+    uint32_t maxl = 0;
+    for (int c = 0; c < 3; c++) {
+        first[c] = (uint32_t)jobs.size();
+        uint64_t blk = 0, sup = 0;
+        for (uint32_t q : P.order[c]) {
+            BatchJob j = make_job(P.L[q], d_S[q], d_trees[q], work + P.slice[q]);
+            j.blk_base = blk;
+            j.sup_base = sup;
+            blk += ceil_div(P.L[q].ntiles, kWaves);
+            sup += P.L[q].nsup;
+            jobs.push_back(j);
+            maxl = std::max(maxl, P.L[q].levels);
+        }
+    }
+    BatchJob *d_jobs = reinterpret_cast<BatchJob *>(work + P.jobs_off);
+    // (pageable source: the call returns once the descriptors are staged)
+    if (hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(BatchJob), hipMemcpyHostToDevice, st) != hipSuccess)
+        return WT_EDEVICE;
+
+    BatchClass cls[3];
+    for (int c = 0; c < 3; c++) {
+        cls[c].jobs = d_jobs + first[c];
+        cls[c].blk_map = reinterpret_cast<uint32_t *>(work + P.map_off[c]);
+        cls[c].sup_map = reinterpret_cast<uint32_t *>(work + P.sup_off[c]);
+        cls[c].njobs = (uint32_t)P.order[c].size();
+    }
+    static const uint32_t widths[3] = {1, 2, 4};
+    hipError_t err = hipSuccess;
+    for (int c = 0; c < 3 && err == hipSuccess; c++) {
+        if (!cls[c].njobs) continue;
+        long pr = prof_begin(st, "batch_setup", 0, widths[c], 0, 0);
+        err = launch_batch_setup(cls[c], P.blocks[c], P.sups[c], st);
+        prof_end(pr, st);
+    }
+    for (int c = 0; c < 3 && err == hipSuccess; c++) {
+        if (!cls[c].njobs) continue;
+        uint64_t nsym = 0;
+        for (uint32_t q : P.order[c]) nsym += P.L[q].n;
+        long pr = prof_begin(st, "batch_ingest", 0, widths[c], nsym, nsym * widths[c]);
+        err = launch_batch_ingest(cls[c], widths[c], P.blocks[c], st);
+        prof_end(pr, st);
+    }
+    for (uint32_t i = 0; i < maxl && err == hipSuccess; i++) {
+        for (int c = 0; c < 3 && err == hipSuccess; c++) {
+            // the sequences still building level i are a prefix of the class
+            uint32_t active = 0;
+            uint64_t blocks = 0, sups = 0, nsym = 0, bytes = 0;
+            for (uint32_t q : P.order[c]) {
+                const Layout &L = P.L[q];
+                if (L.levels <= i) break;
+                active++;
+                blocks += ceil_div(L.ntiles, kWaves);
+                sups += L.nsup;
+                nsym += L.n;
+                bytes += L.n * L.width * (i + 1 < L.levels ? 2 : 1) + L.words * 8 + L.rank_stride * 8;
+            }
+            if (!active) continue;
+            long pr = prof_begin(st, "batch_level", i, widths[c], nsym, bytes);
+            err = launch_batch_level(cls[c], widths[c], i, active, blocks, sups, st);
+            prof_end(pr, st);
+        }
+    }
+    if (err != hipSuccess) return WT_EDEVICE;
     for (uint32_t q = 0; q < m; q++) {
-        Layout L;
-        make_layout(descs[q].n, descs[q].sigma, descs[q].width, &L);
-        wt_tree *h = new_handle(L, d_trees[q], st);
-        if (!h || enqueue_build(d_S[q], L, reinterpret_cast<uint8_t *>(d_trees[q]), work + off, st) != hipSuccess) {
-            delete h;
+        wt_tree *h = new_handle(P.L[q], d_trees[q], st);
+        if (!h) {
             for (uint32_t r = 0; r < q; r++) { delete out[r]; out[r] = nullptr; }
-            return h ? WT_EDEVICE : WT_ENOMEM;
+            return WT_ENOMEM;
         }
         out[q] = h;
-        off += round_up(L.work_bytes, 256);
     }
     return WT_OK;
 }

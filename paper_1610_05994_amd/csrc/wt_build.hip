@@ -227,11 +227,39 @@ __device__ __forceinline__ uint32_t chunk_bit_count(const uint4 &v, uint32_t sh2
            __popc((v.w >> sh2) & lowbits);
 }
 
+// One tile of the ingest pass, run by one wave: returns the tile's level-0
+// ones (when they are counted) and sets bad if a symbol is >= sigma.
 template <int W>
-__global__ __launch_bounds__(kThreads) void k_ingest(IngestArgs a) {
+__device__ __forceinline__ uint32_t ingest_tile(const IngestArgs &a, uint64_t t, bool &bad) {
     constexpr int E = 64 / W;
     constexpr uint64_t TILE = tile_syms(W);
     const int lane = threadIdx.x & 63;
+    uint4 raw[4];
+    const int nval = load64<W>(a.S, t * TILE + (uint64_t)lane * E, a.n, raw);
+    if (a.check) {
+#pragma unroll
+        for (int k = 0; k < E; k++) bad |= (k < nval) && (raw_elem<W>(raw, k) >= a.sigma);
+    }
+    uint32_t ones = 0;
+    if (a.tile_ones0) {
+        // symbols past n load as 0, so they add no ones
+        const typename MaskT<E>::T mb = level_bits<W>(raw, a.msb);
+        ones = wave_sum32((E == 64) ? (uint32_t)__popcll((uint64_t)mb) : (uint32_t)__popc((uint32_t)mb));
+        if (lane == 0) a.tile_ones0[t] = ones;
+    }
+    return ones;
+}
+
+// Ends an ingest wave: reports bad symbols, adds the root's ones.
+__device__ __forceinline__ void ingest_finish(const IngestArgs &a, bool bad, unsigned long long ones_acc,
+                                              uint64_t slot) {
+    const int lane = threadIdx.x & 63;
+    if (__any(bad) && lane == 0) atomicOr(a.tree_status, 1u);
+    if (a.tile_ones0 && lane == 0 && ones_acc) atomicAdd(&a.ones0[slot % a.slots0], ones_acc);
+}
+
+template <int W>
+__global__ __launch_bounds__(kThreads) void k_ingest(IngestArgs a) {
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (blockIdx.x == 0 && threadIdx.x == 0 && a.start0) {
         a.start0[0] = 0;
@@ -242,31 +270,8 @@ __global__ __launch_bounds__(kThreads) void k_ingest(IngestArgs a) {
     const uint64_t t1 = (t0 + a.tiles_per_block < a.ntiles) ? t0 + a.tiles_per_block : a.ntiles;
     bool bad = false;
     unsigned long long ones_acc = 0;
-    uint64_t t = t0 + wv;
-    uint4 raw[4], nxt[4];
-    int nval = (t < t1) ? load64<W>(a.S, t * TILE + (uint64_t)lane * E, a.n, raw) : 0;
-    for (; t < t1; t += kWaves) {
-        int nval_n = 0;
-        if (t + kWaves < t1) nval_n = load64<W>(a.S, (t + kWaves) * TILE + (uint64_t)lane * E, a.n, nxt);
-        if (a.check) {
-#pragma unroll
-            for (int k = 0; k < E; k++) bad |= (k < nval) && (raw_elem<W>(raw, k) >= a.sigma);
-        }
-        if (a.tile_ones0) {
-            // symbols past n load as 0, so they add no ones
-            const typename MaskT<E>::T mb = level_bits<W>(raw, a.msb);
-            const uint32_t ones =
-                wave_sum32((E == 64) ? (uint32_t)__popcll((uint64_t)mb) : (uint32_t)__popc((uint32_t)mb));
-            if (lane == 0) a.tile_ones0[t] = ones;
-            ones_acc += ones;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; q++) raw[q] = nxt[q];
-        nval = nval_n;
-    }
-    if (__any(bad) && lane == 0) atomicOr(a.tree_status, 1u);
-    if (a.tile_ones0 && lane == 0 && ones_acc)
-        atomicAdd(&a.ones0[((uint64_t)blockIdx.x * kWaves + wv) % a.slots0], ones_acc);
+    for (uint64_t t = t0 + wv; t < t1; t += kWaves) ones_acc += ingest_tile<W>(a, t, bad);
+    ingest_finish(a, bad, ones_acc, (uint64_t)blockIdx.x * kWaves + wv);
 }
 
 // ----------------------------------------------------------- node tables --
@@ -279,9 +284,9 @@ __global__ __launch_bounds__(kThreads) void k_ingest(IngestArgs a) {
 // nodes (one counter slot) by k_plan_reduce / _partials / _apply.
 
 // Node tables for entries [b0, b0 + kScanChunk) given the ones before b0;
-// ov[v] holds the ones of node v.
-__device__ __forceinline__ void plan_chunk(const PlanArgs &a, const unsigned long long *ov, uint64_t b0,
-                                           unsigned long long before) {
+// ov[v - b0] holds the ones of node v.  Returns the ones of the chunk.
+__device__ __forceinline__ unsigned long long plan_chunk(const PlanArgs &a, const unsigned long long *ov, uint64_t b0,
+                                                         unsigned long long before) {
     __shared__ unsigned long long s_w[kWaves];
     const uint64_t per = kScanChunk / kThreads;  // 16 consecutive entries per thread
     const uint64_t k0 = b0 + threadIdx.x * per;
@@ -289,7 +294,7 @@ __device__ __forceinline__ void plan_chunk(const PlanArgs &a, const unsigned lon
     unsigned long long tsum = 0;
 #pragma unroll
     for (uint64_t q = 0; q < per; q++) {
-        loc[q] = (k0 + q < a.nodes) ? ov[k0 + q] : 0ull;
+        loc[q] = (k0 + q < a.nodes) ? ov[k0 + q - b0] : 0ull;
         tsum += loc[q];
     }
     unsigned long long tot;
@@ -309,6 +314,7 @@ __device__ __forceinline__ void plan_chunk(const PlanArgs &a, const unsigned lon
         }
     }
     if (a.start_next && b0 == 0 && threadIdx.x == 0) a.start_next[2 * a.nodes] = a.n;
+    return tot;
 }
 
 __global__ __launch_bounds__(kThreads) void k_plan_reduce(PlanArgs a) {
@@ -346,7 +352,8 @@ __global__ __launch_bounds__(kThreads) void k_plan_partials(PlanArgs a, uint64_t
 }
 
 __global__ __launch_bounds__(kThreads) void k_plan_apply(PlanArgs a) {
-    plan_chunk(a, a.ones, (uint64_t)blockIdx.x * kScanChunk, a.partials[blockIdx.x]);
+    const uint64_t b0 = (uint64_t)blockIdx.x * kScanChunk;
+    plan_chunk(a, a.ones + b0, b0, a.partials[blockIdx.x]);
 }
 
 // ------------------------------------------------------ per-level prep ---
@@ -354,20 +361,24 @@ __global__ __launch_bounds__(kThreads) void k_plan_apply(PlanArgs a) {
 // k_prep (one workgroup): sup[c] = ones in all tiles before superchunk c,
 // and, for levels of at most kScanChunk nodes, the level's node tables.
 
-__global__ __launch_bounds__(kThreads) void k_supsum(PrepArgs a) {
+// Workgroup: supsum[c] = ones of the kSup tiles of superchunk c.
+__device__ __forceinline__ void supsum_one(const uint32_t *tile_ones, uint64_t ntiles, uint64_t c,
+                                           unsigned long long *supsum) {
     __shared__ uint32_t s_w[kWaves];
     const uint32_t tid = threadIdx.x;
-    const uint64_t t = (uint64_t)blockIdx.x * kSup + tid;
-    const uint32_t v = wave_sum32(t < a.ntiles ? a.tile_ones[t] : 0u);
+    const uint64_t t = c * kSup + tid;
+    const uint32_t v = wave_sum32(t < ntiles ? tile_ones[t] : 0u);
     if ((tid & 63) == 0) s_w[tid >> 6] = v;
     __syncthreads();
     if (tid == 0) {
         unsigned long long tot = 0;
 #pragma unroll
         for (int w = 0; w < kWaves; w++) tot += s_w[w];
-        a.supsum[blockIdx.x] = tot;
+        supsum[c] = tot;
     }
 }
+
+__global__ __launch_bounds__(kThreads) void k_supsum(PrepArgs a) { supsum_one(a.tile_ones, a.ntiles, blockIdx.x, a.supsum); }
 
 // Sum of the counter slots q = g, g + step, ... of node v (loads batched).
 __device__ __forceinline__ unsigned long long slot_sum(const unsigned long long *ones, uint64_t nodes,
@@ -385,7 +396,9 @@ __device__ __forceinline__ unsigned long long slot_sum(const unsigned long long 
     return c;
 }
 
-__global__ __launch_bounds__(kThreads) void k_prep(PrepArgs a) {
+// Workgroup: superchunk prefixes, then (when plan_here) the node tables of
+// the level, kScanChunk nodes at a time.
+__device__ __forceinline__ void prep_level(const PrepArgs &a) {
     __shared__ unsigned long long s_w[kWaves];
     __shared__ unsigned long long s_n[kScanChunk];
     const uint32_t tid = threadIdx.x;
@@ -399,48 +412,55 @@ __global__ __launch_bounds__(kThreads) void k_prep(PrepArgs a) {
         carry += tot;
     }
     if (!a.plan_here) return;
-    // add up the node counter slots (nodes <= kScanChunk), then scan
     const PlanArgs &p = a.plan;
-    for (uint64_t v = tid; v < p.nodes; v += kThreads) s_n[v] = 0;
-    __syncthreads();
-    if (p.nodes >= kThreads) {
-        for (uint64_t v = tid; v < p.nodes; v += kThreads) s_n[v] = slot_sum(p.ones, p.nodes, p.slots, v, 0, 1);
-    } else {
-        // kThreads / nodes threads per node, then one LDS add per thread
-        const uint64_t groups = kThreads / p.nodes;
-        const uint64_t v = tid % p.nodes, g = tid / p.nodes;
-        const unsigned long long c = slot_sum(p.ones, p.nodes, p.slots, v, g, groups);
-        if (c) atomicAdd(&s_n[v], c);
+    unsigned long long before = 0;
+    for (uint64_t b0 = 0; b0 < p.nodes; b0 += kScanChunk) {
+        // add up the node counter slots of this chunk, then scan it
+        const uint64_t cn = (p.nodes - b0 < kScanChunk) ? p.nodes - b0 : kScanChunk;
+        for (uint64_t v = tid; v < cn; v += kThreads) s_n[v] = 0;
+        __syncthreads();
+        if (cn >= kThreads) {
+            for (uint64_t v = tid; v < cn; v += kThreads) s_n[v] = slot_sum(p.ones, p.nodes, p.slots, b0 + v, 0, 1);
+        } else {
+            // kThreads / nodes threads per node, then one LDS add per thread
+            const uint64_t groups = kThreads / cn;
+            const uint64_t v = tid % cn, g = tid / cn;
+            const unsigned long long c = slot_sum(p.ones, p.nodes, p.slots, b0 + v, g, groups);
+            if (c) atomicAdd(&s_n[v], c);
+        }
+        __syncthreads();
+        before += plan_chunk(p, s_n, b0, before);
+        __syncthreads();
     }
-    __syncthreads();
-    plan_chunk(p, s_n, 0, 0ull);
 }
+
+__global__ __launch_bounds__(kThreads) void k_prep(PrepArgs a) { prep_level(a); }
 
 // ----------------------------------------------------------- level pass ---
 
-// One level pass.  Every wave owns one tile of TILE consecutive positions of
-// T_i (each lane 64 bytes = E symbols); there is no workgroup barrier.
+// LDS bytes of one wave of a level pass: staging of the split (zeros at
+// [a0, a0+Z), ones at [a1, a1+O) with a1 + O <= TILE + 3*CH - 3), or, for
+// tiles spanning several nodes, next-level counters per (node, bit,
+// destination-tile parity).
 template <int W>
-__global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
+__host__ __device__ constexpr uint32_t level_wave_bytes() {
+    return ((uint32_t)(tile_syms(W) + 4 * (16 / W)) * W > 2u * 4u * kNodeCap * 4u)
+               ? (uint32_t)(tile_syms(W) + 4 * (16 / W)) * W
+               : 2u * 4u * kNodeCap * 4u;
+}
+
+// One level pass over tile t, run by one wave (each lane 64 bytes = E
+// symbols of T_i); s_wave is the wave's own LDS slice.  No workgroup barrier.
+template <int W>
+__device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8_t *s_wave) {
     typedef typename ElemT<W>::T T;
     constexpr int E = 64 / W;                 // symbols per lane
     constexpr int CH = 16 / W;                // symbols per 16-byte chunk
     constexpr uint64_t TILE = tile_syms(W);   // 64 * E
     typedef typename MaskT<E>::T M;
-    // per wave: staging of the split (zeros at [a0, a0+Z), ones at [a1, a1+O)
-    // with a1 + O <= TILE + 3*CH - 3), or, for tiles spanning several nodes,
-    // next-level counters per (node, bit, destination-tile parity)
-    constexpr uint32_t kStageBytes = (uint32_t)(TILE + 4 * CH) * W;
-    constexpr uint32_t kCntBytes = 2u * 4u * kNodeCap * 4u;
-    constexpr uint32_t kWaveBytes = (kStageBytes > kCntBytes ? kStageBytes : kCntBytes);
-    __shared__ __align__(16) uint8_t s_all[kWaves * kWaveBytes];
-
     const int lane = threadIdx.x & 63;
-    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint64_t t = (uint64_t)blockIdx.x * kWaves + wv;
-    if (t >= a.ntiles) return;  // whole wave
-    T *s_stage = reinterpret_cast<T *>(s_all + wv * kWaveBytes);
-    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_all + wv * kWaveBytes);
+    T *s_stage = reinterpret_cast<T *>(s_wave);
+    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_wave);
     uint32_t *s_tix = s_cnt + 4 * kNodeCap;
 
     const uint32_t sh = a.levels - 1 - a.level;  // bit of this level
@@ -625,6 +645,140 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
     }
 }
 
+
+template <int W>
+__global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
+    __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W>()];
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t t = (uint64_t)blockIdx.x * kWaves + wv;
+    if (t >= a.ntiles) return;  // whole wave
+    level_tile<W>(a, t, s_all + wv * level_wave_bytes<W>());
+}
+
+// ------------------------------------------------------------ batched ---
+// A batched build runs the same per-tile work for many sequences, one launch
+// per phase and width class: workgroup b of a tile kernel serves sequence
+// blk_map[b], tiles (b - blk_base) * kWaves + wave.
+
+__device__ __forceinline__ LevelArgs job_level(const BatchJob &j, uint32_t i) {
+    LevelArgs a;
+    const uint32_t l = j.levels;
+    uint8_t *w = j.work;
+    a.tin = (i == 0) ? j.S : (const void *)(w + (((i - 1) & 1) ? j.ws_tb : j.ws_ta));
+    a.tout = (i + 1 < l) ? (void *)(w + ((i & 1) ? j.ws_tb : j.ws_ta)) : nullptr;
+    a.bits = reinterpret_cast<uint64_t *>(j.tree + j.tree_bits_off) + (uint64_t)i * j.words;
+    a.ranks = reinterpret_cast<uint64_t *>(j.tree + j.tree_ranks_off) + (uint64_t)i * j.rank_stride;
+    a.zo = reinterpret_cast<const ulonglong2 *>(w + j.ws_zo) + zo_offset(i);
+    uint32_t *tile_ones = reinterpret_cast<uint32_t *>(w + j.ws_tile_ones);
+    a.tile_ones = tile_ones + (uint64_t)i * j.ntiles;
+    a.sup = reinterpret_cast<const unsigned long long *>(w + j.ws_sup) + (uint64_t)i * j.nsup;
+    a.tile_ones_next = (i + 1 < l) ? tile_ones + (uint64_t)(i + 1) * j.ntiles : nullptr;
+    a.ones_next = (i + 1 < l) ? reinterpret_cast<unsigned long long *>(w + j.ws_ones) + ones_offset(i + 1) : nullptr;
+    a.nodes_next = 2ull << i;
+    a.slots_next = level_slots(i + 1);
+    a.n = j.n;
+    a.words = j.words;
+    a.rank_entries = j.rank_entries;
+    a.rank_stride = j.rank_stride;
+    a.ntiles = j.ntiles;
+    a.levels = l;
+    a.level = i;
+    a.symmask = (uint32_t)((1ull << l) - 1);
+    return a;
+}
+
+__device__ __forceinline__ PrepArgs job_prep(const BatchJob &j, uint32_t i) {
+    PrepArgs p;
+    uint8_t *w = j.work;
+    p.tile_ones = reinterpret_cast<const uint32_t *>(w + j.ws_tile_ones) + (uint64_t)i * j.ntiles;
+    p.supsum = reinterpret_cast<unsigned long long *>(w + j.ws_supsum);
+    p.sup = reinterpret_cast<unsigned long long *>(w + j.ws_sup) + (uint64_t)i * j.nsup;
+    p.ntiles = j.ntiles;
+    p.nsup = j.nsup;
+    uint64_t *start = reinterpret_cast<uint64_t *>(w + j.ws_start);
+    p.plan.start = start + start_offset(i);
+    p.plan.ones = reinterpret_cast<const unsigned long long *>(w + j.ws_ones) + ones_offset(i);
+    p.plan.zo = reinterpret_cast<ulonglong2 *>(w + j.ws_zo) + zo_offset(i);
+    p.plan.start_next = (i + 1 < j.levels) ? start + start_offset(i + 1) : nullptr;
+    p.plan.partials = nullptr;
+    p.plan.nodes = 1ull << i;
+    p.plan.slots = level_slots(i);
+    p.plan.n = j.n;
+    p.plan_here = 1u;
+    return p;
+}
+
+__device__ __forceinline__ IngestArgs job_ingest(const BatchJob &j) {
+    IngestArgs a;
+    uint8_t *w = j.work;
+    a.S = j.S;
+    a.tile_ones0 = j.levels ? reinterpret_cast<uint32_t *>(w + j.ws_tile_ones) : nullptr;
+    a.ones0 = reinterpret_cast<unsigned long long *>(w + j.ws_ones);
+    a.start0 = j.levels ? reinterpret_cast<uint64_t *>(w + j.ws_start) : nullptr;
+    a.tree_status = reinterpret_cast<uint32_t *>(j.tree);
+    a.n = j.n;
+    a.ntiles = j.ntiles;
+    a.tiles_per_block = kWaves;
+    a.slots0 = level_slots(0);
+    a.sigma = j.sigma;
+    a.check = j.check;
+    a.msb = j.levels ? j.levels - 1 : 0;
+    return a;
+}
+
+// Workgroup j: fill the maps of sequence j, then clear its control area and
+// tree status (and, for an empty sequence, its rank directories).
+__global__ __launch_bounds__(kThreads) void k_batch_setup(BatchClass c) {
+    const BatchJob &j = c.jobs[blockIdx.x];
+    const uint64_t nb = ceil_div(j.ntiles, kWaves);
+    for (uint64_t b = threadIdx.x; b < nb; b += kThreads) c.blk_map[j.blk_base + b] = blockIdx.x;
+    for (uint64_t b = threadIdx.x; b < j.nsup; b += kThreads) c.sup_map[j.sup_base + b] = blockIdx.x;
+    uint64_t *ctrl = reinterpret_cast<uint64_t *>(j.work + j.ws_ctrl);
+    for (uint64_t k = threadIdx.x; k < j.ws_ctrl_bytes / 8; k += kThreads) ctrl[k] = 0;
+    if (j.n == 0) {
+        uint64_t *r = reinterpret_cast<uint64_t *>(j.tree + j.tree_ranks_off);
+        for (uint64_t k = threadIdx.x; k < (uint64_t)j.levels * j.rank_stride; k += kThreads) r[k] = 0;
+    }
+    if (threadIdx.x == 0) *reinterpret_cast<uint32_t *>(j.tree) = 0;
+}
+
+template <int W>
+__global__ __launch_bounds__(kThreads) void k_batch_ingest(BatchClass c) {
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const BatchJob &j = c.jobs[c.blk_map[blockIdx.x]];
+    const uint64_t blk = blockIdx.x - j.blk_base;
+    const IngestArgs a = job_ingest(j);
+    if (blk == 0 && threadIdx.x == 0 && a.start0) {
+        a.start0[0] = 0;
+        a.start0[1] = a.n;
+    }
+    const uint64_t t = blk * kWaves + wv;
+    if (t >= j.ntiles) return;  // whole wave
+    bool bad = false;
+    const uint32_t ones = ingest_tile<W>(a, t, bad);
+    ingest_finish(a, bad, ones, t);
+}
+
+__global__ __launch_bounds__(kThreads) void k_batch_supsum(BatchClass c, uint32_t level) {
+    const BatchJob &j = c.jobs[c.sup_map[blockIdx.x]];
+    const uint32_t *tile_ones = reinterpret_cast<const uint32_t *>(j.work + j.ws_tile_ones) + (uint64_t)level * j.ntiles;
+    supsum_one(tile_ones, j.ntiles, blockIdx.x - j.sup_base, reinterpret_cast<unsigned long long *>(j.work + j.ws_supsum));
+}
+
+__global__ __launch_bounds__(kThreads) void k_batch_prep(BatchClass c, uint32_t level) {
+    prep_level(job_prep(c.jobs[blockIdx.x], level));
+}
+
+template <int W>
+__global__ __launch_bounds__(kThreads) void k_batch_level(BatchClass c, uint32_t level) {
+    __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W>()];
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const BatchJob &j = c.jobs[c.blk_map[blockIdx.x]];
+    const uint64_t t = (blockIdx.x - j.blk_base) * kWaves + wv;
+    if (t >= j.ntiles) return;  // whole wave
+    level_tile<W>(job_level(j, level), t, s_all + wv * level_wave_bytes<W>());
+}
+
 }  // namespace
 
 // ------------------------------------------------------------- launchers --
@@ -672,6 +826,38 @@ hipError_t launch_level(const LevelArgs &a, uint32_t width, hipStream_t s) {
     if (width == 1) hipLaunchKernelGGL(k_level<1>, g, dim3(kThreads), 0, s, a);
     else if (width == 2) hipLaunchKernelGGL(k_level<2>, g, dim3(kThreads), 0, s, a);
     else hipLaunchKernelGGL(k_level<4>, g, dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_setup(const BatchClass &c, uint64_t blocks, uint64_t sups, hipStream_t s) {
+    (void)blocks;
+    (void)sups;
+    hipLaunchKernelGGL(k_batch_setup, dim3(c.njobs), dim3(kThreads), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_ingest(const BatchClass &c, uint32_t width, uint64_t blocks, hipStream_t s) {
+    if (blocks == 0) return hipSuccess;
+    const dim3 g((uint32_t)blocks);
+    if (width == 1) hipLaunchKernelGGL(k_batch_ingest<1>, g, dim3(kThreads), 0, s, c);
+    else if (width == 2) hipLaunchKernelGGL(k_batch_ingest<2>, g, dim3(kThreads), 0, s, c);
+    else hipLaunchKernelGGL(k_batch_ingest<4>, g, dim3(kThreads), 0, s, c);
+    return hipGetLastError();
+}
+
+// Level `level` of the first `active` sequences of the class: superchunk
+// sums, prefixes and node tables, then the level pass.
+hipError_t launch_batch_level(const BatchClass &c, uint32_t width, uint32_t level, uint32_t active,
+                              uint64_t blocks, uint64_t sups, hipStream_t s) {
+    if (active == 0) return hipSuccess;
+    if (sups) hipLaunchKernelGGL(k_batch_supsum, dim3((uint32_t)sups), dim3(kThreads), 0, s, c, level);
+    hipLaunchKernelGGL(k_batch_prep, dim3(active), dim3(kThreads), 0, s, c, level);
+    if (blocks) {
+        const dim3 g((uint32_t)blocks);
+        if (width == 1) hipLaunchKernelGGL(k_batch_level<1>, g, dim3(kThreads), 0, s, c, level);
+        else if (width == 2) hipLaunchKernelGGL(k_batch_level<2>, g, dim3(kThreads), 0, s, c, level);
+        else hipLaunchKernelGGL(k_batch_level<4>, g, dim3(kThreads), 0, s, c, level);
+    }
     return hipGetLastError();
 }
 

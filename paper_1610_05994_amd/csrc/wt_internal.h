@@ -112,6 +112,38 @@ struct PrepArgs {
     uint32_t plan_here;                  // node tables built here (levels up to kScanChunk nodes)
 };
 
+// One sequence of a batched build as the batch kernels see it (its layout,
+// with the per-level table offsets derived on the device).
+struct BatchJob {
+    const void *S;
+    uint8_t *tree;
+    uint8_t *work;
+    uint64_t n, words, rank_entries, rank_stride, ntiles, nsup;
+    uint64_t tree_bits_off, tree_ranks_off;
+    uint64_t ws_ta, ws_tb, ws_ctrl, ws_ctrl_bytes, ws_tile_ones, ws_ones, ws_sup, ws_supsum, ws_zo, ws_start;
+    uint64_t blk_base;  // first workgroup of this sequence in its class's tile map
+    uint64_t sup_base;  // first workgroup of this sequence in its class's superchunk map
+    uint32_t sigma, width, levels, check;
+};
+
+// Sequences that share one symbol width, sorted by level count (descending),
+// so the sequences still building level i are always a prefix.
+struct BatchClass {
+    const BatchJob *jobs;
+    uint32_t *blk_map;  // tile workgroup -> sequence
+    uint32_t *sup_map;  // superchunk workgroup -> sequence
+    uint32_t njobs;
+};
+
+// Per-level table offsets (entries) shared by the host layout and the device.
+__host__ __device__ constexpr uint64_t zo_offset(uint32_t i) { return (1ull << i) - 1; }
+__host__ __device__ constexpr uint64_t start_offset(uint32_t i) { return (1ull << i) - 1 + i; }
+__host__ __device__ inline uint64_t ones_offset(uint32_t i) {
+    uint64_t e = 0;
+    for (uint32_t k = 0; k < i; k++) e += level_slots(k) << k;
+    return e;
+}
+
 // kernel launchers (wt_build.hip)
 hipError_t launch_zero(void *p, uint64_t bytes, uint32_t *tree_status, uint64_t *tree_ranks,
                        uint64_t tree_ranks_count, hipStream_t s);
@@ -119,6 +151,10 @@ hipError_t launch_ingest(const IngestArgs &a, uint32_t width, hipStream_t s);
 hipError_t launch_prep(const PrepArgs &a, hipStream_t s);  // k_supsum, then k_prep
 hipError_t launch_plan(const PlanArgs &a, hipStream_t s);
 hipError_t launch_level(const LevelArgs &a, uint32_t width, hipStream_t s);
+hipError_t launch_batch_setup(const BatchClass &c, uint64_t blocks, uint64_t sups, hipStream_t s);
+hipError_t launch_batch_ingest(const BatchClass &c, uint32_t width, uint64_t blocks, hipStream_t s);
+hipError_t launch_batch_level(const BatchClass &c, uint32_t width, uint32_t level, uint32_t active,
+                              uint64_t blocks, uint64_t sups, hipStream_t s);
 
 // query launchers (wt_query.hip)
 struct TreeView {

@@ -219,6 +219,48 @@ def test_batch_matches_oracle():
         t.close()
 
 
+def test_batch_mixed_widths_and_edge_sequences():
+    """Batched build of sequences that mix widths, empty and tiny inputs,
+    sigma = 1, and alphabets whose deep levels exceed one node chunk; every
+    tree equals the oracle and the single-sequence build."""
+    import torch
+    wt = _wt()
+    rng = np.random.Generator(np.random.PCG64(77))
+    cases = [(0, 4, 1), (1, 2, 1), (3000, 1, 1), (4095, 20, 1), (70_001, 256, 1), (5000, 1 << 16, 2),
+             (40_000, 1 << 15, 2), (9, 3, 2), (70_000, 1 << 20, 4), (2049, 1000, 4), (0, 1 << 20, 4),
+             (123_457, 27, 1), (64, 1 << 13, 2)]
+    Ss = [wtgen.zipf(n, sg, 1.0, 1000 + k, w) if n else np.zeros(0, wtgen.dtype_for(w))
+          for k, (n, sg, w) in enumerate(cases)]
+    _say("case batch-mixed: %d sequences" % len(Ss))
+    dev = [wt.to_device(S, _dev()) for S in Ss]
+    trees = wt.build_batch(dev, [c[1] for c in cases], [c[2] for c in cases])
+    for (n, sg, w), S, d, t in zip(cases, Ss, dev, trees):
+        assert t.status() == wt.WT_OK, (n, sg, w)
+        ref = oracle.build(S, sg)
+        assert tc.compare_levels(t.bitmaps(), ref.bitmaps) is None, (n, sg, w)
+        assert tc.compare_levels(t.ranks(), ref.ranks, "rank") is None, (n, sg, w)
+        single = wt.build(d, sg, width=w)
+        assert np.array_equal(single.bitmaps(), t.bitmaps()) and np.array_equal(single.ranks(), t.ranks())
+        single.close()
+        if n:
+            pos = torch.from_numpy(rng.integers(0, n, 256)).to(_dev())
+            acc = t.access(pos).cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+            assert np.array_equal(acc, S[pos.cpu().numpy()].astype(np.int64))
+        t.close()
+
+
+def test_batch_reports_out_of_range_per_sequence():
+    wt = _wt()
+    A = wtgen.uniform(5000, 16, 1)
+    B = wtgen.uniform(7000, 16, 2)
+    B[6999] = 16
+    trees = wt.build_batch([wt.to_device(A, _dev()), wt.to_device(B, _dev())], [16, 16], [1, 1])
+    assert trees[0].status() == wt.WT_OK
+    assert trees[1].status() == wt.WT_ERANGE
+    for t in trees:
+        t.close()
+
+
 @pytest.mark.slow
 def test_full_size_c2_against_oracle():
     S, sigma = wtgen.workload("c2")
