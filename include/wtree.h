@@ -157,6 +157,22 @@ int wt_select(const wt_tree *tree, uint32_t c, uint64_t j, uint64_t *pos);
 /* Static text for a status code. */
 const char *wt_strerror(int status);
 
+/*
+ * Tile geometry of the level pass (the segment size of the domain
+ * decomposition, Section 3.2, here the unit of work of one wavefront: 64
+ * lanes x lane_bytes bytes of symbols).  lane_bytes is 32, 64 or 128 with
+ * lane_bytes / width <= 64; 0 restores the default (64).  The setting is kept
+ * per (mode, width, levels, floor(lg n)) for the whole process -- mode 0 for
+ * wt_footprint / wt_build, mode 1 for a sequence of wt_batch_footprint /
+ * wt_build_batch; 1 <= levels <= min(24, 8 * width), lg_n <= 40 -- and read
+ * whenever a layout is computed.  The tree does not depend on it (every
+ * geometry builds the same bits); the workspace size does, so change it only
+ * between builds and take footprints after the change.  Not thread-safe
+ * against concurrent builds.  WT_EINVAL for an invalid key or value.
+ */
+int wt_tune_set(uint32_t mode, uint32_t width, uint32_t levels, uint32_t lg_n, uint32_t lane_bytes);
+int wt_tune_get(uint32_t mode, uint32_t width, uint32_t levels, uint32_t lg_n, uint32_t *lane_bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -72,7 +72,29 @@ static void prof_end(long idx, hipStream_t st) {
     if ((size_t)idx < g_prof.size()) (void)hipEventRecord(g_prof[idx].b, st);
 }
 
-void make_layout(uint64_t n, uint32_t sigma, uint32_t width, Layout *L) {
+// ---------------------------------------------------------- tuning table --
+// Bytes per lane of the tile geometry, per (mode: single or batched build,
+// width class, levels, floor lg n); 0 = the default.  Filled by wt_tune_set
+// (the autotuner writes a table that the Python binding loads); read by every
+// layout computation, so a footprint and the build that uses it must see the
+// same table.
+static uint8_t g_tune[2][3][25][41];
+
+static int wclass(uint32_t w) { return w == 1 ? 0 : (w == 2 ? 1 : 2); }
+static uint32_t floor_lg(uint64_t n) {
+    uint32_t k = 0;
+    while (k < 40 && (2ull << k) <= n) k++;
+    return k;
+}
+
+uint32_t tuned_lane_bytes(uint64_t n, uint32_t sigma, uint32_t width, bool batched) {
+    const uint32_t l = levels_for(sigma);
+    const uint8_t v = g_tune[batched ? 1 : 0][wclass(width)][l < 25 ? l : 24][floor_lg(n)];
+    const uint32_t lb = v ? (uint32_t)v * 32 : kDefaultLaneBytes;
+    return lane_bytes_valid(width, lb) ? lb : kDefaultLaneBytes;
+}
+
+void make_layout(uint64_t n, uint32_t sigma, uint32_t width, bool batched, Layout *L) {
     memset(L, 0, sizeof(*L));
     const uint32_t l = levels_for(sigma);
     L->n = n;
@@ -82,7 +104,8 @@ void make_layout(uint64_t n, uint32_t sigma, uint32_t width, Layout *L) {
     L->words = round_up(ceil_div(n, 64), 8);
     L->rank_entries = ceil_div(n, 512) + 1;
     L->rank_stride = round_up(L->rank_entries, 8);
-    L->ntiles = ceil_div(n, tile_syms(width));
+    L->lane_bytes = tuned_lane_bytes(n, sigma, width, batched);
+    L->ntiles = ceil_div(n, tile_syms(width, L->lane_bytes));
     L->nsup = ceil_div(L->ntiles, kSup);
 
     L->tree_bits_off = kHeaderBytes;
@@ -162,7 +185,7 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         ia.tiles_per_block = k;
     }
     pr = prof_begin(st, "ingest", 0, L.width, L.n, L.n * L.width);
-    err = launch_ingest(ia, L.width, st);
+    err = launch_ingest(ia, L.width, L.lane_bytes, st);
     prof_end(pr, st);
     if (err != hipSuccess) return err;
     if (l == 0) return hipSuccess;
@@ -220,7 +243,7 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         a.symmask = (uint32_t)((1ull << l) - 1);
         const uint64_t lbytes = L.n * L.width * (a.tout ? 2 : 1) + L.words * 8 + L.rank_stride * 8;
         pr = prof_begin(st, "level", i, L.width, L.n, lbytes);
-        err = launch_level(a, L.width, st);
+        err = launch_level(a, L.width, L.lane_bytes, st);
         prof_end(pr, st);
         if (err != hipSuccess) return err;
     }
@@ -262,28 +285,32 @@ static wt_tree *new_handle(const Layout &L, void *tree, hipStream_t st) {
 }
 
 // Batched-build workspace: job descriptors, block maps, then one workspace
-// slice per sequence.
+// slice per sequence.  Sequences are grouped by (width, lane bytes).
+constexpr int kClasses = 9;
+static int batch_class(uint32_t w, uint32_t lb) { return wclass(w) * 3 + (lb == 32 ? 0 : (lb == 64 ? 1 : 2)); }
+static const uint32_t kClassWidth[kClasses] = {1, 1, 1, 2, 2, 2, 4, 4, 4};
+static const uint32_t kClassLane[kClasses] = {32, 64, 128, 32, 64, 128, 32, 64, 128};
+
 struct BatchPlan {
     std::vector<Layout> L;
-    std::vector<uint32_t> order[3];  // per width class (1, 2, 4 bytes): sequences by levels, descending
-    uint64_t jobs_off, map_off[3], sup_off[3], slices_off, total;
+    // per class (width, lane bytes): sequences by levels, descending
+    std::vector<uint32_t> order[kClasses];
+    uint64_t jobs_off, map_off[kClasses], sup_off[kClasses], slices_off, total;
     std::vector<uint64_t> slice;     // workspace offset of each sequence's slice
-    uint64_t blocks[3], sups[3];
+    uint64_t blocks[kClasses], sups[kClasses];
 };
-
-static int width_class(uint32_t w) { return w == 1 ? 0 : (w == 2 ? 1 : 2); }
 
 static int plan_batch(uint32_t m, const wt_desc *descs, BatchPlan *P) {
     P->L.resize(m);
     for (uint32_t q = 0; q < m; q++) {
         int rc = check_desc(&descs[q]);
         if (rc != WT_OK) return rc;
-        make_layout(descs[q].n, descs[q].sigma, descs[q].width, &P->L[q]);
-        P->order[width_class(descs[q].width)].push_back(q);
+        make_layout(descs[q].n, descs[q].sigma, descs[q].width, true, &P->L[q]);
+        P->order[batch_class(descs[q].width, P->L[q].lane_bytes)].push_back(q);
     }
     uint64_t off = round_up((uint64_t)m * sizeof(BatchJob), 256);
     P->jobs_off = 0;
-    for (int c = 0; c < 3; c++) {
+    for (int c = 0; c < kClasses; c++) {
         std::vector<uint32_t> &o = P->order[c];
         std::stable_sort(o.begin(), o.end(), [&](uint32_t x, uint32_t y) { return P->L[x].levels > P->L[y].levels; });
         uint64_t nb = 0, ns = 0;
@@ -336,6 +363,7 @@ static BatchJob make_job(const Layout &L, const void *S, void *tree, uint8_t *wo
     j.width = L.width;
     j.levels = L.levels;
     j.check = (L.width < 4 && (uint64_t)L.sigma == (1ull << (8 * L.width))) ? 0u : 1u;
+    j.lane_bytes = L.lane_bytes;
     return j;
 }
 
@@ -349,7 +377,7 @@ int wt_footprint(const wt_desc *desc, uint64_t *tree_bytes, uint64_t *work_bytes
     int rc = check_desc(desc);
     if (rc != WT_OK) return rc;
     Layout L;
-    make_layout(desc->n, desc->sigma, desc->width, &L);
+    make_layout(desc->n, desc->sigma, desc->width, false, &L);
     if (tree_bytes) *tree_bytes = L.tree_bytes;
     if (work_bytes) *work_bytes = L.work_bytes;
     return WT_OK;
@@ -363,7 +391,7 @@ int wt_build(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t tree_b
     if (!out || !d_tree || !d_work || (desc->n > 0 && !d_S)) return WT_EINVAL;
     if (((uintptr_t)d_S & 15) || ((uintptr_t)d_tree & 255) || ((uintptr_t)d_work & 255)) return WT_EINVAL;
     Layout L;
-    make_layout(desc->n, desc->sigma, desc->width, &L);
+    make_layout(desc->n, desc->sigma, desc->width, false, &L);
     if (tree_bytes < L.tree_bytes || work_bytes < L.work_bytes) return WT_ENOMEM;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     wt_tree *h = new_handle(L, d_tree, st);
@@ -407,9 +435,9 @@ int wt_build_batch(uint32_t m, const void *const *d_S, const wt_desc *descs, voi
     // job descriptors, class by class (levels descending inside a class)
     std::vector<BatchJob> jobs;
     jobs.reserve(m);
-    uint32_t first[3];
+    uint32_t first[kClasses];
     uint32_t maxl = 0;
-    for (int c = 0; c < 3; c++) {
+    for (int c = 0; c < kClasses; c++) {
         first[c] = (uint32_t)jobs.size();
         uint64_t blk = 0, sup = 0;
         for (uint32_t q : P.order[c]) {
@@ -427,31 +455,31 @@ int wt_build_batch(uint32_t m, const void *const *d_S, const wt_desc *descs, voi
     if (hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(BatchJob), hipMemcpyHostToDevice, st) != hipSuccess)
         return WT_EDEVICE;
 
-    BatchClass cls[3];
-    for (int c = 0; c < 3; c++) {
+    BatchClass cls[kClasses];
+    for (int c = 0; c < kClasses; c++) {
         cls[c].jobs = d_jobs + first[c];
         cls[c].blk_map = reinterpret_cast<uint32_t *>(work + P.map_off[c]);
         cls[c].sup_map = reinterpret_cast<uint32_t *>(work + P.sup_off[c]);
         cls[c].njobs = (uint32_t)P.order[c].size();
     }
-    static const uint32_t widths[3] = {1, 2, 4};
+    const uint32_t *widths = kClassWidth;
     hipError_t err = hipSuccess;
-    for (int c = 0; c < 3 && err == hipSuccess; c++) {
+    for (int c = 0; c < kClasses && err == hipSuccess; c++) {
         if (!cls[c].njobs) continue;
         long pr = prof_begin(st, "batch_setup", 0, widths[c], 0, 0);
         err = launch_batch_setup(cls[c], P.blocks[c], P.sups[c], st);
         prof_end(pr, st);
     }
-    for (int c = 0; c < 3 && err == hipSuccess; c++) {
+    for (int c = 0; c < kClasses && err == hipSuccess; c++) {
         if (!cls[c].njobs) continue;
         uint64_t nsym = 0;
         for (uint32_t q : P.order[c]) nsym += P.L[q].n;
         long pr = prof_begin(st, "batch_ingest", 0, widths[c], nsym, nsym * widths[c]);
-        err = launch_batch_ingest(cls[c], widths[c], P.blocks[c], st);
+        err = launch_batch_ingest(cls[c], widths[c], kClassLane[c], P.blocks[c], st);
         prof_end(pr, st);
     }
     for (uint32_t i = 0; i < maxl && err == hipSuccess; i++) {
-        for (int c = 0; c < 3 && err == hipSuccess; c++) {
+        for (int c = 0; c < kClasses && err == hipSuccess; c++) {
             // the sequences still building level i are a prefix of the class
             uint32_t active = 0;
             uint64_t blocks = 0, sups = 0, nsym = 0, bytes = 0;
@@ -466,7 +494,7 @@ int wt_build_batch(uint32_t m, const void *const *d_S, const wt_desc *descs, voi
             }
             if (!active) continue;
             long pr = prof_begin(st, "batch_level", i, widths[c], nsym, bytes);
-            err = launch_batch_level(cls[c], widths[c], i, active, blocks, sups, st);
+            err = launch_batch_level(cls[c], widths[c], kClassLane[c], i, active, blocks, sups, st);
             prof_end(pr, st);
         }
     }
@@ -570,6 +598,26 @@ int wt_select(const wt_tree *t, uint32_t c, uint64_t j, uint64_t *pos) {
     if (rc != WT_OK) return rc;
     if (a == ~0ull) return WT_ENOTFOUND;
     *pos = a;
+    return WT_OK;
+}
+
+static bool tune_key_ok(uint32_t mode, uint32_t width, uint32_t levels, uint32_t lg_n) {
+    return mode <= 1 && (width == 1 || width == 2 || width == 4) && levels >= 1 && levels <= 24 &&
+           levels <= 8 * width && lg_n <= 40;
+}
+
+int wt_tune_set(uint32_t mode, uint32_t width, uint32_t levels, uint32_t lg_n, uint32_t lane_bytes) {
+    if (!tune_key_ok(mode, width, levels, lg_n)) return WT_EINVAL;
+    if (lane_bytes != 0 && !lane_bytes_valid(width, lane_bytes)) return WT_EINVAL;
+    g_tune[mode][wclass(width)][levels][lg_n] = (uint8_t)(lane_bytes / 32);
+    return WT_OK;
+}
+
+int wt_tune_get(uint32_t mode, uint32_t width, uint32_t levels, uint32_t lg_n, uint32_t *lane_bytes) {
+    if (!tune_key_ok(mode, width, levels, lg_n) || !lane_bytes) return WT_EINVAL;
+    const uint8_t v = g_tune[mode][wclass(width)][levels][lg_n];
+    *lane_bytes = v ? (uint32_t)v * 32 : kDefaultLaneBytes;
+    if (!lane_bytes_valid(width, *lane_bytes)) *lane_bytes = kDefaultLaneBytes;
     return WT_OK;
 }
 

@@ -105,37 +105,38 @@ __device__ __forceinline__ uint32_t chunk_elem(const uint4 &v, int e) {
     return (W == 4) ? d : ((d >> (8 * ((e * W) & 3))) & ((1u << (8 * W)) - 1u));
 }
 
-// Symbol k (0 <= k < 64/W) of one thread's 64 bytes.
-template <int W>
-__device__ __forceinline__ uint32_t raw_elem(const uint4 (&raw)[4], int k) {
+// Symbol k (0 <= k < B/W) of one lane's B bytes.
+template <int W, int B>
+__device__ __forceinline__ uint32_t raw_elem(const uint4 (&raw)[B / 16], int k) {
     return chunk_elem<W>(raw[k / (16 / W)], k % (16 / W));
 }
 
-// Load the 64/W symbols of one thread starting at position pos (a multiple
-// of 64/W, so full loads are 16-byte aligned).  Positions >= n read as 0;
+// Load the B/W symbols of one lane starting at position pos (a multiple of
+// B/W, so full loads are 16-byte aligned).  Positions >= n read as 0;
 // returns the number of symbols below n.
-template <int W>
-__device__ __forceinline__ int load64(const void *src, uint64_t pos, uint64_t n, uint4 (&raw)[4]) {
+template <int W, int B>
+__device__ __forceinline__ int load_lane(const void *src, uint64_t pos, uint64_t n, uint4 (&raw)[B / 16]) {
     typedef typename ElemT<W>::T T;
-    constexpr int E = 64 / W;
+    constexpr int E = B / W;
+    constexpr int Q = B / 16;
     const T *s = reinterpret_cast<const T *>(src);
     if (pos + E <= n) {
         const uint4 *p = reinterpret_cast<const uint4 *>(s + pos);
 #pragma unroll
-        for (int q = 0; q < 4; q++) raw[q] = p[q];
+        for (int q = 0; q < Q; q++) raw[q] = p[q];
         return E;
     }
     const int nval = pos < n ? (int)(n - pos) : 0;
-    uint32_t d[16];
+    uint32_t d[4 * Q];
 #pragma unroll
-    for (int q = 0; q < 16; q++) d[q] = 0;
+    for (int q = 0; q < 4 * Q; q++) d[q] = 0;
 #pragma unroll
     for (int k = 0; k < E; k++) {
         const uint32_t v = (k < nval) ? (uint32_t)s[pos + k] : 0u;
         d[(k * W) >> 2] |= (W == 4) ? v : (v << (8 * ((k * W) & 3)));
     }
 #pragma unroll
-    for (int q = 0; q < 4; q++) raw[q] = make_uint4(d[4 * q], d[4 * q + 1], d[4 * q + 2], d[4 * q + 3]);
+    for (int q = 0; q < Q; q++) raw[q] = make_uint4(d[4 * q], d[4 * q + 1], d[4 * q + 2], d[4 * q + 3]);
     return nval;
 }
 
@@ -156,7 +157,7 @@ __global__ void k_zero(uint64_t *p, uint64_t words, uint32_t *tree_status, uint6
 // most significant of the l bits) per tile and in total.  Every later
 // node count is produced by the level pass before it.
 
-template <int E> struct MaskT { typedef uint32_t T; };
+template <int E> struct MaskT { typedef uint32_t T; };  // E <= 32
 template <> struct MaskT<64> { typedef uint64_t T; };
 
 // Orders this wave's LDS accesses (a wave's LDS operations execute in order).
@@ -166,25 +167,26 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Level bits (bit sh) of one lane's E symbols, symbol k at bit k.
-template <int W>
-__device__ __forceinline__ typename MaskT<64 / W>::T level_bits(const uint4 (&raw)[4], uint32_t sh) {
-    typedef typename MaskT<64 / W>::T M;
+// Level bits (bit sh) of one lane's E = B/W symbols, symbol k at bit k.
+template <int W, int B>
+__device__ __forceinline__ typename MaskT<B / W>::T level_bits(const uint4 (&raw)[B / 16], uint32_t sh) {
+    typedef typename MaskT<B / W>::T M;
+    constexpr int D = B / 4;  // dwords per lane
     M mb = 0;
-    const uint32_t d[16] = {raw[0].x, raw[0].y, raw[0].z, raw[0].w, raw[1].x, raw[1].y, raw[1].z, raw[1].w,
-                            raw[2].x, raw[2].y, raw[2].z, raw[2].w, raw[3].x, raw[3].y, raw[3].z, raw[3].w};
 #pragma unroll
-    for (int q = 0; q < 16; q++) {
+    for (int q = 0; q < D; q++) {
+        const uint4 &c = raw[q / 4];
+        const uint32_t d = (q % 4 == 0) ? c.x : (q % 4 == 1) ? c.y : (q % 4 == 2) ? c.z : c.w;
         if (W == 1) {
             // gather bit sh of the four bytes into a nibble (no carries: the
             // sixteen partial products land on distinct bits)
-            const uint32_t nib = (((d[q] >> sh) & 0x01010101u) * 0x10204080u) >> 28;
+            const uint32_t nib = (((d >> sh) & 0x01010101u) * 0x10204080u) >> 28;
             mb |= (M)nib << (4 * q);
         } else if (W == 2) {
-            const uint32_t two = ((d[q] >> sh) & 1u) | (((d[q] >> (16 + sh)) & 1u) << 1);
+            const uint32_t two = ((d >> sh) & 1u) | (((d >> (16 + sh)) & 1u) << 1);
             mb |= (M)two << (2 * q);
         } else {
-            mb |= (M)((d[q] >> sh) & 1u) << q;
+            mb |= (M)((d >> sh) & 1u) << q;
         }
     }
     return mb;
@@ -192,25 +194,26 @@ __device__ __forceinline__ typename MaskT<64 / W>::T level_bits(const uint4 (&ra
 
 // Stable split of one lane's symbols into LDS: zeros to zc, zc+1, ...,
 // ones to oc, oc+1, ...  kFull: all E symbols are valid (no guards).
-template <int W, bool kFull>
-__device__ __forceinline__ void stage_split(typename ElemT<W>::T *s_stage, const uint4 (&raw)[4],
-                                            typename MaskT<64 / W>::T mb, uint32_t zc, uint32_t oc, int nval) {
+template <int W, int B, bool kFull>
+__device__ __forceinline__ void stage_split(typename ElemT<W>::T *s_stage, const uint4 (&raw)[B / 16],
+                                            typename MaskT<B / W>::T mb, uint32_t zc, uint32_t oc, int nval) {
     typedef typename ElemT<W>::T T;
-    constexpr int E = 64 / W;
-    const uint32_t d[16] = {raw[0].x, raw[0].y, raw[0].z, raw[0].w, raw[1].x, raw[1].y, raw[1].z, raw[1].w,
-                            raw[2].x, raw[2].y, raw[2].z, raw[2].w, raw[3].x, raw[3].y, raw[3].z, raw[3].w};
+    constexpr int E = B / W;
 #pragma unroll
     for (int k = 0; k < E; k++) {
         if (kFull || k < nval) {
             const uint32_t b = (uint32_t)(mb >> k) & 1u;
             // slot = b ? oc : zc, as one 24-bit multiply-add (slots < 2^24)
             const uint32_t slot = __umul24(b, oc - zc) + zc;
+            const int q = (k * W) >> 2;
+            const uint4 &c = raw[q / 4];
+            const uint32_t d = (q % 4 == 0) ? c.x : (q % 4 == 1) ? c.y : (q % 4 == 2) ? c.z : c.w;
             // the store keeps the low W bytes of x (or, for the third byte of
             // a dword, the d16_hi form picks it), so no masking is needed
             uint32_t x;
-            if (W == 4) x = d[k];
-            else if (W == 2) x = (k & 1) ? (d[k >> 1] >> 16) : d[k >> 1];
-            else x = ((k & 3) == 1 || (k & 3) == 3) ? (d[k >> 2] >> 8) : d[k >> 2];
+            if (W == 4) x = d;
+            else if (W == 2) x = (k & 1) ? (d >> 16) : d;
+            else x = ((k & 3) == 1 || (k & 3) == 3) ? (d >> 8) : d;
             if (W == 1 && (k & 3) >= 2) x >>= 16;
             s_stage[slot] = (T)x;
             oc += b;
@@ -229,21 +232,21 @@ __device__ __forceinline__ uint32_t chunk_bit_count(const uint4 &v, uint32_t sh2
 
 // One tile of the ingest pass, run by one wave: returns the tile's level-0
 // ones (when they are counted) and sets bad if a symbol is >= sigma.
-template <int W>
+template <int W, int B>
 __device__ __forceinline__ uint32_t ingest_tile(const IngestArgs &a, uint64_t t, bool &bad) {
-    constexpr int E = 64 / W;
-    constexpr uint64_t TILE = tile_syms(W);
+    constexpr int E = B / W;
+    constexpr uint64_t TILE = tile_syms(W, B);
     const int lane = threadIdx.x & 63;
-    uint4 raw[4];
-    const int nval = load64<W>(a.S, t * TILE + (uint64_t)lane * E, a.n, raw);
+    uint4 raw[B / 16];
+    const int nval = load_lane<W, B>(a.S, t * TILE + (uint64_t)lane * E, a.n, raw);
     if (a.check) {
 #pragma unroll
-        for (int k = 0; k < E; k++) bad |= (k < nval) && (raw_elem<W>(raw, k) >= a.sigma);
+        for (int k = 0; k < E; k++) bad |= (k < nval) && (raw_elem<W, B>(raw, k) >= a.sigma);
     }
     uint32_t ones = 0;
     if (a.tile_ones0) {
         // symbols past n load as 0, so they add no ones
-        const typename MaskT<E>::T mb = level_bits<W>(raw, a.msb);
+        const typename MaskT<E>::T mb = level_bits<W, B>(raw, a.msb);
         ones = wave_sum32((E == 64) ? (uint32_t)__popcll((uint64_t)mb) : (uint32_t)__popc((uint32_t)mb));
         if (lane == 0) a.tile_ones0[t] = ones;
     }
@@ -258,7 +261,7 @@ __device__ __forceinline__ void ingest_finish(const IngestArgs &a, bool bad, uns
     if (a.tile_ones0 && lane == 0 && ones_acc) atomicAdd(&a.ones0[slot % a.slots0], ones_acc);
 }
 
-template <int W>
+template <int W, int B>
 __global__ __launch_bounds__(kThreads) void k_ingest(IngestArgs a) {
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (blockIdx.x == 0 && threadIdx.x == 0 && a.start0) {
@@ -270,7 +273,7 @@ __global__ __launch_bounds__(kThreads) void k_ingest(IngestArgs a) {
     const uint64_t t1 = (t0 + a.tiles_per_block < a.ntiles) ? t0 + a.tiles_per_block : a.ntiles;
     bool bad = false;
     unsigned long long ones_acc = 0;
-    for (uint64_t t = t0 + wv; t < t1; t += kWaves) ones_acc += ingest_tile<W>(a, t, bad);
+    for (uint64_t t = t0 + wv; t < t1; t += kWaves) ones_acc += ingest_tile<W, B>(a, t, bad);
     ingest_finish(a, bad, ones_acc, (uint64_t)blockIdx.x * kWaves + wv);
 }
 
@@ -442,21 +445,21 @@ __global__ __launch_bounds__(kThreads) void k_prep(PrepArgs a) { prep_level(a); 
 // [a0, a0+Z), ones at [a1, a1+O) with a1 + O <= TILE + 3*CH - 3), or, for
 // tiles spanning several nodes, next-level counters per (node, bit,
 // destination-tile parity).
-template <int W>
+template <int W, int B>
 __host__ __device__ constexpr uint32_t level_wave_bytes() {
-    return ((uint32_t)(tile_syms(W) + 4 * (16 / W)) * W > 2u * 4u * kNodeCap * 4u)
-               ? (uint32_t)(tile_syms(W) + 4 * (16 / W)) * W
+    return ((uint32_t)(tile_syms(W, B) + 4 * (16 / W)) * W > 2u * 4u * kNodeCap * 4u)
+               ? (uint32_t)(tile_syms(W, B) + 4 * (16 / W)) * W
                : 2u * 4u * kNodeCap * 4u;
 }
 
-// One level pass over tile t, run by one wave (each lane 64 bytes = E
+// One level pass over tile t, run by one wave (each lane B bytes = E = B/W
 // symbols of T_i); s_wave is the wave's own LDS slice.  No workgroup barrier.
-template <int W>
+template <int W, int B>
 __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8_t *s_wave) {
     typedef typename ElemT<W>::T T;
-    constexpr int E = 64 / W;                 // symbols per lane
-    constexpr int CH = 16 / W;                // symbols per 16-byte chunk
-    constexpr uint64_t TILE = tile_syms(W);   // 64 * E
+    constexpr int E = B / W;                    // symbols per lane
+    constexpr int CH = 16 / W;                  // symbols per 16-byte chunk
+    constexpr uint64_t TILE = tile_syms(W, B);  // 64 * E
     typedef typename MaskT<E>::T M;
     const int lane = threadIdx.x & 63;
     T *s_stage = reinterpret_cast<T *>(s_wave);
@@ -469,8 +472,8 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
     const uint64_t pos0 = base + (uint64_t)lane * E;
     const uint64_t nvalid = (a.n - base < TILE) ? a.n - base : TILE;  // base < n
 
-    uint4 raw[4];
-    const int nval = load64<W>(a.tin, pos0, a.n, raw);
+    uint4 raw[B / 16];
+    const int nval = load_lane<W, B>(a.tin, pos0, a.n, raw);
     // ones before the tile: superchunk prefix + earlier tiles of the superchunk
     uint32_t pv = 0;
     {
@@ -481,7 +484,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
     }
     unsigned long long prefix = a.sup[t / kSup];
 
-    const M mb = level_bits<W>(raw, sh);
+    const M mb = level_bits<W, B>(raw, sh);
     const uint32_t pc = (E == 64) ? (uint32_t)__popcll((uint64_t)mb) : (uint32_t)__popc((uint32_t)mb);
     const uint32_t incl = wave_incl_scan(pc);
     const uint32_t agg = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
@@ -514,16 +517,16 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
     // node span of the tile (T_i is sorted by node)
     const bool full = (nvalid == TILE);  // every tile but a ragged last one
     const uint32_t vf =
-        __builtin_amdgcn_readfirstlane(__shfl((raw_elem<W>(raw, 0) & a.symmask) >> nsh, 0, 64));
+        __builtin_amdgcn_readfirstlane(__shfl((raw_elem<W, B>(raw, 0) & a.symmask) >> nsh, 0, 64));
     uint32_t vl;
     if (full) {
-        vl = __shfl((raw_elem<W>(raw, E - 1) & a.symmask) >> nsh, 63, 64);
+        vl = __shfl((raw_elem<W, B>(raw, E - 1) & a.symmask) >> nsh, 63, 64);
     } else {
         const uint64_t last = nvalid - 1;
         const int kl = (int)(last % E);
         uint32_t xv = 0;
 #pragma unroll
-        for (int k = 0; k < E; k++) xv = (k == kl) ? raw_elem<W>(raw, k) : xv;
+        for (int k = 0; k < E; k++) xv = (k == kl) ? raw_elem<W, B>(raw, k) : xv;
         vl = __shfl((xv & a.symmask) >> nsh, (int)(last / E), 64);
     }
     vl = __builtin_amdgcn_readfirstlane(vl);
@@ -543,8 +546,8 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         const uint32_t a1 = r1 + (uint32_t)(g1 % CH);
         const uint32_t zc = a0 + (uint32_t)lane * E - lr1;  // first zero slot of this lane
         const uint32_t oc = a1 + lr1;                       // first one slot of this lane
-        if (full) stage_split<W, true>(s_stage, raw, mb, zc, oc, nval);
-        else stage_split<W, false>(s_stage, raw, mb, zc, oc, nval);
+        if (full) stage_split<W, B, true>(s_stage, raw, mb, zc, oc, nval);
+        else stage_split<W, B, false>(s_stage, raw, mb, zc, oc, nval);
         wave_sync();
         // next-level ones per (run, destination-tile parity): a run holds at
         // most TILE symbols, so it touches at most two consecutive tiles
@@ -609,7 +612,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
 #pragma unroll
     for (int k = 0; k < E; k++) {
         if (k < nval) {
-            const uint32_t x = raw_elem<W>(raw, k) & a.symmask;
+            const uint32_t x = raw_elem<W, B>(raw, k) & a.symmask;
             const uint32_t v = x >> nsh;
             const ulonglong2 zo = a.zo[v];
             const uint64_t p = pos0 + k;
@@ -646,13 +649,13 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
 }
 
 
-template <int W>
+template <int W, int B>
 __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
-    __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W>()];
+    __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W, B>()];
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t t = (uint64_t)blockIdx.x * kWaves + wv;
     if (t >= a.ntiles) return;  // whole wave
-    level_tile<W>(a, t, s_all + wv * level_wave_bytes<W>());
+    level_tile<W, B>(a, t, s_all + wv * level_wave_bytes<W, B>());
 }
 
 // ------------------------------------------------------------ batched ---
@@ -742,7 +745,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_setup(BatchClass c) {
     if (threadIdx.x == 0) *reinterpret_cast<uint32_t *>(j.tree) = 0;
 }
 
-template <int W>
+template <int W, int B>
 __global__ __launch_bounds__(kThreads) void k_batch_ingest(BatchClass c) {
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const BatchJob &j = c.jobs[c.blk_map[blockIdx.x]];
@@ -755,7 +758,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_ingest(BatchClass c) {
     const uint64_t t = blk * kWaves + wv;
     if (t >= j.ntiles) return;  // whole wave
     bool bad = false;
-    const uint32_t ones = ingest_tile<W>(a, t, bad);
+    const uint32_t ones = ingest_tile<W, B>(a, t, bad);
     ingest_finish(a, bad, ones, t);
 }
 
@@ -769,14 +772,14 @@ __global__ __launch_bounds__(kThreads) void k_batch_prep(BatchClass c, uint32_t 
     prep_level(job_prep(c.jobs[blockIdx.x], level));
 }
 
-template <int W>
+template <int W, int B>
 __global__ __launch_bounds__(kThreads) void k_batch_level(BatchClass c, uint32_t level) {
-    __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W>()];
+    __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W, B>()];
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const BatchJob &j = c.jobs[c.blk_map[blockIdx.x]];
     const uint64_t t = (blockIdx.x - j.blk_base) * kWaves + wv;
     if (t >= j.ntiles) return;  // whole wave
-    level_tile<W>(job_level(j, level), t, s_all + wv * level_wave_bytes<W>());
+    level_tile<W, B>(job_level(j, level), t, s_all + wv * level_wave_bytes<W, B>());
 }
 
 }  // namespace
@@ -799,11 +802,25 @@ hipError_t launch_zero(void *p, uint64_t bytes, uint32_t *tree_status, uint64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_ingest(const IngestArgs &a, uint32_t width, hipStream_t s) {
-    const uint32_t g = (uint32_t)ceil_div(a.ntiles, a.tiles_per_block);
-    if (width == 1) hipLaunchKernelGGL(k_ingest<1>, dim3(g), dim3(kThreads), 0, s, a);
-    else if (width == 2) hipLaunchKernelGGL(k_ingest<2>, dim3(g), dim3(kThreads), 0, s, a);
-    else hipLaunchKernelGGL(k_ingest<4>, dim3(g), dim3(kThreads), 0, s, a);
+// Launch KERNEL<width, lane_bytes> (every valid pair is instantiated).
+#define WT_LAUNCH_WB(KERNEL, W_, LB_, GRID, ...)                                                         \
+    do {                                                                                               \
+        switch ((W_) * 1000 + (LB_)) {                                                                 \
+            case 1032: hipLaunchKernelGGL((KERNEL<1, 32>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;  \
+            case 1064: hipLaunchKernelGGL((KERNEL<1, 64>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;  \
+            case 2032: hipLaunchKernelGGL((KERNEL<2, 32>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;  \
+            case 2064: hipLaunchKernelGGL((KERNEL<2, 64>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;  \
+            case 2128: hipLaunchKernelGGL((KERNEL<2, 128>), GRID, dim3(kThreads), 0, __VA_ARGS__); break; \
+            case 4032: hipLaunchKernelGGL((KERNEL<4, 32>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;  \
+            case 4064: hipLaunchKernelGGL((KERNEL<4, 64>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;  \
+            case 4128: hipLaunchKernelGGL((KERNEL<4, 128>), GRID, dim3(kThreads), 0, __VA_ARGS__); break; \
+            default: return hipErrorInvalidValue;                                                      \
+        }                                                                                              \
+    } while (0)
+
+hipError_t launch_ingest(const IngestArgs &a, uint32_t width, uint32_t lane_bytes, hipStream_t s) {
+    const dim3 g((uint32_t)ceil_div(a.ntiles, a.tiles_per_block));
+    WT_LAUNCH_WB(k_ingest, width, lane_bytes, g, s, a);
     return hipGetLastError();
 }
 
@@ -821,11 +838,9 @@ hipError_t launch_plan(const PlanArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_level(const LevelArgs &a, uint32_t width, hipStream_t s) {
+hipError_t launch_level(const LevelArgs &a, uint32_t width, uint32_t lane_bytes, hipStream_t s) {
     const dim3 g((uint32_t)ceil_div(a.ntiles, kWaves));
-    if (width == 1) hipLaunchKernelGGL(k_level<1>, g, dim3(kThreads), 0, s, a);
-    else if (width == 2) hipLaunchKernelGGL(k_level<2>, g, dim3(kThreads), 0, s, a);
-    else hipLaunchKernelGGL(k_level<4>, g, dim3(kThreads), 0, s, a);
+    WT_LAUNCH_WB(k_level, width, lane_bytes, g, s, a);
     return hipGetLastError();
 }
 
@@ -836,28 +851,21 @@ hipError_t launch_batch_setup(const BatchClass &c, uint64_t blocks, uint64_t sup
     return hipGetLastError();
 }
 
-hipError_t launch_batch_ingest(const BatchClass &c, uint32_t width, uint64_t blocks, hipStream_t s) {
+hipError_t launch_batch_ingest(const BatchClass &c, uint32_t width, uint32_t lane_bytes, uint64_t blocks,
+                               hipStream_t s) {
     if (blocks == 0) return hipSuccess;
-    const dim3 g((uint32_t)blocks);
-    if (width == 1) hipLaunchKernelGGL(k_batch_ingest<1>, g, dim3(kThreads), 0, s, c);
-    else if (width == 2) hipLaunchKernelGGL(k_batch_ingest<2>, g, dim3(kThreads), 0, s, c);
-    else hipLaunchKernelGGL(k_batch_ingest<4>, g, dim3(kThreads), 0, s, c);
+    WT_LAUNCH_WB(k_batch_ingest, width, lane_bytes, dim3((uint32_t)blocks), s, c);
     return hipGetLastError();
 }
 
 // Level `level` of the first `active` sequences of the class: superchunk
 // sums, prefixes and node tables, then the level pass.
-hipError_t launch_batch_level(const BatchClass &c, uint32_t width, uint32_t level, uint32_t active,
-                              uint64_t blocks, uint64_t sups, hipStream_t s) {
+hipError_t launch_batch_level(const BatchClass &c, uint32_t width, uint32_t lane_bytes, uint32_t level,
+                              uint32_t active, uint64_t blocks, uint64_t sups, hipStream_t s) {
     if (active == 0) return hipSuccess;
     if (sups) hipLaunchKernelGGL(k_batch_supsum, dim3((uint32_t)sups), dim3(kThreads), 0, s, c, level);
     hipLaunchKernelGGL(k_batch_prep, dim3(active), dim3(kThreads), 0, s, c, level);
-    if (blocks) {
-        const dim3 g((uint32_t)blocks);
-        if (width == 1) hipLaunchKernelGGL(k_batch_level<1>, g, dim3(kThreads), 0, s, c, level);
-        else if (width == 2) hipLaunchKernelGGL(k_batch_level<2>, g, dim3(kThreads), 0, s, c, level);
-        else hipLaunchKernelGGL(k_batch_level<4>, g, dim3(kThreads), 0, s, c, level);
-    }
+    if (blocks) WT_LAUNCH_WB(k_batch_level, width, lane_bytes, dim3((uint32_t)blocks), s, c, level);
     return hipGetLastError();
 }
 

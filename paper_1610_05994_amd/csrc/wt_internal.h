@@ -6,13 +6,20 @@
 
 namespace wt {
 
-// Level pass geometry: one wave owns one tile of 64 lanes x 64 bytes of
-// symbols, i.e. 4096 / width symbols (4096, 2048 or 1024), always a
-// multiple of 512; a workgroup holds kWaves independent tiles.
+// Level pass geometry: one wave owns one tile of 64 lanes x B bytes of
+// symbols (B = lane_bytes: 32, 64 or 128; B / width <= 64), i.e.
+// 64 * B / width symbols, always a multiple of 512; a workgroup holds kWaves
+// independent tiles.  B is picked per (width, levels, lg n) by the tuning
+// table (wt_tune_set).
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr uint64_t kTileBytes = 64 * 64;
-__host__ __device__ constexpr uint64_t tile_syms(uint32_t width) { return kTileBytes / width; }
+constexpr uint32_t kDefaultLaneBytes = 64;
+__host__ __device__ constexpr uint64_t tile_syms(uint32_t width, uint32_t lane_bytes) {
+    return 64ull * lane_bytes / width;
+}
+static inline bool lane_bytes_valid(uint32_t width, uint32_t lb) {
+    return (lb == 32 || lb == 64 || lb == 128) && lb / width <= 64;
+}
 // Tiles per superchunk of the tile-count scan (four counts per lane).
 constexpr uint64_t kSup = kThreads;
 // Node ones counters of shallow levels are spread over slots so that the
@@ -42,7 +49,7 @@ static inline uint32_t levels_for(uint32_t sigma) {
 // Byte layout of one tree (in caller memory) and of one build's workspace.
 struct Layout {
     uint64_t n;
-    uint32_t sigma, width, levels;
+    uint32_t sigma, width, levels, lane_bytes;
     uint64_t words;         // W: bitmap words per level
     uint64_t rank_entries;  // K
     uint64_t rank_stride;   // round_up(K, 8)
@@ -65,7 +72,8 @@ struct Layout {
     uint64_t ones_off[32], zo_off[32], start_off[32];
 };
 
-void make_layout(uint64_t n, uint32_t sigma, uint32_t width, Layout *L);
+void make_layout(uint64_t n, uint32_t sigma, uint32_t width, bool batched, Layout *L);
+uint32_t tuned_lane_bytes(uint64_t n, uint32_t sigma, uint32_t width, bool batched);
 
 // Arguments of one level pass.
 struct LevelArgs {
@@ -123,7 +131,7 @@ struct BatchJob {
     uint64_t ws_ta, ws_tb, ws_ctrl, ws_ctrl_bytes, ws_tile_ones, ws_ones, ws_sup, ws_supsum, ws_zo, ws_start;
     uint64_t blk_base;  // first workgroup of this sequence in its class's tile map
     uint64_t sup_base;  // first workgroup of this sequence in its class's superchunk map
-    uint32_t sigma, width, levels, check;
+    uint32_t sigma, width, levels, check, lane_bytes;
 };
 
 // Sequences that share one symbol width, sorted by level count (descending),
@@ -147,14 +155,15 @@ __host__ __device__ inline uint64_t ones_offset(uint32_t i) {
 // kernel launchers (wt_build.hip)
 hipError_t launch_zero(void *p, uint64_t bytes, uint32_t *tree_status, uint64_t *tree_ranks,
                        uint64_t tree_ranks_count, hipStream_t s);
-hipError_t launch_ingest(const IngestArgs &a, uint32_t width, hipStream_t s);
+hipError_t launch_ingest(const IngestArgs &a, uint32_t width, uint32_t lane_bytes, hipStream_t s);
 hipError_t launch_prep(const PrepArgs &a, hipStream_t s);  // k_supsum, then k_prep
 hipError_t launch_plan(const PlanArgs &a, hipStream_t s);
-hipError_t launch_level(const LevelArgs &a, uint32_t width, hipStream_t s);
+hipError_t launch_level(const LevelArgs &a, uint32_t width, uint32_t lane_bytes, hipStream_t s);
 hipError_t launch_batch_setup(const BatchClass &c, uint64_t blocks, uint64_t sups, hipStream_t s);
-hipError_t launch_batch_ingest(const BatchClass &c, uint32_t width, uint64_t blocks, hipStream_t s);
-hipError_t launch_batch_level(const BatchClass &c, uint32_t width, uint32_t level, uint32_t active,
-                              uint64_t blocks, uint64_t sups, hipStream_t s);
+hipError_t launch_batch_ingest(const BatchClass &c, uint32_t width, uint32_t lane_bytes, uint64_t blocks,
+                               hipStream_t s);
+hipError_t launch_batch_level(const BatchClass &c, uint32_t width, uint32_t lane_bytes, uint32_t level,
+                              uint32_t active, uint64_t blocks, uint64_t sups, hipStream_t s);
 
 // query launchers (wt_query.hip)
 struct TreeView {

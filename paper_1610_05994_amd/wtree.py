@@ -24,7 +24,8 @@ WT_MAX_SIGMA = 1 << 24
 EXPORTED = [
     "wt_footprint", "wt_build", "wt_batch_footprint", "wt_build_batch", "wt_tree_status",
     "wt_free", "wt_levels", "wt_access_batch", "wt_rank_batch", "wt_select_batch",
-    "wt_access", "wt_rank", "wt_select", "wt_strerror", "wt_prof_enable", "wt_prof_read",
+    "wt_access", "wt_rank", "wt_select", "wt_strerror", "wt_tune_set", "wt_tune_get",
+    "wt_prof_enable", "wt_prof_read",
 ]
 
 
@@ -71,6 +72,8 @@ def lib():
         "wt_rank": ([vp, u32, u64, P(u64)], i32),
         "wt_select": ([vp, u32, u64, P(u64)], i32),
         "wt_strerror": ([i32], ctypes.c_char_p),
+        "wt_tune_set": ([u32, u32, u32, u32, u32], i32),
+        "wt_tune_get": ([u32, u32, u32, u32, P(u32)], i32),
         "wt_prof_enable": ([i32], i32),
         "wt_prof_read": ([P(wt_prof_rec), u64, P(u64)], i32),
     }
@@ -79,6 +82,13 @@ def lib():
         f.argtypes = args
         f.restype = res
     _lib = L
+    # tile geometry chosen by the autotuner (tune.py), if a table is present
+    table = os.environ.get("WT_TUNE_TABLE")
+    if table is None:
+        table = os.path.join(_PKG, "tune_table.json")
+    if table:
+        from . import tune
+        tune.load(table)
     return L
 
 
@@ -86,6 +96,16 @@ def lib():
 
 def strerror(status: int) -> str:
     return lib().wt_strerror(status).decode()
+
+
+def wt_tune_set(mode: int, width: int, levels: int, lg_n: int, lane_bytes: int) -> int:
+    return lib().wt_tune_set(mode, width, levels, lg_n, lane_bytes)
+
+
+def wt_tune_get(mode: int, width: int, levels: int, lg_n: int):
+    v = ctypes.c_uint32()
+    rc = lib().wt_tune_get(mode, width, levels, lg_n, ctypes.byref(v))
+    return rc, v.value
 
 
 def wt_footprint(n: int, sigma: int, width: int):

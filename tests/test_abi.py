@@ -99,3 +99,42 @@ def test_status_strings():
     assert wt.strerror(99) == "unknown status"
     assert wt.lib().wt_tree_status(None) == wt.WT_EINVAL
     wt.lib().wt_free(None)
+
+
+def test_tune_table_set_get_and_validation():
+    wt = _wt()
+    rc, before = wt.wt_tune_get(0, 1, 8, 20)
+    assert rc == wt.WT_OK and before in (32, 64, 128)
+    try:
+        assert wt.wt_tune_set(0, 1, 8, 20, 64) == wt.WT_OK
+        _, _, wb64 = wt.wt_footprint(1 << 20, 256, 1)
+        assert wt.wt_tune_set(0, 1, 8, 20, 32) == wt.WT_OK
+        assert wt.wt_tune_get(0, 1, 8, 20) == (wt.WT_OK, 32)
+        rc, tb32, wb32 = wt.wt_footprint(1 << 20, 256, 1)
+        assert rc == wt.WT_OK
+        # half the tile -> twice the per-tile counters; the tree is unchanged
+        assert wb32 > wb64
+        assert tb32 == wt.wt_footprint(1 << 20, 256, 1)[1]
+        # the batched mode keeps its own entry
+        assert wt.wt_tune_get(1, 1, 8, 20)[0] == wt.WT_OK
+        assert wt.wt_tune_set(0, 1, 8, 20, 0) == wt.WT_OK
+        assert wt.wt_tune_get(0, 1, 8, 20) == (wt.WT_OK, 64)
+    finally:
+        wt.wt_tune_set(0, 1, 8, 20, before)
+    for bad in [(2, 1, 8, 20, 64), (0, 3, 8, 20, 64), (0, 1, 0, 20, 64), (0, 1, 9, 20, 64),
+                (0, 4, 25, 20, 64), (0, 1, 8, 41, 64), (0, 1, 8, 20, 128), (0, 2, 8, 20, 48)]:
+        assert wt.wt_tune_set(*bad) == wt.WT_EINVAL, bad
+    assert wt.wt_tune_get(0, 1, 8, 41)[0] == wt.WT_EINVAL
+
+
+def test_tune_table_expansion_takes_nearest_point():
+    from paper_1610_05994_amd import tune
+    pts = [dict(mode=0, width=2, levels=6, lg_n=10, lane_bytes=32),
+           dict(mode=0, width=2, levels=16, lg_n=26, lane_bytes=128),
+           dict(mode=1, width=2, levels=6, lg_n=12, lane_bytes=64)]
+    d = tune.expand(pts)
+    assert d[(0, 2, 5, 0)] == 32 and d[(0, 2, 16, 40)] == 128 and d[(0, 2, 15, 12)] == 128
+    assert d[(1, 2, 6, 12)] == 64 and d[(1, 2, 6, 13)] == 64
+    assert d[(1, 2, 16, 30)] == 128          # past the batched grid: mode 0's point
+    assert (0, 1, 8, 20) not in d            # no point for width 1: default kept
+    assert all(lb in tune.candidates(w) for (_, w, _, _), lb in d.items())
