@@ -73,11 +73,13 @@ static void prof_end(long idx, hipStream_t st) {
 }
 
 // ---------------------------------------------------------- tuning table --
-// Bytes per lane of the tile geometry, per (mode: single or batched build,
-// width class, levels, floor lg n); 0 = the default.  Filled by wt_tune_set
-// (the autotuner writes a table that the Python binding loads); read by every
-// layout computation, so a footprint and the build that uses it must see the
-// same table.
+// Geometry per (mode: single or batched build, width class, levels,
+// floor lg n): 0 = the default, kGeomSmall / kGeomMid = one workgroup per
+// sequence (64 KB / 160 KB of LDS), 32 / 64 / 128 = tiled level passes with
+// that many bytes per lane.  Filled
+// by wt_tune_set (the autotuner writes a table that the Python binding
+// loads); read by every layout computation, so a footprint and the build
+// that uses it must see the same table.
 static uint8_t g_tune[2][3][25][41];
 
 static int wclass(uint32_t w) { return w == 1 ? 0 : (w == 2 ? 1 : 2); }
@@ -87,11 +89,25 @@ static uint32_t floor_lg(uint64_t n) {
     return k;
 }
 
-uint32_t tuned_lane_bytes(uint64_t n, uint32_t sigma, uint32_t width, bool batched) {
+// The default: short sequences take the smallest one-workgroup build that
+// holds them, longer ones 64 bytes per lane.  A one-workgroup geometry that
+// cannot hold the sequence falls back to the default.
+static uint32_t resolve_geometry(uint32_t v, uint64_t n, uint32_t width) {
+    if (v == kGeomSmall || v == kGeomMid) {
+        if (n <= one_wg_cap(width, v)) return v;
+        v = 0;
+    }
+    if (v == 0) {
+        if (n <= one_wg_cap(width, kGeomSmall)) return kGeomSmall;
+        if (n <= one_wg_cap(width, kGeomMid)) return kGeomMid;
+        return kDefaultLaneBytes;
+    }
+    return lane_bytes_valid(width, v) ? v : kDefaultLaneBytes;
+}
+
+uint32_t tuned_geometry(uint64_t n, uint32_t sigma, uint32_t width, bool batched) {
     const uint32_t l = levels_for(sigma);
-    const uint8_t v = g_tune[batched ? 1 : 0][wclass(width)][l < 25 ? l : 24][floor_lg(n)];
-    const uint32_t lb = v ? (uint32_t)v * 32 : kDefaultLaneBytes;
-    return lane_bytes_valid(width, lb) ? lb : kDefaultLaneBytes;
+    return resolve_geometry(g_tune[batched ? 1 : 0][wclass(width)][l < 25 ? l : 24][floor_lg(n)], n, width);
 }
 
 void make_layout(uint64_t n, uint32_t sigma, uint32_t width, bool batched, Layout *L) {
@@ -104,7 +120,9 @@ void make_layout(uint64_t n, uint32_t sigma, uint32_t width, bool batched, Layou
     L->words = round_up(ceil_div(n, 64), 8);
     L->rank_entries = ceil_div(n, 512) + 1;
     L->rank_stride = round_up(L->rank_entries, 8);
-    L->lane_bytes = tuned_lane_bytes(n, sigma, width, batched);
+    const uint32_t geom = tuned_geometry(n, sigma, width, batched);
+    L->small = (geom == kGeomSmall || geom == kGeomMid) ? geom : 0u;
+    L->lane_bytes = L->small ? kDefaultLaneBytes : geom;
     L->ntiles = ceil_div(n, tile_syms(width, L->lane_bytes));
     L->nsup = ceil_div(L->ntiles, kSup);
 
@@ -123,9 +141,7 @@ void make_layout(uint64_t n, uint32_t sigma, uint32_t width, bool batched, Layou
     L->ws_tile_ones = off;
     off += round_up((uint64_t)l * L->ntiles * 4, 256);
     L->ws_ones = off;
-    uint64_t e = 0;
-    for (uint32_t i = 0; i < l; i++) { L->ones_off[i] = e; e += level_slots(i) << i; }
-    off += round_up(e * 8, 256);
+    off += round_up(ones_offset(l) * 8, 256);
     L->ws_ctrl_bytes = off - L->ws_ctrl;
 
     L->ws_sup = off;
@@ -133,22 +149,39 @@ void make_layout(uint64_t n, uint32_t sigma, uint32_t width, bool batched, Layou
     L->ws_supsum = off;
     off += round_up((L->nsup ? L->nsup : 1) * 8, 256);
     L->ws_zo = off;
-    e = 0;
-    for (uint32_t i = 0; i < l; i++) { L->zo_off[i] = e; e += 1ull << i; }
-    off += round_up(e * 16, 256);
+    off += round_up(zo_offset(l) * 16, 256);
     L->ws_start = off;
-    e = 0;
-    for (uint32_t i = 0; i < l; i++) { L->start_off[i] = e; e += (1ull << i) + 1; }
-    off += round_up(e * 8, 256);
+    off += round_up(start_offset(l) * 8, 256);
     L->ws_partials = off;
     off += round_up(kMaxScanBlocks * 8, 256);
-    L->work_bytes = off;
+    L->work_bytes = L->small ? 256 : off;  // the one-workgroup build needs no workspace
+}
+
+static SmallJob make_small_job(const Layout &L, const void *S, void *tree) {
+    SmallJob j;
+    j.S = S;
+    j.tree = reinterpret_cast<uint8_t *>(tree);
+    j.bits_off = L.tree_bits_off;
+    j.ranks_off = L.tree_ranks_off;
+    j.n = (uint32_t)L.n;
+    j.sigma = L.sigma;
+    j.levels = L.levels;
+    j.words = (uint32_t)L.words;
+    j.rank_entries = (uint32_t)L.rank_entries;
+    j.rank_stride = (uint32_t)L.rank_stride;
+    return j;
 }
 
 // Enqueue every kernel of one build.  Arguments are already validated.
 static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, uint8_t *work,
                                 hipStream_t st) {
     const uint32_t l = L.levels;
+    if (L.small) {
+        long pr = prof_begin(st, "small", 0, L.width, L.n, L.n * L.width + (L.words + L.rank_stride) * 8 * l);
+        hipError_t err = launch_small_one(make_small_job(L, S, tree), L.width, L.small, st);
+        prof_end(pr, st);
+        return err;
+    }
     uint32_t *tree_status = reinterpret_cast<uint32_t *>(tree);
     uint64_t *bits = reinterpret_cast<uint64_t *>(tree + L.tree_bits_off);
     uint64_t *ranks = reinterpret_cast<uint64_t *>(tree + L.tree_ranks_off);
@@ -193,10 +226,10 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
     uint8_t *tbuf[2] = {work + L.ws_ta, work + L.ws_tb};
     for (uint32_t i = 0; i < l; i++) {
         PlanArgs pa;
-        pa.start = start + L.start_off[i];
-        pa.ones = ones + L.ones_off[i];
-        pa.zo = zo + L.zo_off[i];
-        pa.start_next = (i + 1 < l) ? start + L.start_off[i + 1] : nullptr;
+        pa.start = start + start_offset(i);
+        pa.ones = ones + ones_offset(i);
+        pa.zo = zo + zo_offset(i);
+        pa.start_next = (i + 1 < l) ? start + start_offset(i + 1) : nullptr;
         pa.partials = partials;
         pa.nodes = 1ull << i;
         pa.slots = level_slots(i);
@@ -226,11 +259,11 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         a.tout = (i + 1 < l) ? tbuf[i & 1] : nullptr;
         a.bits = bits + (uint64_t)i * L.words;
         a.ranks = ranks + (uint64_t)i * L.rank_stride;
-        a.zo = zo + L.zo_off[i];
+        a.zo = zo + zo_offset(i);
         a.tile_ones = tile_ones + (uint64_t)i * L.ntiles;
         a.sup = sup + (uint64_t)i * L.nsup;
         a.tile_ones_next = (i + 1 < l) ? tile_ones + (uint64_t)(i + 1) * L.ntiles : nullptr;
-        a.ones_next = (i + 1 < l) ? ones + L.ones_off[i + 1] : nullptr;
+        a.ones_next = (i + 1 < l) ? ones + ones_offset(i + 1) : nullptr;
         a.nodes_next = 2ull << i;
         a.slots_next = level_slots(i + 1);
         a.n = L.n;
@@ -295,7 +328,8 @@ struct BatchPlan {
     std::vector<Layout> L;
     // per class (width, lane bytes): sequences by levels, descending
     std::vector<uint32_t> order[kClasses];
-    uint64_t jobs_off, map_off[kClasses], sup_off[kClasses], slices_off, total;
+    std::vector<uint32_t> small[6];  // per (width class, 64 KB / 160 KB): one-workgroup builds
+    uint64_t jobs_off, small_off, map_off[kClasses], sup_off[kClasses], slices_off, total;
     std::vector<uint64_t> slice;     // workspace offset of each sequence's slice
     uint64_t blocks[kClasses], sups[kClasses];
 };
@@ -306,10 +340,15 @@ static int plan_batch(uint32_t m, const wt_desc *descs, BatchPlan *P) {
         int rc = check_desc(&descs[q]);
         if (rc != WT_OK) return rc;
         make_layout(descs[q].n, descs[q].sigma, descs[q].width, true, &P->L[q]);
-        P->order[batch_class(descs[q].width, P->L[q].lane_bytes)].push_back(q);
+        if (P->L[q].small) P->small[wclass(descs[q].width) * 2 + (P->L[q].small == kGeomMid)].push_back(q);
+        else P->order[batch_class(descs[q].width, P->L[q].lane_bytes)].push_back(q);
     }
-    uint64_t off = round_up((uint64_t)m * sizeof(BatchJob), 256);
+    uint64_t nsmall = 0;
+    for (int c = 0; c < 6; c++) nsmall += P->small[c].size();
     P->jobs_off = 0;
+    uint64_t off = round_up((uint64_t)(m - nsmall) * sizeof(BatchJob), 256);
+    P->small_off = off;
+    off += round_up(nsmall * sizeof(SmallJob), 256);
     for (int c = 0; c < kClasses; c++) {
         std::vector<uint32_t> &o = P->order[c];
         std::stable_sort(o.begin(), o.end(), [&](uint32_t x, uint32_t y) { return P->L[x].levels > P->L[y].levels; });
@@ -329,7 +368,7 @@ static int plan_batch(uint32_t m, const wt_desc *descs, BatchPlan *P) {
     P->slice.resize(m);
     for (uint32_t q = 0; q < m; q++) {
         P->slice[q] = off;
-        off += round_up(P->L[q].work_bytes, 256);
+        if (!P->L[q].small) off += round_up(P->L[q].work_bytes, 256);
     }
     P->total = off;
     return WT_OK;
@@ -452,8 +491,35 @@ int wt_build_batch(uint32_t m, const void *const *d_S, const wt_desc *descs, voi
     }
     BatchJob *d_jobs = reinterpret_cast<BatchJob *>(work + P.jobs_off);
     // (pageable source: the call returns once the descriptors are staged)
-    if (hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(BatchJob), hipMemcpyHostToDevice, st) != hipSuccess)
+    if (!jobs.empty() &&
+        hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(BatchJob), hipMemcpyHostToDevice, st) != hipSuccess)
         return WT_EDEVICE;
+    // short sequences: one workgroup each, one launch per width
+    std::vector<SmallJob> sjobs;
+    uint32_t sfirst[7];
+    for (int c = 0; c < 6; c++) {
+        sfirst[c] = (uint32_t)sjobs.size();
+        for (uint32_t q : P.small[c]) sjobs.push_back(make_small_job(P.L[q], d_S[q], d_trees[q]));
+    }
+    sfirst[6] = (uint32_t)sjobs.size();
+    SmallJob *d_sjobs = reinterpret_cast<SmallJob *>(work + P.small_off);
+    if (!sjobs.empty() &&
+        hipMemcpyAsync(d_sjobs, sjobs.data(), sjobs.size() * sizeof(SmallJob), hipMemcpyHostToDevice, st) != hipSuccess)
+        return WT_EDEVICE;
+    static const uint32_t kWidthOf[3] = {1, 2, 4};
+    for (int c = 0; c < 6; c++) {
+        const uint32_t cnt = sfirst[c + 1] - sfirst[c];
+        if (!cnt) continue;
+        uint64_t nsym = 0, bytes = 0;
+        for (uint32_t q : P.small[c]) {
+            nsym += P.L[q].n;
+            bytes += P.L[q].n * P.L[q].width + (P.L[q].words + P.L[q].rank_stride) * 8 * P.L[q].levels;
+        }
+        long pr = prof_begin(st, (c & 1) ? "batch_mid" : "batch_small", 0, kWidthOf[c / 2], nsym, bytes);
+        hipError_t e = launch_small_batch(d_sjobs + sfirst[c], cnt, kWidthOf[c / 2], (c & 1) ? kGeomMid : kGeomSmall, st);
+        prof_end(pr, st);
+        if (e != hipSuccess) return WT_EDEVICE;
+    }
 
     BatchClass cls[kClasses];
     for (int c = 0; c < kClasses; c++) {
@@ -606,18 +672,17 @@ static bool tune_key_ok(uint32_t mode, uint32_t width, uint32_t levels, uint32_t
            levels <= 8 * width && lg_n <= 40;
 }
 
-int wt_tune_set(uint32_t mode, uint32_t width, uint32_t levels, uint32_t lg_n, uint32_t lane_bytes) {
+int wt_tune_set(uint32_t mode, uint32_t width, uint32_t levels, uint32_t lg_n, uint32_t geometry) {
     if (!tune_key_ok(mode, width, levels, lg_n)) return WT_EINVAL;
-    if (lane_bytes != 0 && !lane_bytes_valid(width, lane_bytes)) return WT_EINVAL;
-    g_tune[mode][wclass(width)][levels][lg_n] = (uint8_t)(lane_bytes / 32);
+    if (geometry != 0 && geometry != kGeomSmall && geometry != kGeomMid && !lane_bytes_valid(width, geometry))
+        return WT_EINVAL;
+    g_tune[mode][wclass(width)][levels][lg_n] = (uint8_t)geometry;
     return WT_OK;
 }
 
-int wt_tune_get(uint32_t mode, uint32_t width, uint32_t levels, uint32_t lg_n, uint32_t *lane_bytes) {
-    if (!tune_key_ok(mode, width, levels, lg_n) || !lane_bytes) return WT_EINVAL;
-    const uint8_t v = g_tune[mode][wclass(width)][levels][lg_n];
-    *lane_bytes = v ? (uint32_t)v * 32 : kDefaultLaneBytes;
-    if (!lane_bytes_valid(width, *lane_bytes)) *lane_bytes = kDefaultLaneBytes;
+int wt_tune_get(uint32_t mode, uint32_t width, uint32_t levels, uint32_t lg_n, uint32_t *geometry) {
+    if (!tune_key_ok(mode, width, levels, lg_n) || !geometry) return WT_EINVAL;
+    *geometry = resolve_geometry(g_tune[mode][wclass(width)][levels][lg_n], 1ull << lg_n, width);
     return WT_OK;
 }
 

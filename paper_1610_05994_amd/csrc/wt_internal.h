@@ -20,6 +20,18 @@ __host__ __device__ constexpr uint64_t tile_syms(uint32_t width, uint32_t lane_b
 static inline bool lane_bytes_valid(uint32_t width, uint32_t lb) {
     return (lb == 32 || lb == 64 || lb == 128) && lb / width <= 64;
 }
+// Short sequences: one workgroup builds every level in LDS (two symbol
+// buffers and a 16-bit rank per position).  Two sizes: kGeomSmall, 512
+// threads in under 64 KB (two workgroups per CU), and kGeomMid, 1024 threads
+// in up to 160 KB (the whole LDS of a CU).  The tuning table selects them
+// with these geometry codes.
+constexpr uint32_t kGeomSmall = 1;
+constexpr uint32_t kGeomMid = 2;
+__host__ __device__ constexpr int one_wg_threads(uint32_t geom) { return geom == kGeomMid ? 1024 : 512; }
+__host__ __device__ constexpr uint32_t one_wg_cap(uint32_t width, uint32_t geom) {
+    return geom == kGeomMid ? (width == 1 ? 32768u : (width == 2 ? 26624u : 15360u))
+                            : (width == 1 ? 15360u : (width == 2 ? 10240u : 6144u));
+}
 // Tiles per superchunk of the tile-count scan (four counts per lane).
 constexpr uint64_t kSup = kThreads;
 // Node ones counters of shallow levels are spread over slots so that the
@@ -50,6 +62,7 @@ static inline uint32_t levels_for(uint32_t sigma) {
 struct Layout {
     uint64_t n;
     uint32_t sigma, width, levels, lane_bytes;
+    uint32_t small;         // 0, or kGeomSmall / kGeomMid: built by one workgroup (no workspace)
     uint64_t words;         // W: bitmap words per level
     uint64_t rank_entries;  // K
     uint64_t rank_stride;   // round_up(K, 8)
@@ -68,12 +81,20 @@ struct Layout {
     uint64_t ws_start;                  // per level 2^i + 1 node starts (u64)
     uint64_t ws_partials;               // scan partial sums
     uint64_t work_bytes;
-    // per-level table offsets (entries), level < 32
-    uint64_t ones_off[32], zo_off[32], start_off[32];
 };
 
 void make_layout(uint64_t n, uint32_t sigma, uint32_t width, bool batched, Layout *L);
-uint32_t tuned_lane_bytes(uint64_t n, uint32_t sigma, uint32_t width, bool batched);
+uint32_t tuned_geometry(uint64_t n, uint32_t sigma, uint32_t width, bool batched);
+
+// One short sequence for the one-workgroup build.
+struct SmallJob {
+    const void *S;
+    uint8_t *tree;  // status word at offset 0
+    uint64_t bits_off, ranks_off;
+    uint32_t n, sigma, levels, words, rank_entries, rank_stride;
+};
+hipError_t launch_small_one(const SmallJob &j, uint32_t width, uint32_t geom, hipStream_t s);
+hipError_t launch_small_batch(const SmallJob *d_jobs, uint32_t count, uint32_t width, uint32_t geom, hipStream_t s);
 
 // Arguments of one level pass.
 struct LevelArgs {
@@ -146,10 +167,13 @@ struct BatchClass {
 // Per-level table offsets (entries) shared by the host layout and the device.
 __host__ __device__ constexpr uint64_t zo_offset(uint32_t i) { return (1ull << i) - 1; }
 __host__ __device__ constexpr uint64_t start_offset(uint32_t i) { return (1ull << i) - 1 + i; }
+// sum of level_slots(k) << k over k < i: kSlotSpan per level up to the
+// level where one slot remains, then 2^k
 __host__ __device__ inline uint64_t ones_offset(uint32_t i) {
-    uint64_t e = 0;
-    for (uint32_t k = 0; k < i; k++) e += level_slots(k) << k;
-    return e;
+    constexpr uint32_t kFull = 12;  // kSlotSpan >> 12 == 1
+    static_assert((kSlotSpan >> kFull) == 1, "slot span");
+    return (i <= kFull + 1) ? (uint64_t)kSlotSpan * i
+                            : (uint64_t)kSlotSpan * (kFull + 1) + ((1ull << i) - (1ull << (kFull + 1)));
 }
 
 // kernel launchers (wt_build.hip)

@@ -4,9 +4,12 @@ The domain decomposition of the paper (Section 3.2) leaves the segment size
 free.  Here a segment is the tile that one wavefront splits: 64 lanes x
 ``lane_bytes`` bytes of symbols (32, 64 or 128 bytes, at most 64 symbols per
 lane).  Small tiles give short sequences more wavefronts; large tiles spread
-the per-tile prefix, node-span and counter work over more symbols.  Which
-wins depends on the width, the depth and the length, and differs between a
-build on its own and a batched build of many sequences, so both are tuned.
+the per-tile prefix, node-span and counter work over more symbols.  A short
+sequence may instead be built whole by one workgroup in LDS (geometry 1:
+64 KB, geometry 2: 160 KB).
+Which wins depends on the width, the depth and the length, and differs
+between a build on its own and a batched build of many sequences, so both
+are tuned.
 
 ``tune()`` times the library's builds for every valid geometry over a grid
 of (width, levels, lg n) -- mode 0 with ``wt_build``, mode 1 with
@@ -38,9 +41,19 @@ BATCH_MAX = 2048
 BATCH_WORK_CAP = 8 << 30  # workspace bytes of one timed batch
 
 
-def candidates(width: int):
-    """Valid lane-byte values for a width."""
-    return [lb for lb in (32, 64, 128) if lb // width <= 64]
+# one workgroup per sequence, every level in LDS: 512 threads in 64 KB,
+# 1024 threads in 160 KB, with the longest sequence each takes
+GEOM_SMALL, GEOM_MID = 1, 2
+ONE_WG_CAP = {GEOM_SMALL: {1: 15360, 2: 10240, 4: 6144}, GEOM_MID: {1: 32768, 2: 26624, 4: 15360}}
+
+
+def candidates(width: int, n: int | None = None):
+    """Valid geometries for a width (and length): lane bytes of the tiled
+    level passes, plus the one-workgroup builds where the length fits."""
+    out = [lb for lb in (32, 64, 128) if lb // width <= 64]
+    if n is not None:
+        out = [g for g in (GEOM_SMALL, GEOM_MID) if n <= ONE_WG_CAP[g][width]] + out
+    return out
 
 
 def _input(torch, n: int, levels: int, width: int, gen):
@@ -108,27 +121,36 @@ def _time_batch(torch, Ss, sigma: int, width: int, reps: int) -> float:
         rc = L.wt_build_batch(m, c_S, c_d, c_t, c_tb, work.data_ptr(), work.numel(), int(st.cuda_stream), c_h)
         if rc != wt.WT_OK:
             raise wt.WtError(rc, "wt_build_batch")
-        for h in c_h:
-            wt.wt_free(h)
+        return list(c_h)
 
-    once()
+    for h in once():
+        wt.wt_free(h)
     torch.cuda.synchronize()
+    held = []
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(st)
     for _ in range(reps):
-        once()
+        held.extend(once())   # handles are released after the timed region
     e1.record(st)
     torch.cuda.synchronize()
+    for h in held:
+        wt.wt_free(h)
     return e0.elapsed_time(e1) / reps
 
 
-def _batch_count(n: int, sigma: int, width: int) -> int:
-    """Sequences per timed batch: about BATCH_SYMBOLS symbols, workspace capped."""
+def _batch_count(n: int, sigma: int, width: int, levels: int, lg_n: int) -> int:
+    """Sequences per timed batch: about BATCH_SYMBOLS symbols, with the
+    workspace of the most demanding geometry under BATCH_WORK_CAP."""
     cnt = max(1, min(BATCH_MAX, BATCH_SYMBOLS // n))
-    rc, ws1 = wt.wt_batch_footprint([(n, sigma, width)])
-    if rc != wt.WT_OK:
-        raise wt.WtError(rc, "wt_batch_footprint")
-    return max(1, min(cnt, BATCH_WORK_CAP // max(ws1, 1)))
+    ws1 = 256
+    for g in candidates(width, n):
+        wt.wt_tune_set(1, width, levels, lg_n, g)
+        rc, ws = wt.wt_batch_footprint([(n, sigma, width)])
+        if rc != wt.WT_OK:
+            raise wt.WtError(rc, "wt_batch_footprint")
+        ws1 = max(ws1, ws)
+    wt.wt_tune_set(1, width, levels, lg_n, 0)
+    return max(1, min(cnt, BATCH_WORK_CAP // ws1))
 
 
 def tune(quick: bool = False, reps: int = 5, seed: int = 1, log=print):
@@ -150,11 +172,11 @@ def tune(quick: bool = False, reps: int = 5, seed: int = 1, log=print):
                     else:
                         if n > BATCH_SYMBOLS // 4:
                             continue   # long sequences are batched rarely; mode 0 covers them
-                        cnt = _batch_count(n, sigma, width)
+                        cnt = _batch_count(n, sigma, width, levels, lg_n)
                         flat = _input(torch, cnt * n, levels, width, gen)
                         inputs = [flat[k * n:(k + 1) * n] for k in range(cnt)]
                     times = {}
-                    for lb in candidates(width):
+                    for lb in candidates(width, n):
                         rc = wt.wt_tune_set(mode, width, levels, lg_n, lb)
                         if rc != wt.WT_OK:
                             raise wt.WtError(rc, "wt_tune_set")

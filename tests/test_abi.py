@@ -122,7 +122,8 @@ def test_tune_table_set_get_and_validation():
     finally:
         wt.wt_tune_set(0, 1, 8, 20, before)
     for bad in [(2, 1, 8, 20, 64), (0, 3, 8, 20, 64), (0, 1, 0, 20, 64), (0, 1, 9, 20, 64),
-                (0, 4, 25, 20, 64), (0, 1, 8, 41, 64), (0, 1, 8, 20, 128), (0, 2, 8, 20, 48)]:
+                (0, 4, 25, 20, 64), (0, 1, 8, 41, 64), (0, 1, 8, 20, 128), (0, 2, 8, 20, 48),
+                (0, 2, 8, 20, 3)]:
         assert wt.wt_tune_set(*bad) == wt.WT_EINVAL, bad
     assert wt.wt_tune_get(0, 1, 8, 41)[0] == wt.WT_EINVAL
 
@@ -137,4 +138,29 @@ def test_tune_table_expansion_takes_nearest_point():
     assert d[(1, 2, 6, 12)] == 64 and d[(1, 2, 6, 13)] == 64
     assert d[(1, 2, 16, 30)] == 128          # past the batched grid: mode 0's point
     assert (0, 1, 8, 20) not in d            # no point for width 1: default kept
-    assert all(lb in tune.candidates(w) for (_, w, _, _), lb in d.items())
+    assert all(lb in tune.candidates(w, 1) for (_, w, _, _), lb in d.items())
+    assert tune.candidates(1, 15360)[:2] == [tune.GEOM_SMALL, tune.GEOM_MID]
+    assert tune.candidates(1, 15361)[0] == tune.GEOM_MID and tune.GEOM_MID not in tune.candidates(1, 32769)
+
+
+def test_short_sequences_need_no_workspace():
+    wt = _wt()
+    for width, cap, cap2 in [(1, 15360, 32768), (2, 10240, 26624), (4, 6144, 15360)]:
+        assert wt.wt_footprint(cap, 200, width)[2] == 256
+        assert wt.wt_footprint(cap + 1, 200, width)[2] == 256
+        assert wt.wt_footprint(cap2, 200, width)[2] == 256
+        assert wt.wt_footprint(cap2 + 1, 200, width)[2] > 256
+        # forcing tiles on a short sequence brings the workspace back
+        levels = 8
+        lg = cap.bit_length() - 1
+        rc, before = wt.wt_tune_get(0, width, levels, lg)
+        try:
+            assert wt.wt_tune_set(0, width, levels, lg, 64) == wt.WT_OK
+            assert wt.wt_footprint(cap, 200, width)[2] > 256
+            assert wt.wt_tune_set(0, width, levels, lg, 1) == wt.WT_OK
+            assert wt.wt_footprint(cap, 200, width)[2] == 256
+            assert wt.wt_tune_set(0, width, levels, lg, 2) == wt.WT_OK
+            assert wt.wt_footprint(cap, 200, width)[2] == 256
+            assert wt.wt_tune_get(0, width, levels, lg)[1] == 2
+        finally:
+            wt.wt_tune_set(0, width, levels, lg, 0)

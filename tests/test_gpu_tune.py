@@ -1,9 +1,10 @@
 """GPU parity of every tile geometry the autotuner may choose.
 
-The tile geometry (lane bytes per wavefront) changes how the level pass
-splits the work, never the tree: for every valid geometry, single and
-batched builds must equal the oracle bit for bit.  Lengths straddle the
-tile sizes (512 .. 8192 symbols) with ragged tails.
+The geometry (one workgroup per sequence with 64 KB or 160 KB of LDS, or
+tiled level passes with 32, 64 or 128 lane bytes) changes how the work is split, never the tree: for
+every valid geometry, single and batched builds must equal the oracle bit
+for bit.  Lengths straddle the tile sizes (512 .. 8192 symbols) with ragged
+tails; lengths above the one-workgroup capacity fall back to tiles.
 """
 import numpy as np
 import pytest
@@ -24,7 +25,7 @@ def _force(lane_bytes):
     tune, wt = _mods()
     for mode in (0, 1):
         for width in (1, 2, 4):
-            lb = lane_bytes if lane_bytes in tune.candidates(width) else 0
+            lb = lane_bytes if (lane_bytes in (1, 2) or lane_bytes in tune.candidates(width)) else 0
             for levels in range(1, min(24, 8 * width) + 1):
                 for lg_n in range(0, 41):
                     assert wt.wt_tune_set(mode, width, levels, lg_n, lb) == wt.WT_OK
@@ -45,7 +46,7 @@ CASES = [  # (n, sigma, width)
 ]
 
 
-@pytest.mark.parametrize("lane_bytes", [32, 64, 128])
+@pytest.mark.parametrize("lane_bytes", [1, 2, 32, 64, 128])
 def test_every_geometry_builds_the_oracle_tree(lane_bytes, restore_table):
     _, wt = _mods()
     import torch
@@ -60,7 +61,7 @@ def test_every_geometry_builds_the_oracle_tree(lane_bytes, restore_table):
         t.close()
 
 
-@pytest.mark.parametrize("lane_bytes", [32, 128])
+@pytest.mark.parametrize("lane_bytes", [1, 2, 32, 128])
 def test_every_geometry_batched(lane_bytes, restore_table):
     _, wt = _mods()
     import torch
