@@ -38,6 +38,8 @@ WORKLOADS = {
     "c3": "n=2^28 uint32 sigma=2^20 half uniform, half 64 Gaussian clusters (sd 2^10)",
     "c4": "4096 sequences, n = 2^U with U ~ U[10, 22], sigma from {4, 20, 256, 2^16} "
           "(u8/u8/u8/u16), uniform symbols; one batched build",
+    "c5": "serving: Poisson build requests, n = 2^U with U ~ U[12, 26], sigma from {4, 256, 2^16, 2^20} "
+          "(u8/u8/u16/u32), Zipf(1.0) symbols, 10 rank/select queries per tree, HBM-footprint admission",
 }
 
 
@@ -110,6 +112,8 @@ def main() -> int:
 
     if args.workload == "c4":
         return bench_batch(args)
+    if args.workload == "c5":
+        return bench_serve(args)
     dev = torch.device("cuda:0")
     print("bench: generating workload %s" % args.workload, file=sys.stderr, flush=True)
     S, sigma = None, None
@@ -321,7 +325,7 @@ def bench_batch(args) -> int:
     print("bench: one build call per sequence", file=sys.stderr, flush=True)
     ms_single = timed(one_by_one, max(1, args.steps // 4), 1)
 
-    lvl = [r for r in recs if r["kernel"] == "batch_level"]
+    lvl = [r for r in recs if r["kernel"] in ("batch_level", "batch_small", "batch_mid")]
     lvl_ms = sum(r["ms"] for r in lvl)
     lvl_bytes = sum(r["bytes"] for r in lvl)
     achieved = lvl_bytes / (lvl_ms / 1e3) / 1e9 if lvl_ms > 0 else 0.0
@@ -341,9 +345,93 @@ def bench_batch(args) -> int:
         "config": {"workload": "c4: " + WORKLOADS["c4"], "sequences": m, "total_symbols": total},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": "level phase of the batched build (supsum + prep + level pass, all sequences)"},
+                     "kernel": "batched build kernels: one-workgroup builds of the short sequences and the "
+                               "level phases (supsum + prep + level pass) of the long ones"},
         "one_call_per_sequence": {"ms": ms_single, "symbols_per_s": total / (ms_single / 1e3),
                                   "batched_speedup": ms_single / ms_batch},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_serve(args) -> int:
+    """Serving loop: saturation throughput, then Poisson streams at 0.5 /
+    0.8 / 0.95 of it, with p50/p99 request latency (arrival to answers)."""
+    import torch
+
+    from paper_1610_05994_amd import serve, wtree
+
+    dev = torch.device("cuda:0")
+    P = int(os.environ.get("WT_SERVE_POOL", "48"))
+    print("bench: generating %d serving sequences" % P, file=sys.stderr, flush=True)
+    specs = wtgen.serve_stream(P, 1.0, wtgen.SEED_BASE + 4)
+    pool = serve.make_pool(specs, dev, workers=min(12, os.cpu_count() or 1))
+    for p in pool:
+        p["host"] = None          # only the device copies and counts are needed
+    mean_n = float(np.mean([p["n"] for p in pool]))
+    budget = int(float(os.environ.get("WT_SERVE_BUDGET_GIB", "64")) * (1 << 30))
+    srv = serve.Server(budget_bytes=budget, streams=4, max_inflight=8)
+    torch.cuda.synchronize()
+
+    def run(count, qps, seed, rid0):
+        reqs = serve.requests_from(pool, wtgen.pool_stream(P, count, qps, seed), rid0)
+        srv.run_stream(reqs, timeout=300)
+        st = serve.summarize(reqs)
+        for r in reqs:
+            if r.state == serve.RESIDENT:
+                srv.release(r.rid)
+        return reqs, st
+
+    print("bench: serving warmup", file=sys.stderr, flush=True)
+    run(max(8, args.warmup * 8), 1e9, 1, 0)
+    # saturation: every request present at t = 0
+    nsat = int(os.environ.get("WT_SERVE_SAT", "256"))
+    print("bench: serving saturation (%d requests)" % nsat, file=sys.stderr, flush=True)
+    _, sat = run(nsat, 1e9, 2, 10_000)
+    sustain = sat["symbols_per_s"]
+    loads = {}
+    rid = 20_000
+    for f in (0.5, 0.8, 0.95):
+        qps = f * sustain / mean_n
+        count = int(max(100, min(2000, qps * 4.0)))
+        print("bench: serving load %.2f (%.0f req/s, %d requests)" % (f, qps, count), file=sys.stderr, flush=True)
+        _, st = run(count, qps, int(f * 100), rid)
+        rid += 10_000
+        st["qps"] = qps
+        loads["%.2f" % f] = st
+    # the same saturation requests, one wt_build call each, back to back
+    print("bench: one build call per request", file=sys.stderr, flush=True)
+    reqs = serve.requests_from(pool, wtgen.pool_stream(P, nsat, 1e9, 2), 0)
+    t0 = time.perf_counter()
+    for r in reqs:
+        t = wtree.build(r.S, r.sigma)
+        if len(r.rank_c):
+            t.rank(r.rank_c, r.rank_i)
+        if len(r.sel_c):
+            t.select(r.sel_c, r.sel_j)
+        torch.cuda.synchronize()
+        t.close()
+    one = sum(r.S.numel() for r in reqs) / (time.perf_counter() - t0)
+    srv.close()
+    mid = loads["0.80"]
+    out = {
+        "metric": METRIC,
+        "value": sustain,
+        "unit": "symbols/s",
+        "n_gpus": 1,
+        "steps": nsat,
+        "warmup": args.warmup,
+        "ms_per_step": sat["seconds"] * 1e3 / nsat,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8/u16/u32",
+        "data": "synthetic",
+        "config": {"workload": "c5: " + WORKLOADS["c5"], "pool_sequences": P, "mean_n": mean_n,
+                   "budget_bytes": budget, "streams": 4},
+        "latency_ms": {"p50": mid["p50_ms"], "p99": mid["p99_ms"], "at_load": 0.8},
+        "serving": {"saturation": sat, "loads": loads, "arena_high_water": srv.arena.high_water},
+        "one_call_per_request": {"symbols_per_s": one, "served_speedup": sustain / one},
     }
     print(json.dumps(out), flush=True)
     return 0
