@@ -276,7 +276,7 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         a.symmask = (uint32_t)((1ull << l) - 1);
         const uint64_t lbytes = L.n * L.width * (a.tout ? 2 : 1) + L.words * 8 + L.rank_stride * 8;
         pr = prof_begin(st, "level", i, L.width, L.n, lbytes);
-        err = launch_level(a, L.width, L.lane_bytes, st);
+        err = launch_level(a, L.width, L.lane_bytes, level_multi(L.n, i, L.width, L.lane_bytes), st);
         prof_end(pr, st);
         if (err != hipSuccess) return err;
     }
@@ -398,6 +398,7 @@ static BatchJob make_job(const Layout &L, const void *S, void *tree, uint8_t *wo
     j.ws_supsum = L.ws_supsum;
     j.ws_zo = L.ws_zo;
     j.ws_start = L.ws_start;
+    j.ws_partials = L.ws_partials;
     j.sigma = L.sigma;
     j.width = L.width;
     j.levels = L.levels;
@@ -533,7 +534,9 @@ int wt_build_batch(uint32_t m, const void *const *d_S, const wt_desc *descs, voi
     for (int c = 0; c < kClasses && err == hipSuccess; c++) {
         if (!cls[c].njobs) continue;
         long pr = prof_begin(st, "batch_setup", 0, widths[c], 0, 0);
-        err = launch_batch_setup(cls[c], P.blocks[c], P.sups[c], st);
+        uint64_t max_ctrl = 0;
+        for (uint32_t q : P.order[c]) max_ctrl = std::max(max_ctrl, P.L[q].ws_ctrl_bytes);
+        err = launch_batch_setup(cls[c], max_ctrl, st);
         prof_end(pr, st);
     }
     for (int c = 0; c < kClasses && err == hipSuccess; c++) {
@@ -548,11 +551,12 @@ int wt_build_batch(uint32_t m, const void *const *d_S, const wt_desc *descs, voi
         for (int c = 0; c < kClasses && err == hipSuccess; c++) {
             // the sequences still building level i are a prefix of the class
             uint32_t active = 0;
-            uint64_t blocks = 0, sups = 0, nsym = 0, bytes = 0;
+            uint64_t blocks = 0, sups = 0, nsym = 0, bytes = 0, nsym_multi = 0;
             for (uint32_t q : P.order[c]) {
                 const Layout &L = P.L[q];
                 if (L.levels <= i) break;
                 active++;
+                if (level_multi(L.n, i, L.width, L.lane_bytes)) nsym_multi += L.n;
                 blocks += ceil_div(L.ntiles, kWaves);
                 sups += L.nsup;
                 nsym += L.n;
@@ -560,7 +564,9 @@ int wt_build_batch(uint32_t m, const void *const *d_S, const wt_desc *descs, voi
             }
             if (!active) continue;
             long pr = prof_begin(st, "batch_level", i, widths[c], nsym, bytes);
-            err = launch_batch_level(cls[c], widths[c], kClassLane[c], i, active, blocks, sups, st);
+            // the staged split where most of the level's symbols sit in short nodes
+            err = launch_batch_level(cls[c], widths[c], kClassLane[c], 2 * nsym_multi >= nsym, i, active, blocks, sups,
+                                     st);
             prof_end(pr, st);
         }
     }

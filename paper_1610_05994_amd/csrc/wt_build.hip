@@ -320,9 +320,10 @@ __device__ __forceinline__ unsigned long long plan_chunk(const PlanArgs &a, cons
     return tot;
 }
 
-__global__ __launch_bounds__(kThreads) void k_plan_reduce(PlanArgs a) {
+// Chunk b of a level's nodes: partials[b] = its ones.
+__device__ __forceinline__ void plan_reduce_chunk(const PlanArgs &a, uint64_t b) {
     __shared__ unsigned long long s_w[kWaves];
-    const uint64_t b0 = (uint64_t)blockIdx.x * kScanChunk;
+    const uint64_t b0 = b * kScanChunk;
     unsigned long long sum = 0;
     for (uint64_t k = b0 + threadIdx.x; k < b0 + kScanChunk && k < a.nodes; k += kThreads) sum += a.ones[k];
     sum = wave_sum64(sum);
@@ -331,14 +332,14 @@ __global__ __launch_bounds__(kThreads) void k_plan_reduce(PlanArgs a) {
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
         for (int w = 0; w < kWaves; w++) t += s_w[w];
-        a.partials[blockIdx.x] = t;
+        a.partials[b] = t;
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_plan_partials(PlanArgs a, uint64_t nblocks) {
-    // nblocks <= kMaxScanBlocks: a few consecutive entries per thread
+// Exclusive scan of the nblocks (<= kMaxScanBlocks) partials, in place.
+__device__ __forceinline__ void plan_scan_partials(const PlanArgs &a, uint64_t nblocks) {
     __shared__ unsigned long long s_w[kWaves];
-    const uint64_t per = ceil_div(nblocks, kThreads);
+    const uint64_t per = ceil_div(nblocks, kThreads);  // a few consecutive entries per thread
     const uint64_t k0 = threadIdx.x * per;
     unsigned long long sum = 0;
     for (uint64_t q = 0; q < per; q++)
@@ -352,6 +353,12 @@ __global__ __launch_bounds__(kThreads) void k_plan_partials(PlanArgs a, uint64_t
             off += v;
         }
     }
+}
+
+__global__ __launch_bounds__(kThreads) void k_plan_reduce(PlanArgs a) { plan_reduce_chunk(a, blockIdx.x); }
+
+__global__ __launch_bounds__(kThreads) void k_plan_partials(PlanArgs a, uint64_t nblocks) {
+    plan_scan_partials(a, nblocks);
 }
 
 __global__ __launch_bounds__(kThreads) void k_plan_apply(PlanArgs a) {
@@ -441,20 +448,211 @@ __global__ __launch_bounds__(kThreads) void k_prep(PrepArgs a) { prep_level(a); 
 
 // ----------------------------------------------------------- level pass ---
 
+// Tiles spanning fewer than kRunNodes nodes (several nodes, e.g. at deep
+// levels) are staged in LDS as runs, one per (node, bit), each placed at
+// the 16-byte phase of its destination so that it leaves in aligned chunks.
+constexpr uint32_t kRunNodes = 32;
+
+struct MultiTables {
+    uint32_t key[kRunNodes + 1];     // node's first tile position << 16 | tile ones before it
+    uint32_t st[2 * kRunNodes];      // run r = 2j + b: first staging slot
+    uint32_t len[2 * kRunNodes];     // symbols in the run
+    uint32_t blk[2 * kRunNodes + 1]; // first 16-byte staging block of the run; [2 span] = blocks in all
+    uint32_t cnt[4 * kRunNodes];     // next-level ones per (run, destination-tile parity)
+    uint32_t tix[4 * kRunNodes];     // that destination tile
+    unsigned long long g[2 * kRunNodes];  // destination of the run's first symbol
+};
+constexpr uint32_t kMultiTablesBytes = (uint32_t)((sizeof(MultiTables) + 15) / 16 * 16);
+
+template <int W, int B>
+__host__ __device__ constexpr uint32_t multi_stage_elems() {
+    // every run wastes fewer than CH slots at each end
+    return (uint32_t)tile_syms(W, B) + 2 * kRunNodes * 2 * (16 / W);
+}
+
 // LDS bytes of one wave of a level pass: staging of the split (zeros at
 // [a0, a0+Z), ones at [a1, a1+O) with a1 + O <= TILE + 3*CH - 3), or, for
-// tiles spanning several nodes, next-level counters per (node, bit,
-// destination-tile parity).
-template <int W, int B>
+// tiles spanning many nodes, next-level counters per (node, bit,
+// destination-tile parity); with M, also the run tables and staging of a
+// tile spanning a few nodes.  (M is only used for deep levels: the larger
+// LDS slice lowers occupancy.)
+template <int W, int B, bool M>
 __host__ __device__ constexpr uint32_t level_wave_bytes() {
-    return ((uint32_t)(tile_syms(W, B) + 4 * (16 / W)) * W > 2u * 4u * kNodeCap * 4u)
-               ? (uint32_t)(tile_syms(W, B) + 4 * (16 / W)) * W
-               : 2u * 4u * kNodeCap * 4u;
+    constexpr uint32_t split = (uint32_t)(tile_syms(W, B) + 4 * (16 / W)) * W;
+    constexpr uint32_t counters = 2u * 4u * kNodeCap * 4u;
+    constexpr uint32_t multi = kMultiTablesBytes + multi_stage_elems<W, B>() * W;
+    constexpr uint32_t base = split > counters ? split : counters;
+    return (M && multi > base) ? multi : base;
+}
+
+// Split of a tile whose symbols span nodes vf..vl (fewer than kRunNodes):
+// the symbols of node vf + j with bit b form run r = 2j + b, contiguous in
+// T_{i+1}.  With pf / r1f the tile position and tile ones before the node's
+// first symbol, a symbol at tile position p with r tile ones before it sits
+// at offset (p - pf) - (r - r1f) of its zero run or r - r1f of its one run;
+// the runs start at base + pf - R + O1(v) and start_{i+1}(2v+1) - O1(v) + R
+// (R = prefix + r1f, the rank of the node's first symbol), as in the
+// single-node case.  Runs are staged in LDS at their destination's 16-byte
+// phase and written out in aligned chunks; next-level ones are counted per
+// chunk.
+template <int W, int B>
+__device__ __forceinline__ void stage_multi(const LevelArgs &a, const uint4 (&raw)[B / 16],
+                                            typename MaskT<B / W>::T mb, int nval, uint32_t lr1, uint32_t agg,
+                                            unsigned long long prefix, uint64_t base, uint64_t nvalid, uint32_t vf,
+                                            uint32_t vl, uint32_t nsh, uint8_t *s_wave,
+                                            typename ElemT<W>::T *tout, bool counting, uint32_t sh2,
+                                            unsigned long long *ones_next) {
+    typedef typename ElemT<W>::T T;
+    constexpr int E = B / W;
+    constexpr uint32_t CH = 16 / W;
+    constexpr uint64_t TILE = tile_syms(W, B);
+    constexpr uint32_t kStage = multi_stage_elems<W, B>();
+    const int lane = threadIdx.x & 63;
+    MultiTables *tb = reinterpret_cast<MultiTables *>(s_wave);
+    T *s_stage = reinterpret_cast<T *>(s_wave + kMultiTablesBytes);
+    const uint32_t span = vl - vf + 1;  // nodes of the tile, some possibly empty
+    const uint32_t nruns = 2 * span;
+
+    for (uint32_t q = lane; q <= span; q += 64)
+        tb->key[q] = (q == span) ? (((uint32_t)nvalid << 16) | agg) : 0xFFFFFFFFu;
+    for (uint32_t q = lane; q < 4 * span; q += 64) tb->cnt[q] = 0;
+    wave_sync();
+    // first symbol of every node present in the tile
+    {
+        uint32_t vprev = __shfl_up((raw_elem<W, B>(raw, E - 1) & a.symmask) >> nsh, 1, 64);
+        if (lane == 0) vprev = 0xFFFFFFFFu;
+        uint32_t r = lr1;
+#pragma unroll
+        for (int k = 0; k < E; k++) {
+            if (k < nval) {
+                const uint32_t v = (raw_elem<W, B>(raw, k) & a.symmask) >> nsh;
+                if (v != vprev && v - vf < span) tb->key[v - vf] = (((uint32_t)lane * E + k) << 16) | r;
+                vprev = v;
+                r += (uint32_t)(mb >> k) & 1u;
+            }
+        }
+    }
+    wave_sync();
+    // runs of node j = lane: an empty node takes the next node's key (length 0)
+    {
+        uint32_t key = ((uint32_t)lane <= span) ? tb->key[lane] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t t = __shfl_down(key, d, 64);
+            if (lane + d < 64) key = t < key ? t : key;
+        }
+        const uint32_t knext = __shfl_down(key, 1, 64);
+        uint32_t len0 = 0, len1 = 0, nb0 = 0, nb1 = 0;
+        unsigned long long g0 = 0, g1 = 0;
+        if ((uint32_t)lane < span) {
+            const uint32_t pf = key >> 16, r1f = key & 0xFFFFu;
+            len1 = (knext & 0xFFFFu) - r1f;
+            len0 = ((knext >> 16) - pf) - len1;
+            if (len0 + len1) {
+                const ulonglong2 zo = a.zo[vf + lane];
+                const unsigned long long R = prefix + r1f;
+                g0 = base + pf - R + zo.x;
+                g1 = zo.y + R;
+                nb0 = len0 ? (uint32_t)((g0 % CH + len0 + CH - 1) / CH) : 0u;
+                nb1 = len1 ? (uint32_t)((g1 % CH + len1 + CH - 1) / CH) : 0u;
+            }
+        }
+        const uint32_t incl = wave_incl_scan(nb0 + nb1);
+        const uint32_t b0 = incl - nb0 - nb1;
+        if ((uint32_t)lane < span) {
+            tb->st[2 * lane] = b0 * CH + (uint32_t)(g0 % CH);
+            tb->len[2 * lane] = len0;
+            tb->g[2 * lane] = g0;
+            tb->blk[2 * lane] = b0;
+            tb->st[2 * lane + 1] = (b0 + nb0) * CH + (uint32_t)(g1 % CH);
+            tb->len[2 * lane + 1] = len1;
+            tb->g[2 * lane + 1] = g1;
+            tb->blk[2 * lane + 1] = b0 + nb0;
+        }
+        if (lane == 63) tb->blk[nruns] = incl;
+    }
+    wave_sync();
+    // stage every symbol in its run
+    {
+        uint32_t r = lr1, jc = 0xFFFFFFFFu, st0 = 0, st1 = 0, pf = 0, r1f = 0;
+#pragma unroll
+        for (int k = 0; k < E; k++) {
+            if (k < nval) {
+                const uint32_t x = raw_elem<W, B>(raw, k) & a.symmask;
+                const uint32_t j = (x >> nsh) - vf;
+                const uint32_t b = (uint32_t)(mb >> k) & 1u;
+                if (j != jc && j < span) {
+                    jc = j;
+                    const uint32_t key = tb->key[j];
+                    pf = key >> 16;
+                    r1f = key & 0xFFFFu;
+                    st0 = tb->st[2 * j];
+                    st1 = tb->st[2 * j + 1];
+                }
+                if (j < span) {
+                    const uint32_t p = (uint32_t)lane * E + k;
+                    const uint32_t idx = b ? st1 + (r - r1f) : st0 + (p - pf) - (r - r1f);
+                    if (idx < kStage) s_stage[idx] = (T)x;
+                }
+                r += b;
+            }
+        }
+    }
+    wave_sync();
+    // write the runs out, one 16-byte staging block per lane and step
+    const uint32_t nblk = tb->blk[nruns];
+    for (uint32_t blk = (uint32_t)lane; blk < nblk; blk += 64) {
+        uint32_t lo = 0, hi = nruns - 1;  // last run whose first block is <= blk
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (tb->blk[mid] <= blk) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t st = tb->st[lo], len = tb->len[lo];
+        const unsigned long long g = tb->g[lo];
+        const uint32_t s = blk * CH;
+        if (s + CH > kStage) continue;  // (only with inconsistent tables)
+        const uint4 v = *reinterpret_cast<const uint4 *>(&s_stage[s]);
+        uint32_t ones = 0;
+        unsigned long long gfirst;
+        if (s >= st && s + CH <= st + len && g + (s - st) + CH <= a.n) {
+            gfirst = g + (s - st);
+            *reinterpret_cast<uint4 *>(tout + gfirst) = v;
+            if (counting) ones = chunk_bit_count<W>(v, sh2);
+        } else {
+            gfirst = g + ((s > st ? s : st) - st);
+#pragma unroll
+            for (int e = 0; e < (int)CH; e++) {
+                const uint32_t q = s + e;
+                if (q >= st && q < st + len && g + (q - st) < a.n) {
+                    const uint32_t x = chunk_elem<W>(v, e);
+                    tout[g + (q - st)] = (T)x;
+                    ones += (x >> sh2) & 1u;
+                }
+            }
+        }
+        if (counting && ones) {
+            const uint64_t dt = gfirst / TILE;  // a block's symbols share one destination tile
+            const uint32_t key = 2 * lo + (uint32_t)(dt & 1);
+            atomicAdd(&tb->cnt[key], ones);
+            tb->tix[key] = (uint32_t)dt;
+        }
+    }
+    if (!counting) return;
+    wave_sync();
+    for (uint32_t q = lane; q < 4 * span; q += 64) {
+        const uint32_t c = tb->cnt[q];
+        if (c) {
+            const uint32_t r = q >> 1;
+            atomicAdd(&a.tile_ones_next[tb->tix[q]], c);
+            atomicAdd(&ones_next[2ull * (vf + (r >> 1)) + (r & 1u)], (unsigned long long)c);
+        }
+    }
 }
 
 // One level pass over tile t, run by one wave (each lane B bytes = E = B/W
 // symbols of T_i); s_wave is the wave's own LDS slice.  No workgroup barrier.
-template <int W, int B>
+template <int W, int B, bool kMulti>
 __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8_t *s_wave) {
     typedef typename ElemT<W>::T T;
     constexpr int E = B / W;                    // symbols per lane
@@ -602,7 +800,13 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         return;
     }
 
-    // Several nodes: every symbol goes straight to its destination.
+    if (kMulti && vl - vf < kRunNodes) {
+        stage_multi<W, B>(a, raw, mb, nval, lr1, agg, prefix, base, nvalid, vf, vl, nsh, s_wave, tout, counting, sh2,
+                          ones_next);
+        return;
+    }
+
+    // Many nodes: every symbol goes straight to its destination.
     const bool lds_counts = counting && (vl - vf < kNodeCap);
     if (lds_counts) {
         for (uint32_t q = lane; q < 4 * (vl - vf + 1); q += 64) s_cnt[q] = 0;
@@ -649,13 +853,13 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
 }
 
 
-template <int W, int B>
+template <int W, int B, bool M>
 __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
-    __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W, B>()];
+    __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W, B, M>()];
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t t = (uint64_t)blockIdx.x * kWaves + wv;
     if (t >= a.ntiles) return;  // whole wave
-    level_tile<W, B>(a, t, s_all + wv * level_wave_bytes<W, B>());
+    level_tile<W, B, M>(a, t, s_all + wv * level_wave_bytes<W, B, M>());
 }
 
 // ------------------------------------------------------------ batched ---
@@ -703,11 +907,11 @@ __device__ __forceinline__ PrepArgs job_prep(const BatchJob &j, uint32_t i) {
     p.plan.ones = reinterpret_cast<const unsigned long long *>(w + j.ws_ones) + ones_offset(i);
     p.plan.zo = reinterpret_cast<ulonglong2 *>(w + j.ws_zo) + zo_offset(i);
     p.plan.start_next = (i + 1 < j.levels) ? start + start_offset(i + 1) : nullptr;
-    p.plan.partials = nullptr;
+    p.plan.partials = reinterpret_cast<uint64_t *>(w + j.ws_partials);
     p.plan.nodes = 1ull << i;
     p.plan.slots = level_slots(i);
     p.plan.n = j.n;
-    p.plan_here = 1u;
+    p.plan_here = (p.plan.nodes > kScanChunk) ? 0u : 1u;  // larger levels: the k_batch_plan_* kernels
     return p;
 }
 
@@ -731,18 +935,22 @@ __device__ __forceinline__ IngestArgs job_ingest(const BatchJob &j) {
 
 // Workgroup j: fill the maps of sequence j, then clear its control area and
 // tree status (and, for an empty sequence, its rank directories).
-__global__ __launch_bounds__(kThreads) void k_batch_setup(BatchClass c) {
-    const BatchJob &j = c.jobs[blockIdx.x];
+// Workgroups [g * parts, (g + 1) * parts) set up sequence g: its block
+// maps, zeroed counters and status word.
+__global__ __launch_bounds__(kThreads) void k_batch_setup(BatchClass c, uint32_t parts) {
+    const uint32_t q = blockIdx.x / parts, part = blockIdx.x % parts;
+    const BatchJob &j = c.jobs[q];
+    const uint64_t first = (uint64_t)part * kThreads + threadIdx.x, stride = (uint64_t)parts * kThreads;
     const uint64_t nb = ceil_div(j.ntiles, kWaves);
-    for (uint64_t b = threadIdx.x; b < nb; b += kThreads) c.blk_map[j.blk_base + b] = blockIdx.x;
-    for (uint64_t b = threadIdx.x; b < j.nsup; b += kThreads) c.sup_map[j.sup_base + b] = blockIdx.x;
-    uint64_t *ctrl = reinterpret_cast<uint64_t *>(j.work + j.ws_ctrl);
-    for (uint64_t k = threadIdx.x; k < j.ws_ctrl_bytes / 8; k += kThreads) ctrl[k] = 0;
+    for (uint64_t b = first; b < nb; b += stride) c.blk_map[j.blk_base + b] = q;
+    for (uint64_t b = first; b < j.nsup; b += stride) c.sup_map[j.sup_base + b] = q;
+    uint4 *ctrl = reinterpret_cast<uint4 *>(j.work + j.ws_ctrl);  // 256-byte aligned and sized
+    for (uint64_t k = first; k < j.ws_ctrl_bytes / 16; k += stride) ctrl[k] = make_uint4(0, 0, 0, 0);
     if (j.n == 0) {
         uint64_t *r = reinterpret_cast<uint64_t *>(j.tree + j.tree_ranks_off);
-        for (uint64_t k = threadIdx.x; k < (uint64_t)j.levels * j.rank_stride; k += kThreads) r[k] = 0;
+        for (uint64_t k = first; k < (uint64_t)j.levels * j.rank_stride; k += stride) r[k] = 0;
     }
-    if (threadIdx.x == 0) *reinterpret_cast<uint32_t *>(j.tree) = 0;
+    if (part == 0 && threadIdx.x == 0) *reinterpret_cast<uint32_t *>(j.tree) = 0;
 }
 
 template <int W, int B>
@@ -772,14 +980,33 @@ __global__ __launch_bounds__(kThreads) void k_batch_prep(BatchClass c, uint32_t 
     prep_level(job_prep(c.jobs[blockIdx.x], level));
 }
 
-template <int W, int B>
+// Node tables of levels above kScanChunk nodes, chunks of every active
+// sequence side by side: workgroup b serves sequence b / cpj, chunk b % cpj
+// (every sequence has 2^level nodes, so cpj chunks, at this level).
+__global__ __launch_bounds__(kThreads) void k_batch_plan_reduce(BatchClass c, uint32_t level, uint32_t cpj) {
+    const PrepArgs p = job_prep(c.jobs[blockIdx.x / cpj], level);
+    plan_reduce_chunk(p.plan, blockIdx.x % cpj);
+}
+
+__global__ __launch_bounds__(kThreads) void k_batch_plan_partials(BatchClass c, uint32_t level, uint32_t cpj) {
+    const PrepArgs p = job_prep(c.jobs[blockIdx.x], level);
+    plan_scan_partials(p.plan, cpj);
+}
+
+__global__ __launch_bounds__(kThreads) void k_batch_plan_apply(BatchClass c, uint32_t level, uint32_t cpj) {
+    const PrepArgs p = job_prep(c.jobs[blockIdx.x / cpj], level);
+    const uint64_t b = blockIdx.x % cpj;
+    plan_chunk(p.plan, p.plan.ones + b * kScanChunk, b * kScanChunk, p.plan.partials[b]);
+}
+
+template <int W, int B, bool M>
 __global__ __launch_bounds__(kThreads) void k_batch_level(BatchClass c, uint32_t level) {
-    __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W, B>()];
+    __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W, B, M>()];
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const BatchJob &j = c.jobs[c.blk_map[blockIdx.x]];
     const uint64_t t = (blockIdx.x - j.blk_base) * kWaves + wv;
     if (t >= j.ntiles) return;  // whole wave
-    level_tile<W, B>(job_level(j, level), t, s_all + wv * level_wave_bytes<W, B>());
+    level_tile<W, B, M>(job_level(j, level), t, s_all + wv * level_wave_bytes<W, B, M>());
 }
 
 }  // namespace
@@ -818,6 +1045,31 @@ hipError_t launch_zero(void *p, uint64_t bytes, uint32_t *tree_status, uint64_t 
         }                                                                                              \
     } while (0)
 
+// Launch KERNEL<width, lane_bytes, multi> (level passes: with or without
+// the staged split of tiles spanning a few nodes).
+#define WT_LAUNCH_WBM(KERNEL, W_, LB_, M_, GRID, ...)                                                    \
+    do {                                                                                                \
+        switch ((W_) * 10000 + (LB_) * 10 + ((M_) ? 1 : 0)) {                                          \
+            case 10320: hipLaunchKernelGGL((KERNEL<1, 32, false>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;  \
+            case 10321: hipLaunchKernelGGL((KERNEL<1, 32, true>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;   \
+            case 10640: hipLaunchKernelGGL((KERNEL<1, 64, false>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;  \
+            case 10641: hipLaunchKernelGGL((KERNEL<1, 64, true>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;   \
+            case 20320: hipLaunchKernelGGL((KERNEL<2, 32, false>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;  \
+            case 20321: hipLaunchKernelGGL((KERNEL<2, 32, true>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;   \
+            case 20640: hipLaunchKernelGGL((KERNEL<2, 64, false>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;  \
+            case 20641: hipLaunchKernelGGL((KERNEL<2, 64, true>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;   \
+            case 21280: hipLaunchKernelGGL((KERNEL<2, 128, false>), GRID, dim3(kThreads), 0, __VA_ARGS__); break; \
+            case 21281: hipLaunchKernelGGL((KERNEL<2, 128, true>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;  \
+            case 40320: hipLaunchKernelGGL((KERNEL<4, 32, false>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;  \
+            case 40321: hipLaunchKernelGGL((KERNEL<4, 32, true>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;   \
+            case 40640: hipLaunchKernelGGL((KERNEL<4, 64, false>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;  \
+            case 40641: hipLaunchKernelGGL((KERNEL<4, 64, true>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;   \
+            case 41280: hipLaunchKernelGGL((KERNEL<4, 128, false>), GRID, dim3(kThreads), 0, __VA_ARGS__); break; \
+            case 41281: hipLaunchKernelGGL((KERNEL<4, 128, true>), GRID, dim3(kThreads), 0, __VA_ARGS__); break;  \
+            default: return hipErrorInvalidValue;                                                       \
+        }                                                                                               \
+    } while (0)
+
 hipError_t launch_ingest(const IngestArgs &a, uint32_t width, uint32_t lane_bytes, hipStream_t s) {
     const dim3 g((uint32_t)ceil_div(a.ntiles, a.tiles_per_block));
     WT_LAUNCH_WB(k_ingest, width, lane_bytes, g, s, a);
@@ -838,16 +1090,17 @@ hipError_t launch_plan(const PlanArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_level(const LevelArgs &a, uint32_t width, uint32_t lane_bytes, hipStream_t s) {
+hipError_t launch_level(const LevelArgs &a, uint32_t width, uint32_t lane_bytes, bool multi, hipStream_t s) {
     const dim3 g((uint32_t)ceil_div(a.ntiles, kWaves));
-    WT_LAUNCH_WB(k_level, width, lane_bytes, g, s, a);
+    WT_LAUNCH_WBM(k_level, width, lane_bytes, multi, g, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_setup(const BatchClass &c, uint64_t blocks, uint64_t sups, hipStream_t s) {
-    (void)blocks;
-    (void)sups;
-    hipLaunchKernelGGL(k_batch_setup, dim3(c.njobs), dim3(kThreads), 0, s, c);
+hipError_t launch_batch_setup(const BatchClass &c, uint64_t max_ctrl_bytes, hipStream_t s) {
+    // about 256 KB of counters per workgroup for the largest sequence
+    uint64_t parts = max_ctrl_bytes >> 18;
+    parts = parts < 1 ? 1 : (parts > 64 ? 64 : parts);
+    hipLaunchKernelGGL(k_batch_setup, dim3(c.njobs * (uint32_t)parts), dim3(kThreads), 0, s, c, (uint32_t)parts);
     return hipGetLastError();
 }
 
@@ -860,12 +1113,18 @@ hipError_t launch_batch_ingest(const BatchClass &c, uint32_t width, uint32_t lan
 
 // Level `level` of the first `active` sequences of the class: superchunk
 // sums, prefixes and node tables, then the level pass.
-hipError_t launch_batch_level(const BatchClass &c, uint32_t width, uint32_t lane_bytes, uint32_t level,
+hipError_t launch_batch_level(const BatchClass &c, uint32_t width, uint32_t lane_bytes, bool multi, uint32_t level,
                               uint32_t active, uint64_t blocks, uint64_t sups, hipStream_t s) {
     if (active == 0) return hipSuccess;
+    if ((1ull << level) > kScanChunk) {
+        const uint32_t cpj = (uint32_t)((1ull << level) / kScanChunk);
+        hipLaunchKernelGGL(k_batch_plan_reduce, dim3(active * cpj), dim3(kThreads), 0, s, c, level, cpj);
+        hipLaunchKernelGGL(k_batch_plan_partials, dim3(active), dim3(kThreads), 0, s, c, level, cpj);
+        hipLaunchKernelGGL(k_batch_plan_apply, dim3(active * cpj), dim3(kThreads), 0, s, c, level, cpj);
+    }
     if (sups) hipLaunchKernelGGL(k_batch_supsum, dim3((uint32_t)sups), dim3(kThreads), 0, s, c, level);
     hipLaunchKernelGGL(k_batch_prep, dim3(active), dim3(kThreads), 0, s, c, level);
-    if (blocks) WT_LAUNCH_WB(k_batch_level, width, lane_bytes, dim3((uint32_t)blocks), s, c, level);
+    if (blocks) WT_LAUNCH_WBM(k_batch_level, width, lane_bytes, multi, dim3((uint32_t)blocks), s, c, level);
     return hipGetLastError();
 }
 

@@ -150,6 +150,7 @@ struct BatchJob {
     uint64_t n, words, rank_entries, rank_stride, ntiles, nsup;
     uint64_t tree_bits_off, tree_ranks_off;
     uint64_t ws_ta, ws_tb, ws_ctrl, ws_ctrl_bytes, ws_tile_ones, ws_ones, ws_sup, ws_supsum, ws_zo, ws_start;
+    uint64_t ws_partials;
     uint64_t blk_base;  // first workgroup of this sequence in its class's tile map
     uint64_t sup_base;  // first workgroup of this sequence in its class's superchunk map
     uint32_t sigma, width, levels, check, lane_bytes;
@@ -182,11 +183,17 @@ hipError_t launch_zero(void *p, uint64_t bytes, uint32_t *tree_status, uint64_t 
 hipError_t launch_ingest(const IngestArgs &a, uint32_t width, uint32_t lane_bytes, hipStream_t s);
 hipError_t launch_prep(const PrepArgs &a, hipStream_t s);  // k_supsum, then k_prep
 hipError_t launch_plan(const PlanArgs &a, hipStream_t s);
-hipError_t launch_level(const LevelArgs &a, uint32_t width, uint32_t lane_bytes, hipStream_t s);
-hipError_t launch_batch_setup(const BatchClass &c, uint64_t blocks, uint64_t sups, hipStream_t s);
+hipError_t launch_level(const LevelArgs &a, uint32_t width, uint32_t lane_bytes, bool multi, hipStream_t s);
+// Level passes take the staged split of tiles spanning a few nodes where the
+// average node is shorter than this many tiles.
+constexpr uint64_t kMultiAvgTiles = 8;
+__host__ __device__ constexpr bool level_multi(uint64_t n, uint32_t level, uint32_t width, uint32_t lane_bytes) {
+    return (n >> level) < kMultiAvgTiles * tile_syms(width, lane_bytes);
+}
+hipError_t launch_batch_setup(const BatchClass &c, uint64_t max_ctrl_bytes, hipStream_t s);
 hipError_t launch_batch_ingest(const BatchClass &c, uint32_t width, uint32_t lane_bytes, uint64_t blocks,
                                hipStream_t s);
-hipError_t launch_batch_level(const BatchClass &c, uint32_t width, uint32_t lane_bytes, uint32_t level,
+hipError_t launch_batch_level(const BatchClass &c, uint32_t width, uint32_t lane_bytes, bool multi, uint32_t level,
                               uint32_t active, uint64_t blocks, uint64_t sups, hipStream_t s);
 
 // query launchers (wt_query.hip)
