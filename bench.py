@@ -85,6 +85,28 @@ def cpu_baseline(workload: str, lg: int, runs: int):
     }
 
 
+def cpu_multicore(workload: str, lg: int, runs: int):
+    """The paper's parallel algorithms (pwt, dd) on every host core, on the
+    same bounded sample as the oracle baseline."""
+    from paper_1610_05994_amd import cpu_baseline as cb
+    S, sigma = wtgen.workload("%s@lg%d" % (workload, lg))
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = int(os.environ.get("OMP_NUM_THREADS", threads))
+    out = {}
+    for algo in cb.ALGOS:
+        cb.build(S[:4096], sigma, algo, threads)
+        times = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            rc, _, _ = cb.build(S, sigma, algo, threads)
+            times.append(time.perf_counter() - t0)
+            assert rc == 0
+        med = statistics.median(times)
+        out[algo] = {"value": S.shape[0] / med, "unit": "symbols/s", "cores": threads,
+                     "sample": "n=2^%d symbols of the same generator, median of %d runs of %.3f s" % (lg, runs, med)}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,6 +262,7 @@ def main() -> int:
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline on n=2^%d" % args.cpu_sample_lg, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_lg, args.cpu_runs)
+        out["cpu_multicore"] = cpu_multicore(args.workload, args.cpu_sample_lg, args.cpu_runs)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -146,6 +146,23 @@ int wt_select_batch(const wt_tree *tree, const uint32_t *d_c, const uint64_t *d_
                     uint64_t *d_pos, uint64_t m, void *stream);
 
 /*
+ * Mixed queries over many trees in one launch (for serving).  Query k asks
+ * tree trees[d_tree[k]] (d_tree[k] < ntrees): d_kind[k] = 0 access(d_x[k]),
+ * 1 rank(d_c[k], d_x[k]), 2 select(d_c[k], d_x[k]); d_out[k] receives the
+ * symbol, the count or the position, with UINT64_MAX wherever the per-tree
+ * calls above return their out-of-range value (and for an unknown kind or
+ * tree index).  d_work is device memory of wt_query_multi_footprint(ntrees)
+ * bytes (16-byte aligned) into which the trees' layouts are copied on
+ * `stream`; it must stay untouched until the stream has passed the queries.
+ * The trees must be complete by the time the stream reaches the queries
+ * (same stream as their builds, or synchronised).
+ */
+int wt_query_multi_footprint(uint32_t ntrees, uint64_t *work_bytes);
+int wt_query_multi(uint32_t ntrees, const wt_tree *const *trees, const uint32_t *d_tree,
+                   const uint8_t *d_kind, const uint32_t *d_c, const uint64_t *d_x, uint64_t *d_out,
+                   uint64_t m, void *d_work, uint64_t work_bytes, void *stream);
+
+/*
  * Single queries for verification: they run the batched kernels on the
  * build's stream and wait for the answer.  WT_EINVAL for i out of range or
  * c >= sigma, WT_ENOTFOUND for a select with no such occurrence.

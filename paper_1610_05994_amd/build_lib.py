@@ -26,6 +26,21 @@ FLAGS = [
 ]
 
 
+CPU_SRC = os.path.join(PKG, "cpu", "wt_cpu.c")
+CPU_LIB = os.path.join(PKG, "libwtcpu.so")
+
+
+def build_cpu(verbose: bool = False) -> str:
+    """The multicore CPU comparator (OpenMP), a separate host library."""
+    tmp = CPU_LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, CPU_SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, CPU_LIB)
+    return CPU_LIB
+
+
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp%d" % os.getpid()
@@ -39,4 +54,6 @@ def build(verbose: bool = False) -> str:
 
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv)
+    build_cpu(verbose="-v" in sys.argv)
     print(LIB)
+    print(CPU_LIB)

@@ -628,6 +628,31 @@ int wt_select_batch(const wt_tree *t, const uint32_t *d_c, const uint64_t *d_j, 
                ? WT_OK : WT_EDEVICE;
 }
 
+int wt_query_multi_footprint(uint32_t ntrees, uint64_t *work_bytes) {
+    if (!work_bytes) return WT_EINVAL;
+    *work_bytes = round_up((uint64_t)(ntrees ? ntrees : 1) * sizeof(TreeView), 256);
+    return WT_OK;
+}
+
+int wt_query_multi(uint32_t ntrees, const wt_tree *const *trees, const uint32_t *d_tree, const uint8_t *d_kind,
+                   const uint32_t *d_c, const uint64_t *d_x, uint64_t *d_out, uint64_t m, void *d_work,
+                   uint64_t work_bytes, void *stream) {
+    if (m == 0) return WT_OK;
+    if (!trees || ntrees == 0 || !d_tree || !d_kind || !d_c || !d_x || !d_out || !d_work) return WT_EINVAL;
+    if (((uintptr_t)d_work & 15) || work_bytes < (uint64_t)ntrees * sizeof(TreeView)) return WT_ENOMEM;
+    std::vector<TreeView> views(ntrees);
+    for (uint32_t k = 0; k < ntrees; k++) {
+        if (!trees[k]) return WT_EINVAL;
+        views[k] = view_of(trees[k]);
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    // (pageable source: the call returns once the layouts are staged)
+    if (hipMemcpyAsync(d_work, views.data(), ntrees * sizeof(TreeView), hipMemcpyHostToDevice, st) != hipSuccess)
+        return WT_EDEVICE;
+    return launch_query_multi(reinterpret_cast<const TreeView *>(d_work), ntrees, d_tree, d_kind, d_c, d_x, d_out, m,
+                              st) == hipSuccess ? WT_OK : WT_EDEVICE;
+}
+
 // Single queries: argument 0 of the scratch holds the query, 2 the answer.
 static int single_query(const wt_tree *t, int kind, uint32_t c, uint64_t x, uint64_t *ans) {
     wt_tree *h = const_cast<wt_tree *>(t);

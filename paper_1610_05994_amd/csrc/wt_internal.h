@@ -209,5 +209,7 @@ hipError_t launch_rank(const TreeView &t, const uint32_t *c, const uint64_t *i, 
                        uint64_t m, hipStream_t s);
 hipError_t launch_select(const TreeView &t, const uint32_t *c, const uint64_t *j,
                          uint64_t *pos, uint64_t m, hipStream_t s);
+hipError_t launch_query_multi(const TreeView *d_views, uint32_t ntrees, const uint32_t *tree, const uint8_t *kind,
+                              const uint32_t *c, const uint64_t *x, uint64_t *out, uint64_t m, hipStream_t s);
 
 }  // namespace wt

@@ -77,11 +77,9 @@ __device__ uint64_t select0(const Level &L, uint64_t K, uint64_t n, uint64_t m) 
     return w * 64 + select_in_word(~L.B[w], (uint32_t)(m - r - 1));
 }
 
-__global__ void k_access(TreeView t, const uint64_t *qi, uint32_t *out, uint64_t m) {
-    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= m) return;
-    const uint64_t i = qi[q];
-    if (i >= t.n) { out[q] = 0xFFFFFFFFu; return; }
+// access(i): the symbol at position i (0xFFFFFFFF if i >= n).
+__device__ uint32_t access_one(const TreeView &t, uint64_t i) {
+    if (i >= t.n) return 0xFFFFFFFFu;
     uint64_t b = 0, e = t.n, p = i;
     uint32_t s = 0;
     for (uint32_t k = 0; k < t.levels; k++) {
@@ -94,17 +92,14 @@ __global__ void k_access(TreeView t, const uint64_t *qi, uint32_t *out, uint64_t
         else     { before = (p - b) - (rp - rb); e = b + zeros; }
         p = b + before;
         s = (s << 1) | bit;
-        if (p >= e || e > t.n) { out[q] = 0xFFFFFFFEu; return; }  // corrupted tree only
+        if (p >= e || e > t.n) return 0xFFFFFFFEu;  // corrupted tree only
     }
-    out[q] = s;
+    return s;
 }
 
-__global__ void k_rank(TreeView t, const uint32_t *qc, const uint64_t *qi, uint64_t *out, uint64_t m) {
-    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= m) return;
-    const uint32_t c = qc[q];
-    const uint64_t i = qi[q];
-    if (c >= t.sigma || i > t.n) { out[q] = ~0ull; return; }
+// rank(c, i): occurrences of c in S[0, i) (UINT64_MAX if c >= sigma or i > n).
+__device__ uint64_t rank_one(const TreeView &t, uint32_t c, uint64_t i) {
+    if (c >= t.sigma || i > t.n) return ~0ull;
     uint64_t b = 0, e = t.n, cnt = i;
     for (uint32_t k = 0; k < t.levels; k++) {
         const Level L = level_of(t, k);
@@ -113,17 +108,14 @@ __global__ void k_rank(TreeView t, const uint32_t *qc, const uint64_t *qi, uint6
         const uint64_t ones_before = rank1(L, b + cnt) - rb;
         if ((c >> (t.levels - 1 - k)) & 1u) { cnt = ones_before; b = b + zeros; }
         else                                 { cnt = cnt - ones_before; e = b + zeros; }
-        if (b + cnt > e || e > t.n) { out[q] = ~1ull; return; }  // corrupted tree only
+        if (b + cnt > e || e > t.n) return ~1ull;  // corrupted tree only
     }
-    out[q] = cnt;
+    return cnt;
 }
 
-__global__ void k_select(TreeView t, const uint32_t *qc, const uint64_t *qj, uint64_t *out, uint64_t m) {
-    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= m) return;
-    const uint32_t c = qc[q];
-    const uint64_t j = qj[q];
-    if (c >= t.sigma) { out[q] = ~0ull; return; }
+// select(c, j): 0-based position of the j-th (1-based) c (UINT64_MAX if none).
+__device__ uint64_t select_one(const TreeView &t, uint32_t c, uint64_t j) {
+    if (c >= t.sigma) return ~0ull;
     uint64_t bs[32];
     uint64_t b = 0, e = t.n;
     for (uint32_t k = 0; k < t.levels; k++) {  // node ranges of c, top-down
@@ -132,9 +124,9 @@ __global__ void k_select(TreeView t, const uint32_t *qc, const uint64_t *qj, uin
         const uint64_t rb = rank1(L, b), re = rank1(L, e);
         const uint64_t zeros = (e - b) - (re - rb);
         if ((c >> (t.levels - 1 - k)) & 1u) b = b + zeros; else e = b + zeros;
-        if (b > e || e > t.n) { out[q] = ~1ull; return; }  // corrupted tree only
+        if (b > e || e > t.n) return ~1ull;  // corrupted tree only
     }
-    if (j == 0 || j > e - b) { out[q] = ~0ull; return; }
+    if (j == 0 || j > e - b) return ~0ull;
     uint64_t idx = j - 1;
     for (uint32_t k = t.levels; k-- > 0;) {  // bottom-up back to S
         const Level L = level_of(t, k);
@@ -143,10 +135,45 @@ __global__ void k_select(TreeView t, const uint32_t *qc, const uint64_t *qj, uin
         uint64_t pos;
         if ((c >> (t.levels - 1 - k)) & 1u) pos = select1(L, t.rank_entries, (t.n + 63) / 64, rb + idx + 1);
         else pos = select0(L, t.rank_entries, t.n, (bb - rb) + idx + 1);
-        if (pos >= t.n) { out[q] = ~0ull; return; }
+        if (pos >= t.n) return ~0ull;
         idx = pos - bb;
     }
-    out[q] = idx;
+    return idx;
+}
+
+__global__ void k_access(TreeView t, const uint64_t *qi, uint32_t *out, uint64_t m) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < m) out[q] = access_one(t, qi[q]);
+}
+
+__global__ void k_rank(TreeView t, const uint32_t *qc, const uint64_t *qi, uint64_t *out, uint64_t m) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < m) out[q] = rank_one(t, qc[q], qi[q]);
+}
+
+__global__ void k_select(TreeView t, const uint32_t *qc, const uint64_t *qj, uint64_t *out, uint64_t m) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < m) out[q] = select_one(t, qc[q], qj[q]);
+}
+
+// Mixed queries over many trees: query q asks tree views[tree[q]].
+__global__ void k_query_multi(const TreeView *views, uint32_t ntrees, const uint32_t *tree, const uint8_t *kind,
+                              const uint32_t *qc, const uint64_t *qx, uint64_t *out, uint64_t m) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const uint32_t ti = tree[q];
+    if (ti >= ntrees) { out[q] = ~0ull; return; }
+    const TreeView t = views[ti];
+    switch (kind[q]) {
+        case 0: {
+            const uint32_t s = access_one(t, qx[q]);
+            out[q] = (s == 0xFFFFFFFFu) ? ~0ull : (s == 0xFFFFFFFEu ? ~1ull : (uint64_t)s);
+            break;
+        }
+        case 1: out[q] = rank_one(t, qc[q], qx[q]); break;
+        case 2: out[q] = select_one(t, qc[q], qx[q]); break;
+        default: out[q] = ~0ull;
+    }
 }
 
 inline uint32_t blocks_for(uint64_t m) { return (uint32_t)((m + 255) / 256); }
@@ -163,6 +190,13 @@ hipError_t launch_rank(const TreeView &t, const uint32_t *c, const uint64_t *i, 
                        hipStream_t s) {
     if (m == 0) return hipSuccess;
     hipLaunchKernelGGL(k_rank, dim3(blocks_for(m)), dim3(256), 0, s, t, c, i, r, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_query_multi(const TreeView *d_views, uint32_t ntrees, const uint32_t *tree, const uint8_t *kind,
+                              const uint32_t *c, const uint64_t *x, uint64_t *out, uint64_t m, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_query_multi, dim3(blocks_for(m)), dim3(256), 0, s, d_views, ntrees, tree, kind, c, x, out, m);
     return hipGetLastError();
 }
 

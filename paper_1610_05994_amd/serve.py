@@ -346,39 +346,44 @@ class Server:
             ns = 0 if r.sel_c is None else len(r.sel_c)
             nq.append((nr, ns))
             tot += nr + ns
+        # every query of the batch in one launch: per query its tree, kind
+        # (1 rank, 2 select), symbol and argument
+        qt = np.repeat(np.arange(m, dtype=np.uint32), [a + b for a, b in nq]) if tot else np.zeros(0, np.uint32)
+        qk = np.concatenate([np.concatenate([np.full(a, 1, np.uint8), np.full(b, 2, np.uint8)]) for a, b in nq]) \
+            if tot else np.zeros(0, np.uint8)
+        empty32, empty64 = np.zeros(0, np.int32), np.zeros(0, np.int64)
+        qc = np.concatenate([np.concatenate([r.rank_c if r.rank_c is not None else empty32,
+                                             r.sel_c if r.sel_c is not None else empty32]) for r in picked]) \
+            .astype(np.int32) if tot else empty32
+        qx = np.concatenate([np.concatenate([r.rank_i if r.rank_i is not None else empty64,
+                                             r.sel_j if r.sel_j is not None else empty64]) for r in picked]) \
+            .astype(np.int64) if tot else empty64
         with torch.cuda.stream(st):
             dev = torch.empty(m + tot, dtype=torch.int64, device=self.device)
             # status words of the trees (first 4 bytes of each tree)
             offs = torch.tensor([o // 4 for o in tree_offs], dtype=torch.int64, device=self.device)
             dev[:m] = self.mem.view(torch.int32).index_select(0, offs).to(torch.int64)
-            qc = np.concatenate([np.concatenate([r.rank_c if r.rank_c is not None else np.zeros(0, np.int32),
-                                                 r.sel_c if r.sel_c is not None else np.zeros(0, np.int32)])
-                                 for r in picked]).astype(np.int32) if tot else np.zeros(0, np.int32)
-            qx = np.concatenate([np.concatenate([r.rank_i if r.rank_i is not None else np.zeros(0, np.int64),
-                                                 r.sel_j if r.sel_j is not None else np.zeros(0, np.int64)])
-                                 for r in picked]).astype(np.int64) if tot else np.zeros(0, np.int64)
-            d_c = torch.from_numpy(qc).to(self.device, non_blocking=False) if tot else None
-            d_x = torch.from_numpy(qx).to(self.device, non_blocking=False) if tot else None
-        k = 0
+            packed = None
+            if tot:
+                # one host-to-device copy for all query arguments
+                blob = np.concatenate([qx.view(np.uint8), qc.view(np.uint8), qt.view(np.uint8), qk])
+                packed = torch.from_numpy(blob).to(self.device)
+                rc_w, wb = wt.wt_query_multi_footprint(m)
+                views = torch.empty(wb, dtype=torch.uint8, device=self.device)
+                base = packed.data_ptr()
+                rc = wt.wt_query_multi(hs, base + 12 * tot, base + 16 * tot, base + 8 * tot, base,
+                                       dev.data_ptr() + 8 * m, tot, views.data_ptr(), wb, int(st.cuda_stream))
+                if rc != wt.WT_OK:
+                    raise wt.WtError(rc, "wt_query_multi")
+                packed = (packed, views)
         for q, (r, h) in enumerate(zip(picked, hs)):
             r.handle, r.tree_off, r.t_admit, r.state = h, tree_offs[q], now, RUNNING
-            nr, ns = nq[q]
-            if nr:
-                rc = wt.wt_rank_batch(h, d_c.data_ptr() + 4 * k, d_x.data_ptr() + 8 * k,
-                                      dev.data_ptr() + 8 * (m + k), nr, int(st.cuda_stream))
-                assert rc == wt.WT_OK
-            k += nr
-            if ns:
-                rc = wt.wt_select_batch(h, d_c.data_ptr() + 4 * k, d_x.data_ptr() + 8 * k,
-                                        dev.data_ptr() + 8 * (m + k), ns, int(st.cuda_stream))
-                assert rc == wt.WT_OK
-            k += ns
         host = torch.empty(m + tot, dtype=torch.int64, pin_memory=True)
         with torch.cuda.stream(st):
             host.copy_(dev, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(st)
-        self.inflight.append(_Batch(picked, st, ev, work_off, host, (dev, d_c, d_x, offs), nq))
+        self.inflight.append(_Batch(picked, st, ev, work_off, host, (dev, packed, offs), nq))
         self.batches_launched += 1
 
     def step(self) -> bool:

@@ -24,7 +24,8 @@ WT_MAX_SIGMA = 1 << 24
 EXPORTED = [
     "wt_footprint", "wt_build", "wt_batch_footprint", "wt_build_batch", "wt_tree_status",
     "wt_free", "wt_levels", "wt_access_batch", "wt_rank_batch", "wt_select_batch",
-    "wt_access", "wt_rank", "wt_select", "wt_strerror", "wt_tune_set", "wt_tune_get",
+    "wt_access", "wt_rank", "wt_select", "wt_query_multi_footprint", "wt_query_multi", "wt_strerror",
+    "wt_tune_set", "wt_tune_get",
     "wt_prof_enable", "wt_prof_read",
 ]
 
@@ -72,6 +73,8 @@ def lib():
         "wt_rank": ([vp, u32, u64, P(u64)], i32),
         "wt_select": ([vp, u32, u64, P(u64)], i32),
         "wt_strerror": ([i32], ctypes.c_char_p),
+        "wt_query_multi_footprint": ([u32, P(u64)], i32),
+        "wt_query_multi": ([u32, P(vp), vp, vp, vp, vp, vp, u64, vp, u64, vp], i32),
         "wt_tune_set": ([u32, u32, u32, u32, u32], i32),
         "wt_tune_get": ([u32, u32, u32, u32, P(u32)], i32),
         "wt_prof_enable": ([i32], i32),
@@ -168,6 +171,18 @@ def wt_rank_batch(h: int, d_c: int, d_i: int, d_r: int, m: int, stream: int) -> 
 
 def wt_select_batch(h: int, d_c: int, d_j: int, d_pos: int, m: int, stream: int) -> int:
     return lib().wt_select_batch(h, d_c, d_j, d_pos, m, stream)
+
+
+def wt_query_multi_footprint(ntrees: int):
+    wb = ctypes.c_uint64()
+    rc = lib().wt_query_multi_footprint(ntrees, ctypes.byref(wb))
+    return rc, wb.value
+
+
+def wt_query_multi(handles, d_tree: int, d_kind: int, d_c: int, d_x: int, d_out: int, m: int, d_work: int,
+                   work_bytes: int, stream: int) -> int:
+    arr = (ctypes.c_void_p * max(1, len(handles)))(*handles)
+    return lib().wt_query_multi(len(handles), arr, d_tree, d_kind, d_c, d_x, d_out, m, d_work, work_bytes, stream)
 
 
 def wt_access(h: int, i: int):

@@ -164,3 +164,12 @@ def test_short_sequences_need_no_workspace():
             assert wt.wt_tune_get(0, width, levels, lg)[1] == 2
         finally:
             wt.wt_tune_set(0, width, levels, lg, 0)
+
+
+def test_query_multi_argument_checks():
+    wt = _wt()
+    rc, wb = wt.wt_query_multi_footprint(10)
+    assert rc == wt.WT_OK and wb >= 10 * 48 and wb % 256 == 0
+    assert wt.wt_query_multi([], 0, 0, 0, 0, 0, 0, 0, 0, 0) == wt.WT_OK          # m = 0: nothing to do
+    assert wt.wt_query_multi([], 1, 1, 1, 1, 1, 5, 256, 256, 0) == wt.WT_EINVAL  # no trees
+    assert wt.lib().wt_query_multi_footprint(3, None) == wt.WT_EINVAL

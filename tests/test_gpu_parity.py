@@ -302,3 +302,51 @@ def test_full_size_c3_properties():
         got = t.access(pos).to(torch.int64) & 0xFFFFFFFF
         assert torch.equal(got, s64[a: a + pos.numel()]), "access mismatch in [%d, %d)" % (a, a + step)
     t.close()
+
+
+def test_query_multi_matches_per_tree_queries():
+    """Mixed access/rank/select over several trees in one launch equals the
+    per-tree calls (and the oracle), including out-of-range arguments."""
+    wt = _wt()
+    import torch
+    dev = _dev()
+    specs = [(5000, 20, 1), (70_000, 1 << 16, 2), (30_000, 1 << 20, 4), (1, 3, 1)]
+    Ss = [wtgen.uniform(n, sg, 2100 + k).astype(wtgen.dtype_for(w)) for k, (n, sg, w) in enumerate(specs)]
+    trees = [wt.build(wt.to_device(S, dev), sg) for S, (_, sg, _) in zip(Ss, specs)]
+    rng = np.random.default_rng(8)
+    m = 3000
+    ti = rng.integers(0, len(trees) + 1, m).astype(np.uint32)            # index len(trees) is invalid
+    kind = rng.integers(0, 4, m).astype(np.uint8)                         # kind 3 is invalid
+    c = np.zeros(m, np.int32)
+    x = np.zeros(m, np.int64)
+    for q in range(m):
+        if ti[q] < len(trees):
+            n, sg, _ = specs[ti[q]]
+            c[q] = rng.integers(0, sg + 2)
+            x[q] = rng.integers(0, n + 3)
+    blob = [torch.from_numpy(a).to(dev) for a in (ti, kind, c, x)]
+    out = torch.empty(m, dtype=torch.int64, device=dev)
+    rc, wb = wt.wt_query_multi_footprint(len(trees))
+    work = torch.empty(wb, dtype=torch.uint8, device=dev)
+    st = torch.cuda.current_stream()
+    rc = wt.wt_query_multi([t.handle for t in trees], blob[0].data_ptr(), blob[1].data_ptr(), blob[2].data_ptr(),
+                           blob[3].data_ptr(), out.data_ptr(), m, work.data_ptr(), wb, int(st.cuda_stream))
+    assert rc == wt.WT_OK
+    got = out.cpu().numpy().view(np.uint64)
+    refs = [oracle.build(S, sg, with_ranks=False) for S, (_, sg, _) in zip(Ss, specs)]
+    umax = np.iinfo(np.uint64).max
+    for q in range(m):
+        if ti[q] >= len(trees) or kind[q] > 2:
+            assert got[q] == umax, q
+            continue
+        t, ref, (n, sg, _) = trees[ti[q]], refs[ti[q]], specs[ti[q]]
+        if kind[q] == 0:
+            want = Ss[ti[q]][x[q]] if x[q] < n else umax
+        elif kind[q] == 1:
+            want = oracle.rank(ref, int(c[q]), int(x[q])) if (c[q] < sg and x[q] <= n) else umax
+        else:
+            v = oracle.select(ref, int(c[q]), int(x[q])) if c[q] < sg else None
+            want = umax if v is None else v
+        assert int(got[q]) == int(want), (q, ti[q], kind[q], c[q], x[q], got[q], want)
+    for t in trees:
+        t.close()
