@@ -46,14 +46,35 @@ template <> struct ElemT<1> { typedef uint8_t T; };
 template <> struct ElemT<2> { typedef uint16_t T; };
 template <> struct ElemT<4> { typedef uint32_t T; };
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, 64);
-        if (lane >= d) v += t;
+// Wave-wide operations on DPP (register-to-register lane moves; GFX9 row
+// shifts and row broadcasts), not the LDS crossbar.  The whole wave must be
+// active.  DPP controls: row_shr:n = 0x110 + n, row_bcast:15 = 0x142,
+// row_bcast:31 = 0x143, wave_shr:1 = 0x138.
+__device__ __forceinline__ uint32_t dpp_row_shr(uint32_t v, int n) {
+    switch (n) {
+        case 1: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);
+        case 2: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);
+        case 4: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);
+        default: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);
     }
+}
+
+// Inclusive prefix sum over the 64 lanes: a scan inside each row of 16,
+// then row 0's total into row 1 and row 2's into row 3, then lane 31's
+// into rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    v += dpp_row_shr(v, 1);
+    v += dpp_row_shr(v, 2);
+    v += dpp_row_shr(v, 4);
+    v += dpp_row_shr(v, 8);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
     return v;
+}
+
+// Value of the previous lane (lane 0 gets `first`).
+__device__ __forceinline__ uint32_t wave_prev_lane(uint32_t v, uint32_t first) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)first, (int)v, 0x138, 0xf, 0xf, false);
 }
 
 __device__ __forceinline__ unsigned long long wave_incl_scan64(unsigned long long v) {
@@ -73,9 +94,7 @@ __device__ __forceinline__ unsigned long long wave_sum64(unsigned long long v) {
 }
 
 __device__ __forceinline__ uint32_t wave_sum32(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
+    return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(v), 63);
 }
 
 // Exclusive scan of one value per thread over the block (kThreads threads);
@@ -519,8 +538,7 @@ __device__ __forceinline__ void stage_multi(const LevelArgs &a, const uint4 (&ra
     wave_sync();
     // first symbol of every node present in the tile
     {
-        uint32_t vprev = __shfl_up((raw_elem<W, B>(raw, E - 1) & a.symmask) >> nsh, 1, 64);
-        if (lane == 0) vprev = 0xFFFFFFFFu;
+        uint32_t vprev = wave_prev_lane((raw_elem<W, B>(raw, E - 1) & a.symmask) >> nsh, 0xFFFFFFFFu);
         uint32_t r = lr1;
 #pragma unroll
         for (int k = 0; k < E; k++) {
@@ -650,10 +668,21 @@ __device__ __forceinline__ void stage_multi(const LevelArgs &a, const uint4 (&ra
     }
 }
 
+// Next-level ones of a single-node tile, per (run, destination-tile parity)
+// q: destination tile dt[q] and count cnt[q] (0: none), for child node
+// child + (q >> 1).  The workgroup adds them up before its atomics (its
+// consecutive tiles mostly share a node, whose few counter addresses would
+// otherwise take one atomic per tile).
+struct SplitRec {
+    uint32_t dt[4], cnt[4];
+    uint32_t child;
+};
+
 // One level pass over tile t, run by one wave (each lane B bytes = E = B/W
-// symbols of T_i); s_wave is the wave's own LDS slice.  No workgroup barrier.
+// symbols of T_i); s_wave is the wave's own LDS slice.  Single-node tiles
+// leave their next-level counts in *rec; other tiles add theirs directly.
 template <int W, int B, bool kMulti>
-__device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8_t *s_wave) {
+__device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8_t *s_wave, SplitRec *rec) {
     typedef typename ElemT<W>::T T;
     constexpr int E = B / W;                    // symbols per lane
     constexpr int CH = 16 / W;                  // symbols per 16-byte chunk
@@ -685,7 +714,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
     const M mb = level_bits<W, B>(raw, sh);
     const uint32_t pc = (E == 64) ? (uint32_t)__popcll((uint64_t)mb) : (uint32_t)__popc((uint32_t)mb);
     const uint32_t incl = wave_incl_scan(pc);
-    const uint32_t agg = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
+    const uint32_t agg = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     prefix += wave_sum32(pv);
     const uint32_t lr1 = incl - pc;  // ones in the tile before this lane
     const unsigned long long r_lane = prefix + lr1;
@@ -715,17 +744,17 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
     // node span of the tile (T_i is sorted by node)
     const bool full = (nvalid == TILE);  // every tile but a ragged last one
     const uint32_t vf =
-        __builtin_amdgcn_readfirstlane(__shfl((raw_elem<W, B>(raw, 0) & a.symmask) >> nsh, 0, 64));
+        (uint32_t)__builtin_amdgcn_readlane((int)((raw_elem<W, B>(raw, 0) & a.symmask) >> nsh), 0);
     uint32_t vl;
     if (full) {
-        vl = __shfl((raw_elem<W, B>(raw, E - 1) & a.symmask) >> nsh, 63, 64);
+        vl = (uint32_t)__builtin_amdgcn_readlane((int)((raw_elem<W, B>(raw, E - 1) & a.symmask) >> nsh), 63);
     } else {
         const uint64_t last = nvalid - 1;
         const int kl = (int)(last % E);
         uint32_t xv = 0;
 #pragma unroll
         for (int k = 0; k < E; k++) xv = (k == kl) ? raw_elem<W, B>(raw, k) : xv;
-        vl = __shfl((xv & a.symmask) >> nsh, (int)(last / E), 64);
+        vl = (uint32_t)__builtin_amdgcn_readlane((int)((xv & a.symmask) >> nsh), (int)(last / E));
     }
     vl = __builtin_amdgcn_readfirstlane(vl);
 
@@ -790,13 +819,14 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
             const uint32_t tot = wave_sum32(c4[q]);
             if (tot) {
                 const unsigned long long m = __ballot(c4[q] != 0);
-                const uint32_t dt = __shfl(d4[q], __builtin_ctzll(m), 64);
+                const uint32_t dt = (uint32_t)__builtin_amdgcn_readlane((int)d4[q], (int)__builtin_ctzll(m));
                 if (lane == 0) {
-                    atomicAdd(&a.tile_ones_next[dt], tot);
-                    atomicAdd(&ones_next[2ull * vf + (q >> 1)], (unsigned long long)tot);
+                    rec->dt[q] = dt;
+                    rec->cnt[q] = tot;
                 }
             }
         }
+        if (lane == 0) rec->child = 2 * vf;
         return;
     }
 
@@ -853,13 +883,47 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
 }
 
 
+// After the workgroup's tiles: add up the single-node tiles' records by
+// destination tile and by child node, one atomic per distinct key.
+__device__ __forceinline__ void flush_split_recs(const LevelArgs &a, const SplitRec *recs, uint64_t t0) {
+    __syncthreads();
+    const uint32_t r = threadIdx.x;
+    if (r >= 4 * kWaves || a.tile_ones_next == nullptr) return;
+    const uint32_t w = r / 4, q = r % 4;
+    const uint32_t c = recs[w].cnt[q];
+    if (c == 0) return;
+    const uint32_t dt = recs[w].dt[q], child = recs[w].child + (q >> 1);
+    uint32_t sum_dt = 0, sum_ch = 0;
+    bool first_dt = true, first_ch = true;
+    for (uint32_t r2 = 0; r2 < 4 * kWaves; r2++) {
+        const uint32_t w2 = r2 / 4, q2 = r2 % 4;
+        const uint32_t c2 = recs[w2].cnt[q2];
+        if (c2 == 0) continue;
+        if (recs[w2].dt[q2] == dt) {
+            sum_dt += c2;
+            if (r2 < r) first_dt = false;
+        }
+        if (recs[w2].child + (q2 >> 1) == child) {
+            sum_ch += c2;
+            if (r2 < r) first_ch = false;
+        }
+    }
+    if (first_dt) atomicAdd(&a.tile_ones_next[dt], sum_dt);
+    if (first_ch) {
+        unsigned long long *ones_next = a.ones_next + (t0 % a.slots_next) * a.nodes_next;
+        atomicAdd(&ones_next[child], (unsigned long long)sum_ch);
+    }
+}
+
 template <int W, int B, bool M>
 __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
     __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W, B, M>()];
+    __shared__ SplitRec s_rec[kWaves];
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t t = (uint64_t)blockIdx.x * kWaves + wv;
-    if (t >= a.ntiles) return;  // whole wave
-    level_tile<W, B, M>(a, t, s_all + wv * level_wave_bytes<W, B, M>());
+    if ((threadIdx.x & 63) < 4) s_rec[wv].cnt[threadIdx.x & 63] = 0;
+    if (t < a.ntiles) level_tile<W, B, M>(a, t, s_all + wv * level_wave_bytes<W, B, M>(), &s_rec[wv]);
+    flush_split_recs(a, s_rec, (uint64_t)blockIdx.x * kWaves);
 }
 
 // ------------------------------------------------------------ batched ---
@@ -1002,11 +1066,14 @@ __global__ __launch_bounds__(kThreads) void k_batch_plan_apply(BatchClass c, uin
 template <int W, int B, bool M>
 __global__ __launch_bounds__(kThreads) void k_batch_level(BatchClass c, uint32_t level) {
     __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W, B, M>()];
+    __shared__ SplitRec s_rec[kWaves];
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const BatchJob &j = c.jobs[c.blk_map[blockIdx.x]];
-    const uint64_t t = (blockIdx.x - j.blk_base) * kWaves + wv;
-    if (t >= j.ntiles) return;  // whole wave
-    level_tile<W, B, M>(job_level(j, level), t, s_all + wv * level_wave_bytes<W, B, M>());
+    const uint64_t t0 = (blockIdx.x - j.blk_base) * kWaves;
+    const LevelArgs a = job_level(j, level);
+    if ((threadIdx.x & 63) < 4) s_rec[wv].cnt[threadIdx.x & 63] = 0;
+    if (t0 + wv < j.ntiles) level_tile<W, B, M>(a, t0 + wv, s_all + wv * level_wave_bytes<W, B, M>(), &s_rec[wv]);
+    flush_split_recs(a, s_rec, t0);
 }
 
 }  // namespace
