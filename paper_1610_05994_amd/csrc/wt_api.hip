@@ -139,7 +139,7 @@ void make_layout(uint64_t n, uint32_t sigma, uint32_t width, bool batched, Layou
 
     L->ws_ctrl = off;
     L->ws_tile_ones = off;
-    off += round_up((uint64_t)l * L->ntiles * 4, 256);
+    off += round_up((uint64_t)l * tile_stride(L->ntiles) * 4, 256);
     L->ws_ones = off;
     off += round_up(ones_offset(l) * 8, 256);
     L->ws_ctrl_bytes = off - L->ws_ctrl;
@@ -242,7 +242,7 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
             if (err != hipSuccess) return err;
         }
         PrepArgs pp;
-        pp.tile_ones = tile_ones + (uint64_t)i * L.ntiles;
+        pp.tile_ones = tile_ones + (uint64_t)i * tile_stride(L.ntiles);
         pp.supsum = supsum;
         pp.sup = sup + (uint64_t)i * L.nsup;
         pp.ntiles = L.ntiles;
@@ -260,9 +260,9 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         a.bits = bits + (uint64_t)i * L.words;
         a.ranks = ranks + (uint64_t)i * L.rank_stride;
         a.zo = zo + zo_offset(i);
-        a.tile_ones = tile_ones + (uint64_t)i * L.ntiles;
+        a.tile_ones = tile_ones + (uint64_t)i * tile_stride(L.ntiles);
         a.sup = sup + (uint64_t)i * L.nsup;
-        a.tile_ones_next = (i + 1 < l) ? tile_ones + (uint64_t)(i + 1) * L.ntiles : nullptr;
+        a.tile_ones_next = (i + 1 < l) ? tile_ones + (uint64_t)(i + 1) * tile_stride(L.ntiles) : nullptr;
         a.ones_next = (i + 1 < l) ? ones + ones_offset(i + 1) : nullptr;
         a.nodes_next = 2ull << i;
         a.slots_next = level_slots(i + 1);

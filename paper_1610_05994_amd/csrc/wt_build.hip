@@ -218,12 +218,17 @@ __device__ __forceinline__ void stage_split(typename ElemT<W>::T *s_stage, const
                                             typename MaskT<B / W>::T mb, uint32_t zc, uint32_t oc, int nval) {
     typedef typename ElemT<W>::T T;
     constexpr int E = B / W;
+    // With zp the next zero slot and D = (next one slot - zp) + k, symbol k
+    // goes to zp + b * (D - k); zp advances on a zero, D by 2 on a one (one
+    // 24-bit multiply-add per symbol; slots < 2^24).  The empty asm keeps D
+    // an opaque register, so the compiler keeps this two-operation update
+    // instead of rebuilding D from a ones count.
+    T *zp = s_stage + zc;
+    uint32_t D = oc - zc;
 #pragma unroll
     for (int k = 0; k < E; k++) {
         if (kFull || k < nval) {
             const uint32_t b = (uint32_t)(mb >> k) & 1u;
-            // slot = b ? oc : zc, as one 24-bit multiply-add (slots < 2^24)
-            const uint32_t slot = __umul24(b, oc - zc) + zc;
             const int q = (k * W) >> 2;
             const uint4 &c = raw[q / 4];
             const uint32_t d = (q % 4 == 0) ? c.x : (q % 4 == 1) ? c.y : (q % 4 == 2) ? c.z : c.w;
@@ -234,9 +239,10 @@ __device__ __forceinline__ void stage_split(typename ElemT<W>::T *s_stage, const
             else if (W == 2) x = (k & 1) ? (d >> 16) : d;
             else x = ((k & 3) == 1 || (k & 3) == 3) ? (d >> 8) : d;
             if (W == 1 && (k & 3) >= 2) x >>= 16;
-            s_stage[slot] = (T)x;
-            oc += b;
-            zc += b ^ 1u;
+            zp[__umul24(b, D - (uint32_t)k)] = (T)x;
+            zp += b ^ 1u;
+            D += 2u * b;
+            asm volatile("" : "+v"(D));
         }
     }
 }
@@ -704,10 +710,13 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
     // ones before the tile: superchunk prefix + earlier tiles of the superchunk
     uint32_t pv = 0;
     {
+        // four consecutive counts per lane (16-byte aligned: kSup and the
+        // level's base are multiples of 4 entries)
         const uint64_t q = t - t % kSup + 4 * (uint64_t)lane;
-#pragma unroll
-        for (int d = 0; d < 4; d++)
-            if (q + d < t) pv += a.tile_ones[q + d];
+        if (q < t) {
+            const uint4 c = *reinterpret_cast<const uint4 *>(a.tile_ones + q);
+            pv = c.x + (q + 1 < t ? c.y : 0u) + (q + 2 < t ? c.z : 0u) + (q + 3 < t ? c.w : 0u);
+        }
     }
     unsigned long long prefix = a.sup[t / kSup];
 
@@ -941,9 +950,9 @@ __device__ __forceinline__ LevelArgs job_level(const BatchJob &j, uint32_t i) {
     a.ranks = reinterpret_cast<uint64_t *>(j.tree + j.tree_ranks_off) + (uint64_t)i * j.rank_stride;
     a.zo = reinterpret_cast<const ulonglong2 *>(w + j.ws_zo) + zo_offset(i);
     uint32_t *tile_ones = reinterpret_cast<uint32_t *>(w + j.ws_tile_ones);
-    a.tile_ones = tile_ones + (uint64_t)i * j.ntiles;
+    a.tile_ones = tile_ones + (uint64_t)i * tile_stride(j.ntiles);
     a.sup = reinterpret_cast<const unsigned long long *>(w + j.ws_sup) + (uint64_t)i * j.nsup;
-    a.tile_ones_next = (i + 1 < l) ? tile_ones + (uint64_t)(i + 1) * j.ntiles : nullptr;
+    a.tile_ones_next = (i + 1 < l) ? tile_ones + (uint64_t)(i + 1) * tile_stride(j.ntiles) : nullptr;
     a.ones_next = (i + 1 < l) ? reinterpret_cast<unsigned long long *>(w + j.ws_ones) + ones_offset(i + 1) : nullptr;
     a.nodes_next = 2ull << i;
     a.slots_next = level_slots(i + 1);
@@ -961,7 +970,7 @@ __device__ __forceinline__ LevelArgs job_level(const BatchJob &j, uint32_t i) {
 __device__ __forceinline__ PrepArgs job_prep(const BatchJob &j, uint32_t i) {
     PrepArgs p;
     uint8_t *w = j.work;
-    p.tile_ones = reinterpret_cast<const uint32_t *>(w + j.ws_tile_ones) + (uint64_t)i * j.ntiles;
+    p.tile_ones = reinterpret_cast<const uint32_t *>(w + j.ws_tile_ones) + (uint64_t)i * tile_stride(j.ntiles);
     p.supsum = reinterpret_cast<unsigned long long *>(w + j.ws_supsum);
     p.sup = reinterpret_cast<unsigned long long *>(w + j.ws_sup) + (uint64_t)i * j.nsup;
     p.ntiles = j.ntiles;
@@ -1036,7 +1045,8 @@ __global__ __launch_bounds__(kThreads) void k_batch_ingest(BatchClass c) {
 
 __global__ __launch_bounds__(kThreads) void k_batch_supsum(BatchClass c, uint32_t level) {
     const BatchJob &j = c.jobs[c.sup_map[blockIdx.x]];
-    const uint32_t *tile_ones = reinterpret_cast<const uint32_t *>(j.work + j.ws_tile_ones) + (uint64_t)level * j.ntiles;
+    const uint32_t *tile_ones =
+        reinterpret_cast<const uint32_t *>(j.work + j.ws_tile_ones) + (uint64_t)level * tile_stride(j.ntiles);
     supsum_one(tile_ones, j.ntiles, blockIdx.x - j.sup_base, reinterpret_cast<unsigned long long *>(j.work + j.ws_supsum));
 }
 

@@ -32,6 +32,9 @@ __host__ __device__ constexpr uint32_t one_wg_cap(uint32_t width, uint32_t geom)
     return geom == kGeomMid ? (width == 1 ? 32768u : (width == 2 ? 26624u : 15360u))
                             : (width == 1 ? 15360u : (width == 2 ? 10240u : 6144u));
 }
+// Entries per level of the per-tile counts: a multiple of 4, so that a lane
+// reads four consecutive counts with one 16-byte load.
+__host__ __device__ constexpr uint64_t tile_stride(uint64_t ntiles) { return (ntiles + 3) / 4 * 4; }
 // Tiles per superchunk of the tile-count scan (four counts per lane).
 constexpr uint64_t kSup = kThreads;
 // Node ones counters of shallow levels are spread over slots so that the
