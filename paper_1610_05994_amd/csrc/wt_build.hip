@@ -785,56 +785,56 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         if (full) stage_split<W, B, true>(s_stage, raw, mb, zc, oc, nval);
         else stage_split<W, B, false>(s_stage, raw, mb, zc, oc, nval);
         wave_sync();
-        // next-level ones per (run, destination-tile parity): a run holds at
-        // most TILE symbols, so it touches at most two consecutive tiles
-        uint32_t c4[4] = {0u, 0u, 0u, 0u};
-        uint32_t d4[4] = {0u, 0u, 0u, 0u};
-        const uint32_t nch = (a1 + (uint32_t)O + CH - 1) / CH;
-        for (uint32_t c = lane; c < nch; c += 64) {
-            const uint32_t s = c * CH;
-            const uint32_t region = s < r1 ? 0u : 1u;
-            const uint64_t gb = region ? g1 - a1 : g0 - a0;
-            const uint32_t lo = region ? a1 : a0;
-            const uint32_t hi = region ? a1 + (uint32_t)O : a0 + (uint32_t)Z;
-            const uint4 v = *reinterpret_cast<const uint4 *>(&s_stage[s]);
-            uint32_t ones = 0;
-            // (destinations beyond n only arise from inconsistent tables; they
-            // are dropped rather than written)
-            if (s >= lo && s + CH <= hi && gb + s + CH <= a.n) {
-                *reinterpret_cast<uint4 *>(tout + (gb + s)) = v;
-                if (counting) ones = chunk_bit_count<W>(v, sh2);
-            } else {
+        // Write the two runs out (zeros at slots [a0, a0+Z) -> g0.., ones at
+        // [a1, a1+O) -> g1..), one 16-byte chunk per lane and step; the slot
+        // and destination phases agree, so chunks are aligned in both.  A run
+        // holds at most TILE symbols, so it touches at most two consecutive
+        // destination tiles: next-level ones are counted per (run, tile).
+        const uint32_t lowbits = (W == 1) ? 0x01010101u : (W == 2) ? 0x00010001u : 1u;
+        const uint32_t mk = counting ? lowbits << sh2 : 0u;  // next-level bit of every symbol
 #pragma unroll
-                for (int e = 0; e < CH; e++) {
-                    if (s + e >= lo && s + e < hi && gb + s + e < a.n) {
-                        const uint32_t x = chunk_elem<W>(v, e);
-                        tout[gb + s + e] = (T)x;
-                        ones += (x >> sh2) & 1u;
+        for (int r = 0; r < 2; r++) {
+            const uint32_t lo = r ? a1 : a0;
+            const uint32_t len = (uint32_t)(r ? O : Z);
+            const uint64_t gb = (r ? g1 : g0) - lo;  // destination = gb + slot
+            const uint32_t cb = lo / CH, ce = len ? (lo + len + CH - 1) / CH : cb;
+            const uint32_t fb = (lo + CH - 1) / CH, fe = (lo + len) / CH;  // chunks inside the run
+            const uint64_t dt0 = (gb + (uint64_t)cb * CH) / TILE;
+            const uint64_t cs = ((dt0 + 1) * TILE - gb) / CH;  // first chunk in tile dt0 + 1
+            uint32_t cnt0 = 0, cnt1 = 0;
+            for (uint32_t c = cb + lane; c < ce; c += 64) {
+                const uint32_t s = c * CH;
+                const uint4 v = *reinterpret_cast<const uint4 *>(&s_stage[s]);
+                uint32_t ones = 0;
+                // (destinations beyond n only arise from inconsistent tables;
+                // they are dropped rather than written)
+                if (c >= fb && c < fe && gb + s + CH <= a.n) {
+                    *reinterpret_cast<uint4 *>(tout + (gb + s)) = v;
+                    ones = __popc(v.x & mk) + __popc(v.y & mk) + __popc(v.z & mk) + __popc(v.w & mk);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < CH; e++) {
+                        if (s + e >= lo && s + e < lo + len && gb + s + e < a.n) {
+                            const uint32_t x = chunk_elem<W>(v, e);
+                            tout[gb + s + e] = (T)x;
+                            ones += (x >> sh2) & 1u;
+                        }
                     }
                 }
+                if (c < cs) cnt0 += ones;
+                else cnt1 += ones;
             }
-            if (counting && ones) {
-                const uint64_t dt = (gb + s) / TILE;  // 16-byte chunks never straddle tiles
-                const uint32_t key = region * 2 + (uint32_t)(dt & 1);
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    if (q == (int)key) { c4[q] += ones; d4[q] = (uint32_t)dt; }
+            if (counting) {
+                const uint32_t t0 = wave_sum32(cnt0), t1 = wave_sum32(cnt1);
+                if (lane == 0) {
+                    rec->dt[2 * r] = (uint32_t)dt0;
+                    rec->cnt[2 * r] = t0;
+                    rec->dt[2 * r + 1] = (uint32_t)dt0 + 1;
+                    rec->cnt[2 * r + 1] = t1;
                 }
             }
         }
         if (!counting) return;
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const uint32_t tot = wave_sum32(c4[q]);
-            if (tot) {
-                const unsigned long long m = __ballot(c4[q] != 0);
-                const uint32_t dt = (uint32_t)__builtin_amdgcn_readlane((int)d4[q], (int)__builtin_ctzll(m));
-                if (lane == 0) {
-                    rec->dt[q] = dt;
-                    rec->cnt[q] = tot;
-                }
-            }
-        }
         if (lane == 0) rec->child = 2 * vf;
         return;
     }
