@@ -77,6 +77,18 @@ __device__ __forceinline__ uint32_t wave_prev_lane(uint32_t v, uint32_t first) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)first, (int)v, 0x138, 0xf, 0xf, false);
 }
 
+// Inclusive prefix maximum over the 64 lanes (DPP; lanes shifted in read 0).
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
+    uint32_t t;
+    t = dpp_row_shr(v, 1); v = v > t ? v : t;
+    t = dpp_row_shr(v, 2); v = v > t ? v : t;
+    t = dpp_row_shr(v, 4); v = v > t ? v : t;
+    t = dpp_row_shr(v, 8); v = v > t ? v : t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false); v = v > t ? v : t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false); v = v > t ? v : t;
+    return v;
+}
+
 __device__ __forceinline__ unsigned long long wave_incl_scan64(unsigned long long v) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -674,6 +686,189 @@ __device__ __forceinline__ void stage_multi(const LevelArgs &a, const uint4 (&ra
     }
 }
 
+// Split of a tile spanning many nodes vf..vl (at least kRunNodes).  Nodes
+// strictly between vf and vl lie inside the tile, and so do their two
+// children in T_{i+1} (zeros then ones, in the node's own positions): with
+// [ps, pe) the node's tile positions and rs / re the tile ones before ps /
+// pe, a symbol at p with r tile ones before it goes to
+//     bit 0: p - r + rs,      bit 1: pe - (re - r)
+// (the node-local form of the destinations, Section 3.1).  Those symbols are
+// staged in LDS at their own tile positions and leave as one aligned block;
+// their children's next-level ones are stored once per node (atomics only
+// for nodes crossing lanes).  The two edge nodes vf and vl may extend past
+// the tile and use the node tables; their next-level ones are counted per
+// (node, bit, destination-tile parity).  Node starts and their tile ranks
+// travel between lanes as (position << 16 | rank) in a prefix maximum and a
+// suffix minimum.
+template <int W, int B>
+__device__ __forceinline__ void split_dense(const LevelArgs &a, const uint4 (&raw)[B / 16],
+                                            typename MaskT<B / W>::T mb, int nval, uint32_t lr1, uint32_t agg,
+                                            unsigned long long prefix, uint64_t base, uint64_t nvalid, uint64_t t,
+                                            uint32_t vf, uint32_t vl, uint32_t nsh, uint8_t *s_wave,
+                                            typename ElemT<W>::T *tout, bool counting, uint32_t sh2,
+                                            unsigned long long *ones_next) {
+    typedef typename ElemT<W>::T T;
+    typedef typename MaskT<B / W>::T Mk;
+    constexpr int E = B / W;
+    constexpr uint32_t CH = 16 / W;
+    constexpr uint64_t TILE = tile_syms(W, B);
+    const int lane = threadIdx.x & 63;
+    T *s_stage = reinterpret_cast<T *>(s_wave);
+    const uint32_t p0 = (uint32_t)lane * E;
+    const uint32_t nv = (uint32_t)nvalid;
+
+    // node starts of this lane
+    Mk fm = 0;
+    {
+        uint32_t vprev = wave_prev_lane((raw_elem<W, B>(raw, E - 1) & a.symmask) >> nsh, 0xFFFFFFFFu);
+#pragma unroll
+        for (int k = 0; k < E; k++) {
+            if (k < nval) {
+                const uint32_t v = (raw_elem<W, B>(raw, k) & a.symmask) >> nsh;
+                if (v != vprev) fm |= (Mk)1 << k;
+                vprev = v;
+            }
+        }
+    }
+    // (position << 16 | tile rank) of the lane's last and first node start
+    uint32_t last_pk = 0, first_pk = 0xFFFFFFFFu;
+    if (fm) {
+        const int kl = (E == 64) ? 63 - __clzll((unsigned long long)fm) : 31 - __clz((uint32_t)fm);
+        const int kf = (E == 64) ? __ffsll((unsigned long long)fm) - 1 : __ffs((uint32_t)fm) - 1;
+        const uint32_t rl = lr1 + ((E == 64) ? (uint32_t)__popcll((unsigned long long)mb & ((1ull << kl) - 1ull))
+                                             : (uint32_t)__popc((uint32_t)mb & ((1u << kl) - 1u)));
+        const uint32_t rf = lr1 + ((E == 64) ? (uint32_t)__popcll((unsigned long long)mb & ((1ull << kf) - 1ull))
+                                             : (uint32_t)__popc((uint32_t)mb & ((1u << kf) - 1u)));
+        last_pk = ((p0 + kl) << 16) | rl;
+        first_pk = ((p0 + kf) << 16) | rf;
+    }
+    // node start before the lane (position 0 always starts one) and node end
+    // after it (or the tile end, nvalid with all the tile's ones)
+    const uint32_t start_in = wave_prev_lane(wave_incl_max(last_pk), 0u);
+    uint32_t end_in;
+    {
+        const uint32_t rev = ~(uint32_t)__shfl(first_pk, 63 - lane, 64);
+        const uint32_t ex = wave_prev_lane(wave_incl_max(rev), 0u);
+        end_in = ~(uint32_t)__shfl(ex, 63 - lane, 64);
+        if (end_in == 0xFFFFFFFFu) end_in = (nv << 16) | agg;
+    }
+    // interior block of the tile: from the second node start to the last one
+    const uint32_t sec = (lane == 0) ? (((uint64_t)fm >> 1) ? (uint32_t)__builtin_ctzll((uint64_t)fm >> 1) + 1 : nv)
+                                     : (fm ? (first_pk >> 16) : nv);
+    const uint32_t ia_u = ~(uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(~sec), 63);  // lane minimum
+    // last node start of the tile (vl's first tile position) and its tile rank
+    const uint32_t lastmax = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(last_pk), 63);
+    const uint32_t ib_u = lastmax >> 16, rvl = lastmax & 0xFFFFu;
+
+    const ulonglong2 zf = a.zo[vf], zl = a.zo[vl];
+    // edge counts, key = 4 e + 2 b + parity (e = 0: vf, 1: vl), 16 bits each
+    unsigned long long ecl = 0, ech = 0;
+    uint32_t icount = 0;                 // next-level ones of interior symbols (all in tile t)
+    uint32_t ps = 0, pe = 0, rs = 0, re = 0, vcur = 0, c0 = 0, c1 = 0;
+    bool interior = false, open = false;
+    uint32_t r = lr1;
+    // ones of an interior node's children: a plain store when the node lies
+    // in this lane, an atomic when it crosses lanes
+    auto flush = [&]() {
+        if (open && interior && counting && (c0 | c1)) {
+            unsigned long long *o = &ones_next[2ull * vcur];
+            if (ps >= p0 && pe <= p0 + E) {
+                o[0] = c0;
+                o[1] = c1;
+            } else {
+                if (c0) atomicAdd(&o[0], (unsigned long long)c0);
+                if (c1) atomicAdd(&o[1], (unsigned long long)c1);
+            }
+        }
+    };
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+        if (k < nval) {
+            const uint32_t x = raw_elem<W, B>(raw, k) & a.symmask;
+            const uint32_t v = x >> nsh;
+            const uint32_t b = (uint32_t)(mb >> k) & 1u;
+            const uint32_t p = p0 + k;
+            const bool fl = ((uint64_t)fm >> k) & 1u;
+            if (k == 0 || fl) {
+                flush();
+                open = true;
+                c0 = c1 = 0;
+                vcur = v;
+                if (fl) { ps = p; rs = r; }
+                else { ps = start_in >> 16; rs = start_in & 0xFFFFu; }
+                const uint64_t above = (k + 1 < 64) ? ((uint64_t)fm >> (k + 1)) : 0ull;
+                if (above) {
+                    const int kn = k + 1 + __builtin_ctzll(above);
+                    pe = p0 + kn;
+                    re = lr1 + ((E == 64) ? (uint32_t)__popcll((unsigned long long)mb & ((1ull << kn) - 1ull))
+                                          : (uint32_t)__popc((uint32_t)mb & ((1u << kn) - 1u)));
+                } else {
+                    pe = end_in >> 16;
+                    re = end_in & 0xFFFFu;
+                }
+                interior = v != vf && v != vl && v - vf <= vl - vf;
+            }
+            const uint32_t nb = counting ? (x >> sh2) & 1u : 0u;
+            if (interior) {
+                const uint32_t dl = b ? pe - (re - r) : p - r + rs;
+                if (dl < TILE) s_stage[dl] = (T)x;
+                c0 += nb & (b ^ 1u);
+                c1 += nb & b;
+                icount += nb;
+            } else if (v == vf || v == vl) {
+                const ulonglong2 zo = (v == vf) ? zf : zl;
+                const unsigned long long R = prefix + r;
+                const uint64_t dst = b ? zo.y + R : base + p - R + zo.x;
+                if (dst < a.n) {
+                    tout[dst] = (T)x;
+                    const uint32_t key = ((v == vf) ? 0u : 4u) + 2 * b + (uint32_t)((dst / TILE) & 1);
+                    if (key < 4) ecl += (unsigned long long)nb << (16 * key);
+                    else ech += (unsigned long long)nb << (16 * (key - 4));
+                }
+            }
+            r += b;
+        }
+    }
+    flush();
+    wave_sync();
+    // the interior block, aligned chunks (tile positions and destinations agree)
+    for (uint32_t c = ia_u / CH + lane; c * CH < ib_u; c += 64) {
+        const uint32_t s0 = c * CH;
+        const uint4 v4 = *reinterpret_cast<const uint4 *>(&s_stage[s0]);
+        if (s0 >= ia_u && s0 + CH <= ib_u && base + s0 + CH <= a.n) {
+            *reinterpret_cast<uint4 *>(tout + (base + s0)) = v4;
+        } else {
+#pragma unroll
+            for (int e = 0; e < (int)CH; e++) {
+                const uint32_t q = s0 + e;
+                if (q >= ia_u && q < ib_u && base + q < a.n) tout[base + q] = (T)chunk_elem<W>(v4, e);
+            }
+        }
+    }
+    if (!counting) return;
+    const uint32_t itot = wave_sum32(icount);
+    if (lane == 0 && itot) atomicAdd(&a.tile_ones_next[t], itot);
+    // edge runs: vf's part starts at tile position 0 (tile rank 0), vl's at
+    // ib_u (tile rank rvl); a run of at most TILE symbols touches two
+    // consecutive destination tiles, and its first destination tells which
+    // one has a given parity
+#pragma unroll
+    for (int key = 0; key < 8; key++) {
+        const uint32_t cnt = wave_sum32((uint32_t)((((key < 4) ? ecl : ech) >> (16 * (key & 3))) & 0xFFFFu));
+        if (cnt && lane == 0) {
+            const uint32_t e = (uint32_t)key >> 2, b = ((uint32_t)key >> 1) & 1u, par = (uint32_t)key & 1u;
+            const ulonglong2 zo = e ? zl : zf;
+            const uint32_t fp = e ? ib_u : 0u, fr = e ? rvl : 0u;
+            const unsigned long long R = prefix + fr;
+            const uint64_t d0 = b ? zo.y + R : base + fp - R + zo.x;
+            const uint64_t dt0 = d0 / TILE;
+            const uint64_t dt = ((dt0 & 1) == par) ? dt0 : dt0 + 1;
+            if (dt < a.ntiles) atomicAdd(&a.tile_ones_next[dt], cnt);  // (always, with consistent tables)
+            atomicAdd(&ones_next[2ull * (e ? vl : vf) + b], (unsigned long long)cnt);
+        }
+    }
+}
+
 // Next-level ones of a single-node tile, per (run, destination-tile parity)
 // q: destination tile dt[q] and count cnt[q] (0: none), for child node
 // child + (q >> 1).  The workgroup adds them up before its atomics (its
@@ -842,6 +1037,12 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
     if (kMulti && vl - vf < kRunNodes) {
         stage_multi<W, B>(a, raw, mb, nval, lr1, agg, prefix, base, nvalid, vf, vl, nsh, s_wave, tout, counting, sh2,
                           ones_next);
+        return;
+    }
+
+    if (kMulti) {
+        split_dense<W, B>(a, raw, mb, nval, lr1, agg, prefix, base, nvalid, t, vf, vl, nsh, s_wave, tout, counting,
+                          sh2, ones_next);
         return;
     }
 
