@@ -488,7 +488,7 @@ __global__ __launch_bounds__(kThreads) void k_prep(PrepArgs a) { prep_level(a); 
 // Tiles spanning fewer than kRunNodes nodes (several nodes, e.g. at deep
 // levels) are staged in LDS as runs, one per (node, bit), each placed at
 // the 16-byte phase of its destination so that it leaves in aligned chunks.
-constexpr uint32_t kRunNodes = 32;
+constexpr uint32_t kRunNodes = 16;
 
 struct MultiTables {
     uint32_t key[kRunNodes + 1];     // node's first tile position << 16 | tile ones before it
@@ -513,13 +513,19 @@ __host__ __device__ constexpr uint32_t multi_stage_elems() {
 // destination-tile parity); with M, also the run tables and staging of a
 // tile spanning a few nodes.  (M is only used for deep levels: the larger
 // LDS slice lowers occupancy.)
+// LDS of a wave: without M, the single-node staging or the direct path's
+// counters; with M (no direct path), the single-node staging, or the run
+// tables and staging of the few-nodes split, or the dense split's staging
+// and symbol copy (two tiles), whichever is largest.
 template <int W, int B, bool M>
 __host__ __device__ constexpr uint32_t level_wave_bytes() {
     constexpr uint32_t split = (uint32_t)(tile_syms(W, B) + 4 * (16 / W)) * W;
     constexpr uint32_t counters = 2u * 4u * kNodeCap * 4u;
     constexpr uint32_t multi = kMultiTablesBytes + multi_stage_elems<W, B>() * W;
-    constexpr uint32_t base = split > counters ? split : counters;
-    return (M && multi > base) ? multi : base;
+    constexpr uint32_t dense = 2u * (uint32_t)tile_syms(W, B) * W;
+    constexpr uint32_t plain = split > counters ? split : counters;
+    constexpr uint32_t m1 = split > multi ? split : multi;
+    return M ? (m1 > dense ? m1 : dense) : plain;
 }
 
 // Split of a tile whose symbols span nodes vf..vl (fewer than kRunNodes):
@@ -716,15 +722,20 @@ __device__ __forceinline__ void split_dense(const LevelArgs &a, const uint4 (&ra
     T *s_stage = reinterpret_cast<T *>(s_wave);
     const uint32_t p0 = (uint32_t)lane * E;
     const uint32_t nv = (uint32_t)nvalid;
+    // the lane's symbols go to LDS behind the staging area, so that the
+    // per-symbol loops run rolled (unrolled, they held too many registers)
+    T *s_sym = reinterpret_cast<T *>(s_wave + TILE * W) + p0;
+#pragma unroll
+    for (int q = 0; q < B / 16; q++) reinterpret_cast<uint4 *>(s_sym)[q] = raw[q];
 
     // node starts of this lane
     Mk fm = 0;
     {
-        uint32_t vprev = wave_prev_lane((raw_elem<W, B>(raw, E - 1) & a.symmask) >> nsh, 0xFFFFFFFFu);
-#pragma unroll
+        uint32_t vprev = wave_prev_lane(((uint32_t)s_sym[E - 1] & a.symmask) >> nsh, 0xFFFFFFFFu);
+#pragma unroll 2
         for (int k = 0; k < E; k++) {
             if (k < nval) {
-                const uint32_t v = (raw_elem<W, B>(raw, k) & a.symmask) >> nsh;
+                const uint32_t v = ((uint32_t)s_sym[k] & a.symmask) >> nsh;
                 if (v != vprev) fm |= (Mk)1 << k;
                 vprev = v;
             }
@@ -781,10 +792,10 @@ __device__ __forceinline__ void split_dense(const LevelArgs &a, const uint4 (&ra
             }
         }
     };
-#pragma unroll
+#pragma unroll 2
     for (int k = 0; k < E; k++) {
         if (k < nval) {
-            const uint32_t x = raw_elem<W, B>(raw, k) & a.symmask;
+            const uint32_t x = (uint32_t)s_sym[k] & a.symmask;
             const uint32_t v = x >> nsh;
             const uint32_t b = (uint32_t)(mb >> k) & 1u;
             const uint32_t p = p0 + k;
