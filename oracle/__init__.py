@@ -60,6 +60,14 @@ def lib():
         L.wto_select.restype = ctypes.c_int
         L.wto_decode.argtypes = [vp, u64, u32, vp]
         L.wto_decode.restype = ctypes.c_int
+        L.wto_build_matrix.argtypes = [vp, u64, u32, u32, vp, vp, vp]
+        L.wto_build_matrix.restype = ctypes.c_int
+        L.wto_matrix_access.argtypes = [vp, vp, u64, u32, u64, vp]
+        L.wto_matrix_access.restype = ctypes.c_int
+        L.wto_matrix_rank.argtypes = [vp, vp, u64, u32, u32, u64, vp]
+        L.wto_matrix_rank.restype = ctypes.c_int
+        L.wto_matrix_select.argtypes = [vp, vp, u64, u32, u32, u64, vp]
+        L.wto_matrix_select.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -152,3 +160,56 @@ def decode(t: OracleTree) -> np.ndarray:
     if rc != OK:
         raise ValueError("decode status %d" % rc)
     return out
+
+
+# ------------------------------------------------------- wavelet matrix ---
+
+@dataclass
+class OracleMatrix:
+    n: int
+    sigma: int
+    levels: int
+    bitmaps: np.ndarray        # (levels, words_per_level(n)) uint64
+    ranks: np.ndarray | None   # (levels, rank_stride(n)) uint64, or None
+    zeros: np.ndarray          # (levels,) uint64: zeros of each level
+
+
+def build_matrix(S: np.ndarray, sigma: int, with_ranks: bool = True) -> OracleMatrix:
+    """Sequential wavelet-matrix construction from its definition."""
+    S = np.ascontiguousarray(S)
+    width = S.dtype.itemsize
+    n = int(S.shape[0])
+    lv = levels(sigma)
+    B = np.zeros((lv, words_per_level(n)), dtype=np.uint64)
+    R = np.zeros((lv, rank_stride(n)), dtype=np.uint64) if with_ranks else None
+    Z = np.zeros(max(lv, 1), dtype=np.uint64)
+    rc = lib().wto_build_matrix(_ptr(S), n, sigma, width, _ptr(B), _ptr(R) if R is not None else None, _ptr(Z))
+    if rc != OK:
+        raise ValueError("oracle wto_build_matrix status %d" % rc)
+    return OracleMatrix(n, sigma, lv, B, R, Z[:lv])
+
+
+def matrix_access(t: OracleMatrix, i: int) -> int:
+    sym = ctypes.c_uint32()
+    rc = lib().wto_matrix_access(_ptr(t.bitmaps), _ptr(t.zeros), t.n, t.sigma, i, ctypes.byref(sym))
+    if rc != OK:
+        raise ValueError("matrix access status %d" % rc)
+    return int(sym.value)
+
+
+def matrix_rank(t: OracleMatrix, c: int, i: int) -> int:
+    out = ctypes.c_uint64()
+    rc = lib().wto_matrix_rank(_ptr(t.bitmaps), _ptr(t.zeros), t.n, t.sigma, c, i, ctypes.byref(out))
+    if rc != OK:
+        raise ValueError("matrix rank status %d" % rc)
+    return int(out.value)
+
+
+def matrix_select(t: OracleMatrix, c: int, j: int):
+    out = ctypes.c_uint64()
+    rc = lib().wto_matrix_select(_ptr(t.bitmaps), _ptr(t.zeros), t.n, t.sigma, c, j, ctypes.byref(out))
+    if rc == ENOTFOUND:
+        return None
+    if rc != OK:
+        raise ValueError("matrix select status %d" % rc)
+    return int(out.value)

@@ -283,3 +283,143 @@ int wto_decode(const uint64_t *B, uint64_t n, uint32_t sigma, uint32_t *out)
     free(cnt);
     return WTO_OK;
 }
+
+/* ---------------------------------------------------- wavelet matrix ---- */
+/*
+ * The wavelet matrix, one of the variants the paper names as future work
+ * (Section 5): the paper gives no construction for it, so this follows its
+ * standard definition (Claude, Navarro and Ordonez, "The wavelet matrix",
+ * Information Systems 2015).  A_0 = S; level i's bitmap is bit (l-1-i) of
+ * A_i, position by position; A_{i+1} is A_i stably partitioned by that bit
+ * over the whole level (all zeros first, in order, then all ones); z_i is
+ * the number of zeros of level i.  Same word and rank-directory conventions
+ * as the tree above.
+ */
+int wto_build_matrix(const void *S, uint64_t n, uint32_t sigma, uint32_t width,
+                     uint64_t *B, uint64_t *R, uint64_t *Z)
+{
+    if (sigma == 0 || (width != 1 && width != 2 && width != 4)) return WTO_EINVAL;
+    if (width < 4 && (uint64_t)sigma > (1ull << (8 * width))) return WTO_EINVAL;
+    for (uint64_t j = 0; j < n; j++)
+        if (sym_at(S, width, j) >= sigma) return WTO_ERANGE;
+
+    uint32_t l = wto_levels(sigma);
+    uint64_t W = wto_words_per_level(n);
+    uint64_t K = wto_rank_entries(n), KS = wto_rank_stride(n);
+    uint64_t *A = (uint64_t *)malloc((n ? n : 1) * sizeof(uint64_t));
+    uint64_t *Anext = (uint64_t *)malloc((n ? n : 1) * sizeof(uint64_t));
+    if (!A || !Anext) { free(A); free(Anext); return WTO_ENOMEM; }
+    for (uint64_t j = 0; j < n; j++) A[j] = sym_at(S, width, j);
+
+    for (uint32_t i = 0; i < l; i++) {
+        uint32_t sh = l - 1 - i;
+        uint64_t *Bi = B + (uint64_t)i * W;
+        memset(Bi, 0, W * sizeof(uint64_t));
+        uint64_t zeros = 0;
+        for (uint64_t p = 0; p < n; p++) {
+            uint64_t bit = (A[p] >> sh) & 1u;
+            if (bit) Bi[p >> 6] |= 1ull << (p & 63);
+            else zeros++;
+        }
+        if (Z) Z[i] = zeros;
+        /* stable partition: zeros in order, then ones in order */
+        uint64_t zp = 0, op = zeros;
+        for (uint64_t p = 0; p < n; p++) {
+            if ((A[p] >> sh) & 1u) Anext[op++] = A[p];
+            else Anext[zp++] = A[p];
+        }
+        uint64_t *t = A; A = Anext; Anext = t;
+        if (R) {
+            uint64_t *Ri = R + (uint64_t)i * KS;
+            memset(Ri, 0, KS * sizeof(uint64_t));
+            uint64_t ones = 0;
+            for (uint64_t p = 0; p < n; p++) {
+                if ((p & 511) == 0) Ri[p >> 9] = ones;
+                ones += (uint64_t)get_bit(Bi, p);
+            }
+            Ri[K - 1] = ones;
+        }
+    }
+    free(A);
+    free(Anext);
+    return WTO_OK;
+}
+
+/*
+ * Matrix queries (same definition): reading bit b at position p of level
+ * i, the walk continues at rank0(B_i, p) when b = 0 and at
+ * z_i + rank1(B_i, p) when b = 1.  Ranks are counted bit by bit.
+ */
+int wto_matrix_access(const uint64_t *B, const uint64_t *Z, uint64_t n, uint32_t sigma, uint64_t i,
+                      uint32_t *sym)
+{
+    if (i >= n) return WTO_EINVAL;
+    uint32_t l = wto_levels(sigma);
+    uint64_t W = wto_words_per_level(n);
+    uint64_t p = i;
+    uint32_t s = 0;
+    for (uint32_t k = 0; k < l; k++) {
+        const uint64_t *Bk = B + (uint64_t)k * W;
+        int bit = get_bit(Bk, p);
+        uint64_t ones = ones_in(Bk, 0, p);
+        p = bit ? Z[k] + ones : p - ones;
+        s = (s << 1) | (uint32_t)bit;
+    }
+    *sym = s;
+    return WTO_OK;
+}
+
+/* rank(c, i): the range [b, e) of the symbols before i narrows level by level. */
+int wto_matrix_rank(const uint64_t *B, const uint64_t *Z, uint64_t n, uint32_t sigma, uint32_t c,
+                    uint64_t i, uint64_t *out)
+{
+    if (c >= sigma || i > n) return WTO_EINVAL;
+    uint32_t l = wto_levels(sigma);
+    uint64_t W = wto_words_per_level(n);
+    uint64_t b = 0, e = i;
+    for (uint32_t k = 0; k < l; k++) {
+        const uint64_t *Bk = B + (uint64_t)k * W;
+        uint64_t ob = ones_in(Bk, 0, b), oe = ones_in(Bk, 0, e);
+        if ((c >> (l - 1 - k)) & 1u) { b = Z[k] + ob; e = Z[k] + oe; }
+        else                         { b = b - ob; e = e - oe; }
+    }
+    *out = e - b;
+    return WTO_OK;
+}
+
+/* select(c, j): the j-th (1-based) c; WTO_ENOTFOUND when there is none. */
+int wto_matrix_select(const uint64_t *B, const uint64_t *Z, uint64_t n, uint32_t sigma, uint32_t c,
+                      uint64_t j, uint64_t *out)
+{
+    if (c >= sigma) return WTO_EINVAL;
+    uint64_t occ;
+    int rc = wto_matrix_rank(B, Z, n, sigma, c, n, &occ);
+    if (rc != WTO_OK) return rc;
+    if (j == 0 || j > occ) return WTO_ENOTFOUND;
+    uint32_t l = wto_levels(sigma);
+    uint64_t W = wto_words_per_level(n);
+    /* start of c's block at the bottom: follow position 0 down */
+    uint64_t b = 0;
+    for (uint32_t k = 0; k < l; k++) {
+        const uint64_t *Bk = B + (uint64_t)k * W;
+        uint64_t ob = ones_in(Bk, 0, b);
+        b = ((c >> (l - 1 - k)) & 1u) ? Z[k] + ob : b - ob;
+    }
+    uint64_t p = b + j - 1;
+    /* back up: the position holding the (t+1)-th zero / one of level k */
+    for (uint32_t k = l; k-- > 0;) {
+        const uint64_t *Bk = B + (uint64_t)k * W;
+        int want = (int)((c >> (l - 1 - k)) & 1u);
+        uint64_t t = want ? p - Z[k] : p;   /* rank of the wanted bit */
+        uint64_t seen = 0, q = 0;
+        for (q = 0; q < n; q++) {
+            if (get_bit(Bk, q) == want) {
+                if (seen == t) break;
+                seen++;
+            }
+        }
+        p = q;
+    }
+    *out = p;
+    return WTO_OK;
+}
