@@ -93,6 +93,27 @@ int wt_build(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t tree_b
              void *d_work, uint64_t work_bytes, void *stream, wt_tree **out);
 
 /*
+ * Wavelet matrix of S (a variant the paper names as future work, Section 5;
+ * built from its standard definition): A_0 = S, level i's bitmap is bit
+ * (l-1-i) of A_i position by position, and A_{i+1} is A_i stably
+ * partitioned by that bit over the whole level (zeros first).  Same
+ * arguments, footprint (wt_footprint), memory rules and bitmap / rank
+ * directory layout as wt_build; the zeros z_i of every level are kept in
+ * the tree header and returned by wt_matrix_zeros.  All queries below accept
+ * a matrix handle and answer for S (access / rank / select walk the levels
+ * with z_i: bit b at p continues at rank0(p), or z_i + rank1(p)).
+ */
+int wt_build_matrix(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t tree_bytes,
+                    void *d_work, uint64_t work_bytes, void *stream, wt_tree **out);
+
+/*
+ * zeros[i] = z_i for the levels i of a wavelet matrix (host array of
+ * `levels` entries); waits for the build's stream.  WT_EINVAL for a tree
+ * handle.
+ */
+int wt_matrix_zeros(const wt_tree *tree, uint64_t *zeros);
+
+/*
  * Workspace bytes that wt_build_batch needs for the m sequences descs[0..m).
  * Tree memory of sequence q is its own wt_footprint tree_bytes.
  */

@@ -169,6 +169,7 @@ static SmallJob make_small_job(const Layout &L, const void *S, void *tree) {
     j.words = (uint32_t)L.words;
     j.rank_entries = (uint32_t)L.rank_entries;
     j.rank_stride = (uint32_t)L.rank_stride;
+    j.matrix = L.matrix;
     return j;
 }
 
@@ -197,6 +198,8 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
     hipError_t err = launch_zero(work + L.ws_ctrl, L.ws_ctrl_bytes, tree_status, L.n == 0 ? ranks : nullptr,
                                  (uint64_t)l * L.rank_stride, st);
     prof_end(pr, st);
+    if (err == hipSuccess && L.n == 0 && L.matrix && l)  // the zeros of an empty matrix
+        err = launch_zero(tree + kZerosOff, (uint64_t)l * 8, tree_status, nullptr, 0, st);
     if (err != hipSuccess || L.n == 0) return err;
 
     IngestArgs ia;
@@ -231,9 +234,10 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         pa.zo = zo + zo_offset(i);
         pa.start_next = (i + 1 < l) ? start + start_offset(i + 1) : nullptr;
         pa.partials = partials;
-        pa.nodes = 1ull << i;
+        pa.nodes = L.matrix ? 1ull : 1ull << i;  // a matrix level is one node
         pa.slots = level_slots(i);
         pa.n = L.n;
+        pa.matrix = L.matrix;
         const bool big = pa.nodes > kScanChunk;  // one counter slot there
         if (big) {
             pr = prof_begin(st, "plan", i, L.width, L.n, pa.nodes * (8 + 16 + 8 + 16));
@@ -264,7 +268,7 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         a.sup = sup + (uint64_t)i * L.nsup;
         a.tile_ones_next = (i + 1 < l) ? tile_ones + (uint64_t)(i + 1) * tile_stride(L.ntiles) : nullptr;
         a.ones_next = (i + 1 < l) ? ones + ones_offset(i + 1) : nullptr;
-        a.nodes_next = 2ull << i;
+        a.nodes_next = L.matrix ? 1ull : 2ull << i;
         a.slots_next = level_slots(i + 1);
         a.n = L.n;
         a.words = L.words;
@@ -274,9 +278,11 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         a.levels = l;
         a.level = i;
         a.symmask = (uint32_t)((1ull << l) - 1);
+        a.matrix = L.matrix;
+        a.zeros = L.matrix ? reinterpret_cast<unsigned long long *>(tree + kZerosOff) : nullptr;
         const uint64_t lbytes = L.n * L.width * (a.tout ? 2 : 1) + L.words * 8 + L.rank_stride * 8;
         pr = prof_begin(st, "level", i, L.width, L.n, lbytes);
-        err = launch_level(a, L.width, L.lane_bytes, level_multi(L.n, i, L.width, L.lane_bytes), st);
+        err = launch_level(a, L.width, L.lane_bytes, !L.matrix && level_multi(L.n, i, L.width, L.lane_bytes), st);
         prof_end(pr, st);
         if (err != hipSuccess) return err;
     }
@@ -302,6 +308,7 @@ static TreeView view_of(const wt_tree *t) {
     v.rank_stride = t->L.rank_stride;
     v.sigma = t->L.sigma;
     v.levels = t->L.levels;
+    v.zeros = t->L.matrix ? reinterpret_cast<const unsigned long long *>(t->tree + kZerosOff) : nullptr;
     return v;
 }
 
@@ -423,8 +430,8 @@ int wt_footprint(const wt_desc *desc, uint64_t *tree_bytes, uint64_t *work_bytes
     return WT_OK;
 }
 
-int wt_build(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t tree_bytes, void *d_work,
-             uint64_t work_bytes, void *stream, wt_tree **out) {
+static int build_one(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t tree_bytes, void *d_work,
+                     uint64_t work_bytes, void *stream, wt_tree **out, uint32_t matrix) {
     if (out) *out = nullptr;
     int rc = check_desc(desc);
     if (rc != WT_OK) return rc;
@@ -432,6 +439,7 @@ int wt_build(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t tree_b
     if (((uintptr_t)d_S & 15) || ((uintptr_t)d_tree & 255) || ((uintptr_t)d_work & 255)) return WT_EINVAL;
     Layout L;
     make_layout(desc->n, desc->sigma, desc->width, false, &L);
+    L.matrix = matrix;
     if (tree_bytes < L.tree_bytes || work_bytes < L.work_bytes) return WT_ENOMEM;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     wt_tree *h = new_handle(L, d_tree, st);
@@ -442,6 +450,25 @@ int wt_build(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t tree_b
         return WT_EDEVICE;
     }
     *out = h;
+    return WT_OK;
+}
+
+int wt_build(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t tree_bytes, void *d_work,
+             uint64_t work_bytes, void *stream, wt_tree **out) {
+    return build_one(d_S, desc, d_tree, tree_bytes, d_work, work_bytes, stream, out, 0u);
+}
+
+int wt_build_matrix(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t tree_bytes, void *d_work,
+                    uint64_t work_bytes, void *stream, wt_tree **out) {
+    return build_one(d_S, desc, d_tree, tree_bytes, d_work, work_bytes, stream, out, 1u);
+}
+
+int wt_matrix_zeros(const wt_tree *t, uint64_t *zeros) {
+    if (!t || !zeros || !t->L.matrix) return WT_EINVAL;
+    if (t->L.levels == 0) return WT_OK;
+    if (hipStreamSynchronize(t->stream) != hipSuccess) return WT_EDEVICE;
+    if (hipMemcpy(zeros, t->tree + kZerosOff, t->L.levels * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return WT_EDEVICE;
     return WT_OK;
 }
 

@@ -346,14 +346,17 @@ __device__ __forceinline__ unsigned long long plan_chunk(const PlanArgs &a, cons
             const unsigned long long ones = loc[q];
             const uint64_t s_next = a.start[v + 1];
             a.zo[v] = make_ulonglong2(o1, s_next - ones - o1);
-            if (a.start_next) {
+            if (a.start_next && !a.matrix) {
                 a.start_next[2 * v] = a.start[v];
                 a.start_next[2 * v + 1] = s_next - ones;
             }
             o1 += ones;
         }
     }
-    if (a.start_next && b0 == 0 && threadIdx.x == 0) a.start_next[2 * a.nodes] = a.n;
+    if (a.start_next && b0 == 0 && threadIdx.x == 0) {
+        if (a.matrix) a.start_next[0] = 0;
+        a.start_next[a.matrix ? 1 : 2 * a.nodes] = a.n;
+    }
     return tot;
 }
 
@@ -949,6 +952,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         const uint64_t k = pos0 >> 9;
         if (k < a.rank_stride) a.ranks[k] = (k < a.rank_entries) ? r_lane : 0ull;
     }
+    if (a.zeros && t == a.ntiles - 1 && lane == 0) a.zeros[a.level] = a.n - (prefix + agg);
     if (t == a.ntiles - 1 && lane < 8) {  // entries past the last tile
         const uint64_t k = (base + TILE) / 512 + lane;
         if (k < a.rank_stride) a.ranks[k] = (k < a.rank_entries) ? prefix + agg : 0ull;
@@ -958,7 +962,8 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
 
     // node span of the tile (T_i is sorted by node)
     const bool full = (nvalid == TILE);  // every tile but a ragged last one
-    const uint32_t vf =
+    // (a wavelet matrix has one node per level: every tile is single-node)
+    const uint32_t vf = a.matrix ? 0u :
         (uint32_t)__builtin_amdgcn_readlane((int)((raw_elem<W, B>(raw, 0) & a.symmask) >> nsh), 0);
     uint32_t vl;
     if (full) {
@@ -971,7 +976,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         for (int k = 0; k < E; k++) xv = (k == kl) ? raw_elem<W, B>(raw, k) : xv;
         vl = (uint32_t)__builtin_amdgcn_readlane((int)((xv & a.symmask) >> nsh), (int)(last / E));
     }
-    vl = __builtin_amdgcn_readfirstlane(vl);
+    vl = a.matrix ? 0u : __builtin_amdgcn_readfirstlane(vl);
 
     T *tout = reinterpret_cast<T *>(a.tout);
     const bool counting = a.tile_ones_next != nullptr;
@@ -1113,7 +1118,7 @@ __device__ __forceinline__ void flush_split_recs(const LevelArgs &a, const Split
     const uint32_t w = r / 4, q = r % 4;
     const uint32_t c = recs[w].cnt[q];
     if (c == 0) return;
-    const uint32_t dt = recs[w].dt[q], child = recs[w].child + (q >> 1);
+    const uint32_t dt = recs[w].dt[q], child = a.matrix ? 0u : recs[w].child + (q >> 1);
     uint32_t sum_dt = 0, sum_ch = 0;
     bool first_dt = true, first_ch = true;
     for (uint32_t r2 = 0; r2 < 4 * kWaves; r2++) {
@@ -1124,7 +1129,7 @@ __device__ __forceinline__ void flush_split_recs(const LevelArgs &a, const Split
             sum_dt += c2;
             if (r2 < r) first_dt = false;
         }
-        if (recs[w2].child + (q2 >> 1) == child) {
+        if ((a.matrix ? 0u : recs[w2].child + (q2 >> 1)) == child) {
             sum_ch += c2;
             if (r2 < r) first_ch = false;
         }
@@ -1176,6 +1181,8 @@ __device__ __forceinline__ LevelArgs job_level(const BatchJob &j, uint32_t i) {
     a.levels = l;
     a.level = i;
     a.symmask = (uint32_t)((1ull << l) - 1);
+    a.matrix = 0;
+    a.zeros = nullptr;
     return a;
 }
 
@@ -1196,6 +1203,7 @@ __device__ __forceinline__ PrepArgs job_prep(const BatchJob &j, uint32_t i) {
     p.plan.nodes = 1ull << i;
     p.plan.slots = level_slots(i);
     p.plan.n = j.n;
+    p.plan.matrix = 0;
     p.plan_here = (p.plan.nodes > kScanChunk) ? 0u : 1u;  // larger levels: the k_batch_plan_* kernels
     return p;
 }

@@ -35,6 +35,9 @@ __host__ __device__ constexpr uint32_t one_wg_cap(uint32_t width, uint32_t geom)
 // Entries per level of the per-tile counts: a multiple of 4, so that a lane
 // reads four consecutive counts with one 16-byte load.
 __host__ __device__ constexpr uint64_t tile_stride(uint64_t ntiles) { return (ntiles + 3) / 4 * 4; }
+// Tree header: status word at byte 0; for a wavelet matrix, the zeros of
+// every level (u64) from byte kZerosOff (24 levels fit the 256-byte header).
+constexpr uint64_t kZerosOff = 8;
 // Tiles per superchunk of the tile-count scan (four counts per lane).
 constexpr uint64_t kSup = kThreads;
 // Node ones counters of shallow levels are spread over slots so that the
@@ -66,6 +69,7 @@ struct Layout {
     uint64_t n;
     uint32_t sigma, width, levels, lane_bytes;
     uint32_t small;         // 0, or kGeomSmall / kGeomMid: built by one workgroup (no workspace)
+    uint32_t matrix;        // a wavelet matrix rather than a wavelet tree
     uint64_t words;         // W: bitmap words per level
     uint64_t rank_entries;  // K
     uint64_t rank_stride;   // round_up(K, 8)
@@ -92,9 +96,10 @@ uint32_t tuned_geometry(uint64_t n, uint32_t sigma, uint32_t width, bool batched
 // One short sequence for the one-workgroup build.
 struct SmallJob {
     const void *S;
-    uint8_t *tree;  // status word at offset 0
+    uint8_t *tree;  // status word at offset 0, wavelet-matrix zeros at kZerosOff
     uint64_t bits_off, ranks_off;
     uint32_t n, sigma, levels, words, rank_entries, rank_stride;
+    uint32_t matrix;
 };
 hipError_t launch_small_one(const SmallJob &j, uint32_t width, uint32_t geom, hipStream_t s);
 hipError_t launch_small_batch(const SmallJob *d_jobs, uint32_t count, uint32_t width, uint32_t geom, hipStream_t s);
@@ -113,6 +118,9 @@ struct LevelArgs {
     uint64_t nodes_next, slots_next;
     uint64_t n, words, rank_entries, rank_stride, ntiles;
     uint32_t levels, level, symmask;
+    // wavelet matrix: one node per level; zeros[level] receives z_i
+    uint32_t matrix;
+    unsigned long long *zeros;
 };
 
 struct IngestArgs {
@@ -133,6 +141,7 @@ struct PlanArgs {
     uint64_t *start_next;              // level i+1 starts (null on the last level)
     uint64_t *partials;
     uint64_t nodes, slots, n;
+    uint32_t matrix;                   // wavelet matrix: the next level is again one node [0, n)
 };
 
 struct PrepArgs {
@@ -203,6 +212,7 @@ hipError_t launch_batch_level(const BatchClass &c, uint32_t width, uint32_t lane
 struct TreeView {
     const uint64_t *bits;
     const uint64_t *ranks;
+    const unsigned long long *zeros;  // wavelet matrix: zeros of every level (else null)
     uint64_t n, words, rank_entries, rank_stride;
     uint32_t sigma, levels;
 };

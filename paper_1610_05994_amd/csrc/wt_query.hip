@@ -77,9 +77,53 @@ __device__ uint64_t select0(const Level &L, uint64_t K, uint64_t n, uint64_t m) 
     return w * 64 + select_in_word(~L.B[w], (uint32_t)(m - r - 1));
 }
 
+// Wavelet matrix (one node per level, z_k zeros at level k): reading bit b
+// at position p of level k, the walk continues at rank0(p) for b = 0 and at
+// z_k + rank1(p) for b = 1.
+__device__ uint32_t matrix_access(const TreeView &t, uint64_t i) {
+    uint64_t p = i;
+    uint32_t s = 0;
+    for (uint32_t k = 0; k < t.levels; k++) {
+        const Level L = level_of(t, k);
+        const uint32_t bit = (uint32_t)((L.B[p >> 6] >> (p & 63)) & 1ull);
+        const uint64_t r1 = rank1(L, p);
+        p = bit ? t.zeros[k] + r1 : p - r1;
+        s = (s << 1) | bit;
+        if (p >= t.n) return 0xFFFFFFFEu;  // corrupted matrix only
+    }
+    return s;
+}
+
+// The range [b, e) of the symbols c among positions [0, i), at the bottom.
+__device__ void matrix_range(const TreeView &t, uint32_t c, uint64_t i, uint64_t &b, uint64_t &e) {
+    b = 0;
+    e = i;
+    for (uint32_t k = 0; k < t.levels; k++) {
+        const Level L = level_of(t, k);
+        const uint64_t rb = rank1(L, b), re = rank1(L, e);
+        if ((c >> (t.levels - 1 - k)) & 1u) { b = t.zeros[k] + rb; e = t.zeros[k] + re; }
+        else                                 { b = b - rb; e = e - re; }
+    }
+}
+
+__device__ uint64_t matrix_select(const TreeView &t, uint32_t c, uint64_t j) {
+    uint64_t b, e;
+    matrix_range(t, c, t.n, b, e);
+    if (j == 0 || j > e - b) return ~0ull;
+    uint64_t p = b + j - 1;
+    for (uint32_t k = t.levels; k-- > 0;) {  // back up: the (t+1)-th zero / one of level k
+        const Level L = level_of(t, k);
+        if ((c >> (t.levels - 1 - k)) & 1u) p = select1(L, t.rank_entries, (t.n + 63) / 64, p - t.zeros[k] + 1);
+        else p = select0(L, t.rank_entries, t.n, p + 1);
+        if (p >= t.n) return ~0ull;
+    }
+    return p;
+}
+
 // access(i): the symbol at position i (0xFFFFFFFF if i >= n).
 __device__ uint32_t access_one(const TreeView &t, uint64_t i) {
     if (i >= t.n) return 0xFFFFFFFFu;
+    if (t.zeros) return matrix_access(t, i);
     uint64_t b = 0, e = t.n, p = i;
     uint32_t s = 0;
     for (uint32_t k = 0; k < t.levels; k++) {
@@ -100,6 +144,11 @@ __device__ uint32_t access_one(const TreeView &t, uint64_t i) {
 // rank(c, i): occurrences of c in S[0, i) (UINT64_MAX if c >= sigma or i > n).
 __device__ uint64_t rank_one(const TreeView &t, uint32_t c, uint64_t i) {
     if (c >= t.sigma || i > t.n) return ~0ull;
+    if (t.zeros) {
+        uint64_t b, e;
+        matrix_range(t, c, i, b, e);
+        return e - b;
+    }
     uint64_t b = 0, e = t.n, cnt = i;
     for (uint32_t k = 0; k < t.levels; k++) {
         const Level L = level_of(t, k);
@@ -116,6 +165,7 @@ __device__ uint64_t rank_one(const TreeView &t, uint32_t c, uint64_t i) {
 // select(c, j): 0-based position of the j-th (1-based) c (UINT64_MAX if none).
 __device__ uint64_t select_one(const TreeView &t, uint32_t c, uint64_t j) {
     if (c >= t.sigma) return ~0ull;
+    if (t.zeros) return matrix_select(t, c, j);
     uint64_t bs[32];
     uint64_t b = 0, e = t.n;
     for (uint32_t k = 0; k < t.levels; k++) {  // node ranges of c, top-down

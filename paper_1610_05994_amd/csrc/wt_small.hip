@@ -133,13 +133,13 @@ __device__ void small_levels(const SmallJob &j, typename SElem<W>::T (*s_buf)[CA
             for (int q = 0; q < D; q++) d[q] = 0;
         }
         // level bits (bm) and run starts (fm) of the chunk
-        uint32_t vprev = (cnt && p0 > 0) ? ((uint32_t)tin[p0 - 1] >> nsh) : 0xFFFFFFFFu;
+        uint32_t vprev = (cnt && p0 > 0) ? (j.matrix ? 0u : ((uint32_t)tin[p0 - 1] >> nsh)) : 0xFFFFFFFFu;
         uint32_t bm = 0, fm = 0;
 #pragma unroll
         for (int k = 0; k < E; k++) {
             if ((uint32_t)k < cnt) {
                 const uint32_t x = sym_of<W>(d, k);
-                const uint32_t v = x >> nsh;
+                const uint32_t v = j.matrix ? 0u : x >> nsh;  // a matrix level is one node
                 bm |= ((x >> sh) & 1u) << k;
                 fm |= (v != vprev ? 1u : 0u) << k;
                 vprev = v;
@@ -154,7 +154,10 @@ __device__ void small_levels(const SmallJob &j, typename SElem<W>::T (*s_buf)[CA
 #pragma unroll
         for (int k = 0; k < E; k++)
             if ((fm >> k) & 1u) s_rank[p0 + k] = (uint16_t)(base + __popc(bm & ((1u << k) - 1u)));
-        if (tid == 0) s_rank[n] = (uint16_t)sc.total;
+        if (tid == 0) {
+            s_rank[n] = (uint16_t)sc.total;
+            if (j.matrix) reinterpret_cast<unsigned long long *>(j.tree + kZerosOff)[i] = n - sc.total;
+        }
 
         // bitmap words: 64 / E consecutive threads form one word (chunks of
         // positions >= n contribute zeros, so padding words are written too)

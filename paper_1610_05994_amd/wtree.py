@@ -22,7 +22,7 @@ WT_OK, WT_EINVAL, WT_ERANGE, WT_ENOMEM, WT_ENOTFOUND, WT_EDEVICE = range(6)
 WT_MAX_SIGMA = 1 << 24
 
 EXPORTED = [
-    "wt_footprint", "wt_build", "wt_batch_footprint", "wt_build_batch", "wt_tree_status",
+    "wt_footprint", "wt_build", "wt_build_matrix", "wt_matrix_zeros", "wt_batch_footprint", "wt_build_batch", "wt_tree_status",
     "wt_free", "wt_levels", "wt_access_batch", "wt_rank_batch", "wt_select_batch",
     "wt_access", "wt_rank", "wt_select", "wt_query_multi_footprint", "wt_query_multi", "wt_strerror",
     "wt_tune_set", "wt_tune_get",
@@ -61,6 +61,8 @@ def lib():
     sig = {
         "wt_footprint": ([P(wt_desc), P(u64), P(u64)], i32),
         "wt_build": ([vp, P(wt_desc), vp, u64, vp, u64, vp, P(vp)], i32),
+        "wt_build_matrix": ([vp, P(wt_desc), vp, u64, vp, u64, vp, P(vp)], i32),
+        "wt_matrix_zeros": ([vp, P(u64)], i32),
         "wt_batch_footprint": ([u32, P(wt_desc), P(u64)], i32),
         "wt_build_batch": ([u32, P(vp), P(wt_desc), P(vp), P(u64), vp, u64, vp, P(vp)], i32),
         "wt_tree_status": ([vp], i32),
@@ -124,6 +126,21 @@ def wt_build(d_S: int, n: int, sigma: int, width: int, d_tree: int, tree_bytes: 
     h = ctypes.c_void_p()
     rc = lib().wt_build(d_S, ctypes.byref(d), d_tree, tree_bytes, d_work, work_bytes, stream, ctypes.byref(h))
     return rc, h.value
+
+
+def wt_build_matrix(d_S: int, n: int, sigma: int, width: int, d_tree: int, tree_bytes: int, d_work: int,
+                    work_bytes: int, stream: int):
+    d = wt_desc(n, sigma, width)
+    h = ctypes.c_void_p()
+    rc = lib().wt_build_matrix(d_S, ctypes.byref(d), d_tree, tree_bytes, d_work, work_bytes, stream,
+                               ctypes.byref(h))
+    return rc, h.value
+
+
+def wt_matrix_zeros(h: int, levels: int):
+    z = (ctypes.c_uint64 * max(1, levels))()
+    rc = lib().wt_matrix_zeros(h, z)
+    return rc, np.array(z[:levels], dtype=np.uint64)
 
 
 def wt_batch_footprint(descs):
@@ -245,8 +262,10 @@ def _alloc(nbytes: int, device):
 class Tree:
     """A built tree whose memory is a torch tensor; owns the C handle."""
 
-    def __init__(self, handle: int, tree_mem, work_mem, S, n: int, sigma: int, width: int, stream):
+    def __init__(self, handle: int, tree_mem, work_mem, S, n: int, sigma: int, width: int, stream,
+                 matrix: bool = False):
         self.handle = handle
+        self.matrix = matrix
         self.tree_mem = tree_mem
         self.work_mem = work_mem   # kept alive until the build has finished
         self.S = S
@@ -268,6 +287,13 @@ class Tree:
         rc = self.status()
         if rc != WT_OK:
             raise WtError(rc, "build")
+
+    def zeros(self) -> np.ndarray:
+        """z_i of every level (wavelet matrix only)."""
+        rc, z = wt_matrix_zeros(self.handle, self.levels)
+        if rc != WT_OK:
+            raise WtError(rc, "wt_matrix_zeros")
+        return z
 
     def release_workspace(self) -> None:
         self.work_mem = None
@@ -349,8 +375,10 @@ def to_device(S: np.ndarray, device="cuda"):
     return torch.from_numpy(np.ascontiguousarray(S).view(view)).to(device)
 
 
-def build(S, sigma: int, width: int | None = None, stream=None, tree_mem=None, work_mem=None) -> Tree:
-    """Build the tree of a device tensor S (uint8 / int16 / int32 storage)."""
+def build(S, sigma: int, width: int | None = None, stream=None, tree_mem=None, work_mem=None,
+          matrix: bool = False) -> Tree:
+    """Build the tree (or, with matrix=True, the wavelet matrix) of a device
+    tensor S (uint8 / int16 / int32 storage)."""
     torch = _torch()
     width = width or S.element_size()
     n = S.numel()
@@ -361,11 +389,12 @@ def build(S, sigma: int, width: int | None = None, stream=None, tree_mem=None, w
     tree_mem = tree_mem if tree_mem is not None else _alloc(tb, dev)
     work_mem = work_mem if work_mem is not None else _alloc(wb, dev)
     st = stream if stream is not None else torch.cuda.current_stream(dev)
-    rc, h = wt_build(S.data_ptr() if n else 0, n, sigma, width, tree_mem.data_ptr(), tree_mem.numel(),
-                     work_mem.data_ptr(), work_mem.numel(), int(st.cuda_stream))
+    fn = wt_build_matrix if matrix else wt_build
+    rc, h = fn(S.data_ptr() if n else 0, n, sigma, width, tree_mem.data_ptr(), tree_mem.numel(),
+               work_mem.data_ptr(), work_mem.numel(), int(st.cuda_stream))
     if rc != WT_OK:
-        raise WtError(rc, "wt_build")
-    return Tree(h, tree_mem, work_mem, S, n, sigma, width, st)
+        raise WtError(rc, "wt_build_matrix" if matrix else "wt_build")
+    return Tree(h, tree_mem, work_mem, S, n, sigma, width, st, matrix)
 
 
 def build_batch(Ss, sigmas, widths=None, stream=None):

@@ -173,3 +173,12 @@ def test_query_multi_argument_checks():
     assert wt.wt_query_multi([], 0, 0, 0, 0, 0, 0, 0, 0, 0) == wt.WT_OK          # m = 0: nothing to do
     assert wt.wt_query_multi([], 1, 1, 1, 1, 1, 5, 256, 256, 0) == wt.WT_EINVAL  # no trees
     assert wt.lib().wt_query_multi_footprint(3, None) == wt.WT_EINVAL
+
+
+def test_matrix_entry_points_argument_checks():
+    wt = _wt()
+    d = wt.wt_desc(10, 0, 1)
+    h = ctypes.c_void_p()
+    assert wt.lib().wt_build_matrix(None, ctypes.byref(d), None, 0, None, 0, None, ctypes.byref(h)) == wt.WT_EINVAL
+    z = (ctypes.c_uint64 * 4)()
+    assert wt.lib().wt_matrix_zeros(None, z) == wt.WT_EINVAL
