@@ -64,14 +64,15 @@ def load_traffic(workload: str):
     return ent.get("bytes_per_level_launch")
 
 
-def cpu_baseline(workload: str, lg: int, runs: int):
+def cpu_baseline(workload: str, lg: int, runs: int, matrix: bool = False):
     import oracle
     S, sigma = wtgen.workload("%s@lg%d" % (workload, lg))
-    oracle.build(S[:4096], sigma)  # load + warm the library
+    build = oracle.build_matrix if matrix else oracle.build
+    build(S[:4096], sigma)  # load + warm the library
     times = []
     for _ in range(runs):
         t0 = time.perf_counter()
-        oracle.build(S, sigma)
+        build(S, sigma)
         times.append(time.perf_counter() - t0)
     med = statistics.median(times)
     return {
@@ -114,6 +115,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--matrix", action="store_true",
+                    help="build the wavelet matrix of the workload instead of the wavelet tree (c1-c3)")
     ap.add_argument("--cpu-sample-lg", type=int, default=26)
     ap.add_argument("--cpu-runs", type=int, default=3)
     ap.add_argument("--input-cache", default="",
@@ -165,11 +168,12 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
+    build_fn = wtree.wt_build_matrix if args.matrix else wtree.wt_build
+
     def one_build():
-        rc, h = wtree.wt_build(dS.data_ptr(), n, sigma, width, tree_mem.data_ptr(), tb,
-                               work_mem.data_ptr(), wb, sh)
+        rc, h = build_fn(dS.data_ptr(), n, sigma, width, tree_mem.data_ptr(), tb, work_mem.data_ptr(), wb, sh)
         if rc != wtree.WT_OK:
-            raise wtree.WtError(rc, "wt_build")
+            raise wtree.WtError(rc, "wt_build_matrix" if args.matrix else "wt_build")
         return h
 
     print("bench: warmup %d" % args.warmup, file=sys.stderr, flush=True)
@@ -224,7 +228,7 @@ def main() -> int:
         f["avg_us"] = round(f["ms"] * 1e3 / f["launches"], 2)
         f["ms_per_step"] = round(f["ms"] / args.steps, 4)
         del f["ms"]
-    traffic = load_traffic(args.workload)
+    traffic = None if args.matrix else load_traffic(args.workload)
     levels = max(0, (sigma - 1).bit_length())
     qmin = n * width + (tb - 256)  # read S once + write every bitmap word and rank entry once
     qmin_gbps = qmin / (p50 / 1e3) / 1e9
@@ -242,7 +246,8 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": {1: "u8", 2: "u16", 4: "u32"}[width],
         "data": "synthetic",
-        "config": {"workload": "%s: %s" % (args.workload, WORKLOADS[args.workload]), "n": n, "sigma": sigma,
+        "config": {"workload": "%s: %s%s" % (args.workload, WORKLOADS[args.workload],
+                                             "; wavelet matrix" if args.matrix else ""), "n": n, "sigma": sigma,
                    "width_bytes": width, "levels": levels, "seed": wtgen.SEED_BASE + int(args.workload[1]) - 1},
         "roofline": {
             "bound": "hbm",
@@ -261,7 +266,7 @@ def main() -> int:
     }
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline on n=2^%d" % args.cpu_sample_lg, file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_lg, args.cpu_runs)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_lg, args.cpu_runs, args.matrix)
         out["cpu_multicore"] = cpu_multicore(args.workload, args.cpu_sample_lg, args.cpu_runs)
     print(json.dumps(out), flush=True)
     return 0
