@@ -114,6 +114,33 @@ int wt_build_matrix(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t
 int wt_matrix_zeros(const wt_tree *tree, uint64_t *zeros);
 
 /*
+ * Buffered build (the extension for inputs that do not fit, Section 5, on
+ * Algorithm dd of Section 3.2 and Function mergeBA): S is read in buffers of
+ * buffer_syms symbols; each buffer is copied to the device and built as a
+ * partial tree without using the rest of S, the partial trees' node offsets
+ * are combined by prefix sums over the buffers, and the partial bitmaps are
+ * concatenated into the final levels, whose rank directories are then
+ * written.  The tree is the one wt_build produces (same layout and
+ * queries).
+ *
+ * S may be host memory (page-locked memory lets the copy of one buffer
+ * overlap the build of the previous one; pageable memory works too) or
+ * device memory, any alignment.  The device holds two staging buffers, one
+ * partial-build workspace, the partial trees (about the size of the final
+ * tree's bitmaps) and an offset table of (buffers + 1) x (2^l + 1) u64, so
+ * the workspace grows with n l / 8 + (n / buffer_syms) 2^l * 8 bytes rather
+ * than with n * width.  With n <= buffer_syms it is one ordinary build of a
+ * staged copy.  The call returns once every symbol of S has been read (S may
+ * then be reused); the partial builds still in flight and the merge complete
+ * on `stream`.  WT_EINVAL for buffer_syms = 0 or more than 2^20 buffers.
+ */
+int wt_buffered_footprint(const wt_desc *desc, uint64_t buffer_syms, uint64_t *tree_bytes,
+                          uint64_t *work_bytes);
+int wt_build_buffered(const void *S, const wt_desc *desc, uint64_t buffer_syms, void *d_tree,
+                      uint64_t tree_bytes, void *d_work, uint64_t work_bytes, void *stream,
+                      wt_tree **out);
+
+/*
  * Workspace bytes that wt_build_batch needs for the m sequences descs[0..m).
  * Tree memory of sequence q is its own wt_footprint tree_bytes.
  */

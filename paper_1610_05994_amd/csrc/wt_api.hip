@@ -111,6 +111,10 @@ uint32_t tuned_geometry(uint64_t n, uint32_t sigma, uint32_t width, bool batched
 }
 
 void make_layout(uint64_t n, uint32_t sigma, uint32_t width, bool batched, Layout *L) {
+    make_layout_geom(n, sigma, width, tuned_geometry(n, sigma, width, batched), L);
+}
+
+void make_layout_geom(uint64_t n, uint32_t sigma, uint32_t width, uint32_t geom, Layout *L) {
     memset(L, 0, sizeof(*L));
     const uint32_t l = levels_for(sigma);
     L->n = n;
@@ -120,7 +124,6 @@ void make_layout(uint64_t n, uint32_t sigma, uint32_t width, bool batched, Layou
     L->words = round_up(ceil_div(n, 64), 8);
     L->rank_entries = ceil_div(n, 512) + 1;
     L->rank_stride = round_up(L->rank_entries, 8);
-    const uint32_t geom = tuned_geometry(n, sigma, width, batched);
     L->small = (geom == kGeomSmall || geom == kGeomMid) ? geom : 0u;
     L->lane_bytes = L->small ? kDefaultLaneBytes : geom;
     L->ntiles = ceil_div(n, tile_syms(width, L->lane_bytes));
@@ -235,7 +238,9 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         pa.start_next = (i + 1 < l) ? start + start_offset(i + 1) : nullptr;
         pa.partials = partials;
         pa.nodes = L.matrix ? 1ull : 1ull << i;  // a matrix level is one node
-        pa.slots = level_slots(i);
+        // a matrix level is a single node: its counters keep every slot of the
+        // level's allocation (level_slots(i) << i >= kSlotSpan entries)
+        pa.slots = L.matrix ? kSlotSpan : level_slots(i);
         pa.n = L.n;
         pa.matrix = L.matrix;
         const bool big = pa.nodes > kScanChunk;  // one counter slot there
@@ -269,7 +274,7 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         a.tile_ones_next = (i + 1 < l) ? tile_ones + (uint64_t)(i + 1) * tile_stride(L.ntiles) : nullptr;
         a.ones_next = (i + 1 < l) ? ones + ones_offset(i + 1) : nullptr;
         a.nodes_next = L.matrix ? 1ull : 2ull << i;
-        a.slots_next = level_slots(i + 1);
+        a.slots_next = L.matrix ? kSlotSpan : level_slots(i + 1);
         a.n = L.n;
         a.words = L.words;
         a.rank_entries = L.rank_entries;
@@ -414,6 +419,156 @@ static BatchJob make_job(const Layout &L, const void *S, void *tree, uint8_t *wo
     return j;
 }
 
+// ---------------------------------------------------------- buffered build --
+// S is read in buffers of b symbols; each becomes a partial tree in the
+// workspace, built with a tiled geometry so that its last-level node tables
+// (the leaf offsets of the buffer) are left in the partial workspace.
+struct BufPlan {
+    Layout L;          // the final tree
+    Layout Lb, Llast;  // a full partial tree and the last (ragged) one
+    uint64_t b, nbuf;
+    uint64_t stage_bytes, off_stage[2], off_pwork, off_ptrees, pstride, off_C, off_csum, row, wg_per_level;
+    uint64_t work_bytes;
+};
+
+constexpr uint64_t kMaxBuffers = 1ull << 20;
+
+static int plan_buffered(const wt_desc *d, uint64_t b, BufPlan *P) {
+    if (b == 0) return WT_EINVAL;
+    memset(P, 0, sizeof(*P));
+    make_layout(d->n, d->sigma, d->width, false, &P->L);
+    P->b = b < d->n ? b : (d->n ? d->n : 1);
+    P->nbuf = d->n ? ceil_div(d->n, P->b) : 1;
+    if (P->nbuf > kMaxBuffers) return WT_EINVAL;
+    P->stage_bytes = round_up(P->b * d->width, 256);
+    P->off_stage[0] = 0;
+    if (P->nbuf == 1) {  // one buffer: the ordinary build of the staged copy
+        P->off_pwork = P->stage_bytes;
+        P->work_bytes = P->off_pwork + P->L.work_bytes;
+        return WT_OK;
+    }
+    uint32_t g = tuned_geometry(P->b, d->sigma, d->width, false);
+    if (g == kGeomSmall || g == kGeomMid) g = 32;  // partial trees need node tables
+    make_layout_geom(P->b, d->sigma, d->width, g, &P->Lb);
+    make_layout_geom(d->n - (P->nbuf - 1) * P->b, d->sigma, d->width, g, &P->Llast);
+    const uint32_t l = P->L.levels;
+    uint64_t off = 0;
+    P->off_stage[0] = off;
+    off += P->stage_bytes;
+    P->off_stage[1] = off;
+    off += P->stage_bytes;
+    P->off_pwork = off;
+    off += P->Lb.work_bytes;
+    P->pstride = round_up(P->Lb.tree_bytes, 256);
+    P->off_ptrees = off;
+    off += P->nbuf * P->pstride;
+    P->row = (1ull << l) + 1;
+    P->off_C = off;
+    off += round_up((P->nbuf + 1) * P->row * 8, 256);
+    P->wg_per_level = ceil_div(ceil_div(d->n, 512), 256);
+    P->off_csum = off;
+    off += round_up((uint64_t)(l ? l : 1) * P->wg_per_level * 8, 256);
+    P->work_bytes = off;
+    return WT_OK;
+}
+
+// One non-blocking copy stream per device (default priority) for the
+// host-to-device copies of the buffers; it lives until the process ends.
+static hipStream_t copy_stream() {
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+        streams[dev] = nullptr;
+    return streams[dev];
+}
+
+// Copies buffer q of S into staging slot q & 1 (on the copy stream) and
+// builds its partial tree on `st`.  Double buffered: the copy of buffer q + 2
+// waits until the build of buffer q has consumed the slot.
+static hipError_t enqueue_buffered(const uint8_t *S, const BufPlan &P, uint8_t *tree, uint8_t *work, hipStream_t st) {
+    const uint64_t w = P.L.width;
+    if (P.nbuf == 1) {
+        uint8_t *stage = work + P.off_stage[0];
+        if (P.L.n == 0) return enqueue_build(stage, P.L, tree, work + P.off_pwork, st);
+        hipEvent_t done = nullptr;
+        hipError_t err = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+        if (err != hipSuccess) return err;
+        err = hipMemcpyAsync(stage, S, P.L.n * w, hipMemcpyDefault, st);
+        if (err == hipSuccess) err = hipEventRecord(done, st);
+        if (err == hipSuccess) err = enqueue_build(stage, P.L, tree, work + P.off_pwork, st);
+        if (err == hipSuccess) err = hipEventSynchronize(done);  // S has been read once the call returns
+        (void)hipEventDestroy(done);
+        return err;
+    }
+    hipStream_t cs = copy_stream();
+    if (!cs) return hipErrorInvalidValue;
+    hipEvent_t ev[5] = {};  // start, copied[2], used[2]
+    hipError_t err = hipSuccess;
+    for (int e = 0; e < 5 && err == hipSuccess; e++) err = hipEventCreateWithFlags(&ev[e], hipEventDisableTiming);
+    const uint32_t l = P.L.levels;
+    unsigned long long *C = reinterpret_cast<unsigned long long *>(work + P.off_C);
+    uint8_t *pwork = work + P.off_pwork;
+    if (err == hipSuccess) err = hipEventRecord(ev[0], st);  // the workspace is free once st gets here
+    if (err == hipSuccess) err = hipStreamWaitEvent(cs, ev[0], 0);
+    uint64_t copied = 0;  // buffers whose copy was enqueued
+    for (uint64_t q = 0; q < P.nbuf && err == hipSuccess; q++) {
+        const int s = (int)(q & 1);
+        const Layout &Lq = (q + 1 == P.nbuf) ? P.Llast : P.Lb;
+        uint8_t *stage = work + P.off_stage[s];
+        uint8_t *ptree = work + P.off_ptrees + q * P.pstride;
+        if (q >= 2) err = hipStreamWaitEvent(cs, ev[3 + s], 0);
+        if (err == hipSuccess) err = hipMemcpyAsync(stage, S + q * P.b * w, Lq.n * w, hipMemcpyDefault, cs);
+        if (err == hipSuccess) copied = q + 1;
+        if (err == hipSuccess) err = hipEventRecord(ev[1 + s], cs);
+        if (err == hipSuccess) err = hipStreamWaitEvent(st, ev[1 + s], 0);
+        if (err == hipSuccess) err = enqueue_build(stage, Lq, ptree, pwork, st);
+        if (err == hipSuccess && l)
+            err = launch_leaf_prefix(reinterpret_cast<const uint64_t *>(pwork + Lq.ws_start) + start_offset(l - 1),
+                                     reinterpret_cast<const ulonglong2 *>(pwork + Lq.ws_zo) + zo_offset(l - 1), l, Lq.n,
+                                     C + q * P.row, st);
+        if (err == hipSuccess && q + 2 < P.nbuf) err = hipEventRecord(ev[3 + s], st);
+    }
+    if (err == hipSuccess) {
+        MergeArgs a;
+        a.C = C;
+        a.ptrees = work + P.off_ptrees;
+        a.pstride = P.pstride;
+        a.pbits_off = P.Lb.tree_bits_off;
+        a.pwords = P.Lb.words;
+        a.pwords_last = P.Llast.words;
+        a.bits = reinterpret_cast<uint64_t *>(tree + P.L.tree_bits_off);
+        a.ranks = reinterpret_cast<uint64_t *>(tree + P.L.tree_ranks_off);
+        a.tree_status = reinterpret_cast<uint32_t *>(tree);
+        a.csum = reinterpret_cast<unsigned long long *>(work + P.off_csum);
+        a.n = P.L.n;
+        a.words = P.L.words;
+        a.rank_stride = P.L.rank_stride;
+        a.nblk = ceil_div(P.L.n, 512);
+        a.wg_per_level = P.wg_per_level;
+        a.row = P.row;
+        a.levels = l;
+        a.nbuf = (uint32_t)P.nbuf;
+        const uint64_t mbytes = (uint64_t)l * (P.L.words * 8 * 2 + P.L.rank_stride * 8);
+        long pr = prof_begin(st, "merge", 0, P.L.width, P.L.n, mbytes);
+        err = launch_merge(a, st);
+        prof_end(pr, st);
+    }
+    // S has been read once every enqueued copy is done; every event recorded
+    // above is complete by then, so they can be released.
+    if (copied) {
+        hipError_t e2 = hipEventSynchronize(ev[1 + (int)((copied - 1) & 1)]);
+        if (err == hipSuccess) err = e2;
+    } else {
+        (void)hipStreamSynchronize(cs);
+    }
+    for (int e = 0; e < 5; e++)
+        if (ev[e]) (void)hipEventDestroy(ev[e]);
+    return err;
+}
+
 }  // namespace wt
 
 using namespace wt;
@@ -469,6 +624,38 @@ int wt_matrix_zeros(const wt_tree *t, uint64_t *zeros) {
     if (hipStreamSynchronize(t->stream) != hipSuccess) return WT_EDEVICE;
     if (hipMemcpy(zeros, t->tree + kZerosOff, t->L.levels * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
         return WT_EDEVICE;
+    return WT_OK;
+}
+
+int wt_buffered_footprint(const wt_desc *desc, uint64_t buffer_syms, uint64_t *tree_bytes, uint64_t *work_bytes) {
+    int rc = check_desc(desc);
+    if (rc != WT_OK) return rc;
+    BufPlan P;
+    if ((rc = plan_buffered(desc, buffer_syms, &P)) != WT_OK) return rc;
+    if (tree_bytes) *tree_bytes = P.L.tree_bytes;
+    if (work_bytes) *work_bytes = P.work_bytes;
+    return WT_OK;
+}
+
+int wt_build_buffered(const void *S, const wt_desc *desc, uint64_t buffer_syms, void *d_tree, uint64_t tree_bytes,
+                      void *d_work, uint64_t work_bytes, void *stream, wt_tree **out) {
+    if (out) *out = nullptr;
+    int rc = check_desc(desc);
+    if (rc != WT_OK) return rc;
+    if (!out || !d_tree || !d_work || (desc->n > 0 && !S)) return WT_EINVAL;
+    if (((uintptr_t)d_tree & 255) || ((uintptr_t)d_work & 255)) return WT_EINVAL;
+    BufPlan P;
+    if ((rc = plan_buffered(desc, buffer_syms, &P)) != WT_OK) return rc;
+    if (tree_bytes < P.L.tree_bytes || work_bytes < P.work_bytes) return WT_ENOMEM;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    wt_tree *h = new_handle(P.L, d_tree, st);
+    if (!h) return WT_ENOMEM;
+    if (enqueue_buffered(reinterpret_cast<const uint8_t *>(S), P, reinterpret_cast<uint8_t *>(d_tree),
+                         reinterpret_cast<uint8_t *>(d_work), st) != hipSuccess) {
+        delete h;
+        return WT_EDEVICE;
+    }
+    *out = h;
     return WT_OK;
 }
 

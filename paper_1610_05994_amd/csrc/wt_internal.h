@@ -91,6 +91,9 @@ struct Layout {
 };
 
 void make_layout(uint64_t n, uint32_t sigma, uint32_t width, bool batched, Layout *L);
+// The same for a given geometry code (lane bytes, kGeomSmall or kGeomMid; a
+// one-workgroup code must hold n).
+void make_layout_geom(uint64_t n, uint32_t sigma, uint32_t width, uint32_t geom, Layout *L);
 uint32_t tuned_geometry(uint64_t n, uint32_t sigma, uint32_t width, bool batched);
 
 // One short sequence for the one-workgroup build.
@@ -207,6 +210,24 @@ hipError_t launch_batch_ingest(const BatchClass &c, uint32_t width, uint32_t lan
                                hipStream_t s);
 hipError_t launch_batch_level(const BatchClass &c, uint32_t width, uint32_t lane_bytes, bool multi, uint32_t level,
                               uint32_t active, uint64_t blocks, uint64_t sups, hipStream_t s);
+
+// Buffered build (wt_buffered.hip): merge of the partial trees of nbuf
+// buffers into one tree.
+struct MergeArgs {
+    unsigned long long *C;           // (nbuf + 1) rows of `row` = 2^l + 1 leaf offsets
+    const uint8_t *ptrees;           // partial trees, pstride bytes apart (status word first)
+    uint64_t pstride, pbits_off;     // partial tree stride and bitmap offset
+    uint64_t pwords, pwords_last;    // bitmap words per level of a full / the last partial tree
+    uint64_t *bits;                  // final bitmaps, `words` per level
+    uint64_t *ranks;                 // final rank directories, `rank_stride` per level
+    uint32_t *tree_status;           // final status word
+    unsigned long long *csum;        // per level, wg_per_level workgroup sums
+    uint64_t n, words, rank_stride, nblk, wg_per_level, row;
+    uint32_t levels, nbuf;
+};
+hipError_t launch_leaf_prefix(const uint64_t *start_last, const ulonglong2 *zo_last, uint32_t levels, uint64_t nq,
+                              unsigned long long *row, hipStream_t s);
+hipError_t launch_merge(const MergeArgs &a, hipStream_t s);  // column prefix, merge, rank directory, status
 
 // query launchers (wt_query.hip)
 struct TreeView {

@@ -25,7 +25,7 @@ EXPORTED = [
     "wt_footprint", "wt_build", "wt_build_matrix", "wt_matrix_zeros", "wt_batch_footprint", "wt_build_batch", "wt_tree_status",
     "wt_free", "wt_levels", "wt_access_batch", "wt_rank_batch", "wt_select_batch",
     "wt_access", "wt_rank", "wt_select", "wt_query_multi_footprint", "wt_query_multi", "wt_strerror",
-    "wt_tune_set", "wt_tune_get",
+    "wt_tune_set", "wt_tune_get", "wt_buffered_footprint", "wt_build_buffered",
     "wt_prof_enable", "wt_prof_read",
 ]
 
@@ -63,6 +63,8 @@ def lib():
         "wt_build": ([vp, P(wt_desc), vp, u64, vp, u64, vp, P(vp)], i32),
         "wt_build_matrix": ([vp, P(wt_desc), vp, u64, vp, u64, vp, P(vp)], i32),
         "wt_matrix_zeros": ([vp, P(u64)], i32),
+        "wt_buffered_footprint": ([P(wt_desc), u64, P(u64), P(u64)], i32),
+        "wt_build_buffered": ([vp, P(wt_desc), u64, vp, u64, vp, u64, vp, P(vp)], i32),
         "wt_batch_footprint": ([u32, P(wt_desc), P(u64)], i32),
         "wt_build_batch": ([u32, P(vp), P(wt_desc), P(vp), P(u64), vp, u64, vp, P(vp)], i32),
         "wt_tree_status": ([vp], i32),
@@ -141,6 +143,22 @@ def wt_matrix_zeros(h: int, levels: int):
     z = (ctypes.c_uint64 * max(1, levels))()
     rc = lib().wt_matrix_zeros(h, z)
     return rc, np.array(z[:levels], dtype=np.uint64)
+
+
+def wt_buffered_footprint(n: int, sigma: int, width: int, buffer_syms: int):
+    d = wt_desc(n, sigma, width)
+    tb, wb = ctypes.c_uint64(), ctypes.c_uint64()
+    rc = lib().wt_buffered_footprint(ctypes.byref(d), buffer_syms, ctypes.byref(tb), ctypes.byref(wb))
+    return rc, tb.value, wb.value
+
+
+def wt_build_buffered(S: int, n: int, sigma: int, width: int, buffer_syms: int, d_tree: int, tree_bytes: int,
+                      d_work: int, work_bytes: int, stream: int):
+    d = wt_desc(n, sigma, width)
+    h = ctypes.c_void_p()
+    rc = lib().wt_build_buffered(S, ctypes.byref(d), buffer_syms, d_tree, tree_bytes, d_work, work_bytes, stream,
+                                 ctypes.byref(h))
+    return rc, h.value
 
 
 def wt_batch_footprint(descs):
@@ -395,6 +413,30 @@ def build(S, sigma: int, width: int | None = None, stream=None, tree_mem=None, w
     if rc != WT_OK:
         raise WtError(rc, "wt_build_matrix" if matrix else "wt_build")
     return Tree(h, tree_mem, work_mem, S, n, sigma, width, st, matrix)
+
+
+def build_buffered(S, sigma: int, buffer_syms: int, width: int | None = None, device="cuda", stream=None,
+                   tree_mem=None, work_mem=None) -> Tree:
+    """Buffered build of S read in pieces of buffer_syms symbols.  S is a
+    host numpy array or torch tensor (page-locked for overlapped copies) or
+    a device tensor; it has been read completely when this returns."""
+    torch = _torch()
+    if isinstance(S, np.ndarray):
+        S = torch.from_numpy(np.ascontiguousarray(S).view({1: np.uint8, 2: np.int16, 4: np.int32}[S.dtype.itemsize]))
+    width = width or S.element_size()
+    n = S.numel()
+    rc, tb, wb = wt_buffered_footprint(n, sigma, width, buffer_syms)
+    if rc != WT_OK:
+        raise WtError(rc, "wt_buffered_footprint")
+    dev = torch.device(device) if not S.is_cuda else S.device
+    tree_mem = tree_mem if tree_mem is not None else _alloc(tb, dev)
+    work_mem = work_mem if work_mem is not None else _alloc(wb, dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    rc, h = wt_build_buffered(S.data_ptr() if n else 0, n, sigma, width, buffer_syms, tree_mem.data_ptr(),
+                              tree_mem.numel(), work_mem.data_ptr(), work_mem.numel(), int(st.cuda_stream))
+    if rc != WT_OK:
+        raise WtError(rc, "wt_build_buffered")
+    return Tree(h, tree_mem, work_mem, S, n, sigma, width, st)
 
 
 def build_batch(Ss, sigmas, widths=None, stream=None):

@@ -182,3 +182,29 @@ def test_matrix_entry_points_argument_checks():
     assert wt.lib().wt_build_matrix(None, ctypes.byref(d), None, 0, None, 0, None, ctypes.byref(h)) == wt.WT_EINVAL
     z = (ctypes.c_uint64 * 4)()
     assert wt.lib().wt_matrix_zeros(None, z) == wt.WT_EINVAL
+
+
+def test_buffered_footprint_and_argument_checks():
+    wt = _wt()
+    # one buffer: the ordinary build of a staged copy
+    rc, tb, wb = wt.wt_buffered_footprint(1000, 256, 1, 1 << 20)
+    rc2, tb2, wb2 = wt.wt_footprint(1000, 256, 1)
+    assert rc == rc2 == wt.WT_OK and tb == tb2 and wb >= wb2 + 1000
+    # several buffers: the tree is the plain one; the workspace holds the
+    # partial trees (at least the final bitmaps) and the (nbuf + 1) x (2^l + 1)
+    # offset table, and shrinks with the buffer as long as 2^l is small
+    n, sigma = 1 << 24, 256
+    rc, tb, wb_small = wt.wt_buffered_footprint(n, sigma, 1, 1 << 20)
+    _, tb2, wb_plain = wt.wt_footprint(n, sigma, 1)
+    assert rc == wt.WT_OK and tb == tb2
+    assert wb_small >= 16 * 257 * 8 + 8 * (n // 8) and wb_small < wb_plain + tb
+    _, _, wb_big = wt.wt_buffered_footprint(n, sigma, 1, 1 << 22)
+    assert wb_big > wb_small - 2 * (1 << 20)
+    d = wt.wt_desc(n, sigma, 1)
+    h = ctypes.c_void_p()
+    tbv, wbv = ctypes.c_uint64(), ctypes.c_uint64()
+    assert wt.lib().wt_buffered_footprint(ctypes.byref(d), 0, ctypes.byref(tbv), ctypes.byref(wbv)) == wt.WT_EINVAL
+    assert wt.lib().wt_buffered_footprint(ctypes.byref(d), 8, ctypes.byref(tbv), ctypes.byref(wbv)) == wt.WT_EINVAL
+    bad = wt.wt_desc(10, 0, 1)
+    assert wt.lib().wt_build_buffered(None, ctypes.byref(bad), 4, None, 0, None, 0, None, ctypes.byref(h)) == wt.WT_EINVAL
+    assert wt.lib().wt_build_buffered(None, ctypes.byref(d), 1 << 20, None, 0, None, 0, None, ctypes.byref(h)) == wt.WT_EINVAL
