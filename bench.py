@@ -117,6 +117,11 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--matrix", action="store_true",
                     help="build the wavelet matrix of the workload instead of the wavelet tree (c1-c3)")
+    ap.add_argument("--buffered", type=int, default=0, metavar="LG",
+                    help="buffered build of the workload (c1-c3) in buffers of 2^LG symbols, read from "
+                         "page-locked host memory (PCIe included in the step) or, with --buffered-source "
+                         "device, from HBM")
+    ap.add_argument("--buffered-source", default="host", choices=["host", "device"])
     ap.add_argument("--cpu-sample-lg", type=int, default=26)
     ap.add_argument("--cpu-runs", type=int, default=3)
     ap.add_argument("--input-cache", default="",
@@ -153,8 +158,18 @@ def main() -> int:
             os.makedirs(args.input_cache, exist_ok=True)
             np.save(os.path.join(args.input_cache, "%s.npy" % args.workload), S)
     n, width = S.shape[0], S.dtype.itemsize
-    dS = wtree.to_device(S, dev)
-    rc, tb, wb = wtree.wt_footprint(n, sigma, width)
+    if args.buffered and args.matrix:
+        print("bench.py: --buffered builds wavelet trees only", file=sys.stderr)
+        return 2
+    if args.buffered and args.buffered_source == "host":
+        view = {1: np.uint8, 2: np.int16, 4: np.int32}[width]
+        dS = torch.from_numpy(S.view(view)).pin_memory()
+    else:
+        dS = wtree.to_device(S, dev)
+    if args.buffered:
+        rc, tb, wb = wtree.wt_buffered_footprint(n, sigma, width, 1 << args.buffered)
+    else:
+        rc, tb, wb = wtree.wt_footprint(n, sigma, width)
     assert rc == wtree.WT_OK
     tree_mem = torch.empty(tb, dtype=torch.uint8, device=dev)
     work_mem = torch.empty(wb, dtype=torch.uint8, device=dev)
@@ -169,11 +184,15 @@ def main() -> int:
         del src, dst
 
     build_fn = wtree.wt_build_matrix if args.matrix else wtree.wt_build
+    if args.buffered:
+        def build_fn(S_ptr, n, sigma, width, t_ptr, tb, w_ptr, wb, sh):
+            return wtree.wt_build_buffered(S_ptr, n, sigma, width, 1 << args.buffered, t_ptr, tb, w_ptr, wb, sh)
+    fn_name = "wt_build_buffered" if args.buffered else ("wt_build_matrix" if args.matrix else "wt_build")
 
     def one_build():
         rc, h = build_fn(dS.data_ptr(), n, sigma, width, tree_mem.data_ptr(), tb, work_mem.data_ptr(), wb, sh)
         if rc != wtree.WT_OK:
-            raise wtree.WtError(rc, "wt_build_matrix" if args.matrix else "wt_build")
+            raise wtree.WtError(rc, fn_name)
         return h
 
     print("bench: warmup %d" % args.warmup, file=sys.stderr, flush=True)
@@ -228,7 +247,7 @@ def main() -> int:
         f["avg_us"] = round(f["ms"] * 1e3 / f["launches"], 2)
         f["ms_per_step"] = round(f["ms"] / args.steps, 4)
         del f["ms"]
-    traffic = None if args.matrix else load_traffic(args.workload)
+    traffic = None if (args.matrix or args.buffered) else load_traffic(args.workload)
     levels = max(0, (sigma - 1).bit_length())
     qmin = n * width + (tb - 256)  # read S once + write every bitmap word and rank entry once
     qmin_gbps = qmin / (p50 / 1e3) / 1e9
@@ -246,8 +265,12 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": {1: "u8", 2: "u16", 4: "u32"}[width],
         "data": "synthetic",
-        "config": {"workload": "%s: %s%s" % (args.workload, WORKLOADS[args.workload],
-                                             "; wavelet matrix" if args.matrix else ""), "n": n, "sigma": sigma,
+        "config": {"workload": "%s: %s%s%s" % (args.workload, WORKLOADS[args.workload],
+                                               "; wavelet matrix" if args.matrix else "",
+                                               ("; buffered build, 2^%d-symbol buffers from %s" % (
+                                                   args.buffered, "page-locked host memory (PCIe included)"
+                                                   if args.buffered_source == "host" else "HBM"))
+                                               if args.buffered else ""), "n": n, "sigma": sigma,
                    "width_bytes": width, "levels": levels, "seed": wtgen.SEED_BASE + int(args.workload[1]) - 1},
         "roofline": {
             "bound": "hbm",
@@ -264,6 +287,18 @@ def main() -> int:
         "compulsory_bytes": {"bytes": qmin, "gbps_at_p50": qmin_gbps, "frac_of_peak": qmin_gbps / HBM_PEAK_GBPS},
         "kernels": fams,
     }
+    if args.buffered:
+        mg = [r for r in recs if r["kernel"] == "merge"]
+        mg_ms = sum(r["ms"] for r in mg)
+        out["buffered"] = {
+            "buffer_syms": 1 << args.buffered,
+            "buffers": -(-n // (1 << args.buffered)),
+            "source": args.buffered_source,
+            "input_gbps": n * width / (ms_per_step / 1e3) / 1e9,
+            "merge_avg_us": mg_ms * 1e3 / max(1, len(mg)),
+            "merge_gbps": (sum(r["bytes"] for r in mg) / (mg_ms / 1e3) / 1e9) if mg_ms > 0 else None,
+            "workspace_bytes": wb,
+        }
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline on n=2^%d" % args.cpu_sample_lg, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_lg, args.cpu_runs, args.matrix)

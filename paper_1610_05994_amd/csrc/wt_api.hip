@@ -427,7 +427,7 @@ struct BufPlan {
     Layout L;          // the final tree
     Layout Lb, Llast;  // a full partial tree and the last (ragged) one
     uint64_t b, nbuf;
-    uint64_t stage_bytes, off_stage[2], off_pwork, off_ptrees, pstride, off_C, off_csum, row, wg_per_level;
+    uint64_t stage_bytes, off_stage[2], off_pwork, off_ptrees, pstride, off_C, off_csum, off_span, row, wg_per_level;
     uint64_t work_bytes;
 };
 
@@ -465,9 +465,11 @@ static int plan_buffered(const wt_desc *d, uint64_t b, BufPlan *P) {
     P->row = (1ull << l) + 1;
     P->off_C = off;
     off += round_up((P->nbuf + 1) * P->row * 8, 256);
-    P->wg_per_level = ceil_div(ceil_div(d->n, 512), 256);
+    P->wg_per_level = ceil_div(P->L.words, 1024);  // merge workgroups per level: 1024 words each
     P->off_csum = off;
     off += round_up((uint64_t)(l ? l : 1) * P->wg_per_level * 8, 256);
+    P->off_span = off;
+    off += round_up((uint64_t)(l ? l : 1) * (P->wg_per_level + 1) * 8, 256);
     P->work_bytes = off;
     return WT_OK;
 }
@@ -543,6 +545,7 @@ static hipError_t enqueue_buffered(const uint8_t *S, const BufPlan &P, uint8_t *
         a.ranks = reinterpret_cast<uint64_t *>(tree + P.L.tree_ranks_off);
         a.tree_status = reinterpret_cast<uint32_t *>(tree);
         a.csum = reinterpret_cast<unsigned long long *>(work + P.off_csum);
+        a.span_run = reinterpret_cast<uint64_t *>(work + P.off_span);
         a.n = P.L.n;
         a.words = P.L.words;
         a.rank_stride = P.L.rank_stride;

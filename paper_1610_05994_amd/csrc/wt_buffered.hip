@@ -19,11 +19,11 @@
 // and tile the level.
 //
 // The merge is written word by word rather than run by run: each thread owns
-// one 512-bit block of the output (one rank-directory entry), finds the run
-// holding its first bit by a galloping search over the run order, and ORs
-// shifted pieces of the partial bitmaps into its eight words.  Every word has
-// a single writer, so the boundary-word atomics of mergeBA are not needed,
-// and the popcounts of the block feed the rank directory in the same pass.
+// one 64-bit word of the output, finds the run holding its first bit (from
+// a per-span table of first runs), and ORs
+// shifted pieces of the partial bitmaps into it.  Every word has a single
+// writer, so the boundary-word atomics of mergeBA are not needed, and the
+// popcounts of the words feed the rank directory in the same pass.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -133,53 +133,212 @@ __device__ __forceinline__ uint64_t find_run(const MergeArgs &a, uint32_t k, uin
     return lo;
 }
 
-// One thread per 512-bit block of level blockIdx.y: its eight words from
-// the partial bitmaps, its local rank prefix, and the workgroup's ones.
-__global__ __launch_bounds__(kMT) void k_merge(MergeArgs a) {
-    __shared__ unsigned long long s_scan[kMT];
-    const uint32_t i = blockIdx.y, k = a.levels - i;
-    const uint64_t blk = (uint64_t)blockIdx.x * kMT + threadIdx.x;
-    const uint64_t R = (uint64_t)a.nbuf << i;
-    uint32_t ones = 0;
-    if (blk < a.nblk) {
-        uint64_t *out = a.bits + (uint64_t)i * a.words + blk * 8;
-        const uint64_t p0 = blk * 512;
-        const uint64_t pend = (p0 + 512 < a.n) ? p0 + 512 : a.n;
-        uint64_t r = find_run(a, k, R, 0, p0);
-        Run x = run_at(a, k, r);
-        for (int wi = 0; wi < 8; wi++) {
-            const uint64_t w0 = p0 + 64ull * wi;
-            const uint64_t wend = (w0 + 64 < pend) ? w0 + 64 : pend;
-            uint64_t word = 0, p = w0;
-            while (p < wend) {
-                if (x.d1 <= p) {  // the run is used up: the next non-empty one starts at p
-                    if (r + 1 >= R) break;  // inconsistent tables: leave the rest zero
-                    r = find_run(a, k, R, r + 1, p);
-                    x = run_at(a, k, r);
-                    if (x.d1 <= p || x.d0 > p) break;  // inconsistent tables: leave the rest zero
-                }
-                const uint64_t e = (x.d1 < wend) ? x.d1 : wend;
-                const uint32_t m = (uint32_t)(e - p);
-                const uint64_t s = x.src + (p - x.d0);
-                const uint64_t pw = (x.q + 1 == a.nbuf) ? a.pwords_last : a.pwords;
-                if (((s + m - 1) >> 6) >= pw) break;
-                const uint64_t *src = reinterpret_cast<const uint64_t *>(a.ptrees + (uint64_t)x.q * a.pstride +
-                                                                         a.pbits_off) + (uint64_t)i * pw;
-                const uint32_t sh = (uint32_t)(s & 63);
-                uint64_t val = src[s >> 6] >> sh;
-                if (sh + m > 64) val |= src[(s >> 6) + 1] << (64 - sh);
-                if (m < 64) val &= (1ull << m) - 1;
-                word |= val << (p - w0);
-                p = e;
-            }
-            out[wi] = word;
-            ones += (uint32_t)__popcll(word);
-        }
+// Words per merge thread.  A workgroup covers kMW = kMT * kWPT consecutive
+// words; thread t takes words t, t + kMT, ... so every load and store
+// instruction of a wave touches consecutive words.
+constexpr int kWPT = 4;
+constexpr uint64_t kMW = (uint64_t)kMT * kWPT;
+constexpr uint64_t kSpan = kMW * 64;  // positions per merge workgroup
+
+// Exclusive scan of one u64 per thread over the workgroup with wave
+// shuffles (one barrier pair).  s holds kMT / 64 entries.
+__device__ __forceinline__ unsigned long long block_excl_scan_w(unsigned long long x, unsigned long long *s,
+                                                                unsigned long long *total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    unsigned long long inc = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned long long y = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += y;
     }
-    unsigned long long total;
-    const unsigned long long before = block_excl_scan(ones, s_scan, &total);
-    if (blk < a.nblk) a.ranks[(uint64_t)i * a.rank_stride + blk] = before;
-    if (threadIdx.x == 0) a.csum[(uint64_t)i * a.wg_per_level + blockIdx.x] = total;
+    if (lane == 63) s[wv] = inc;
+    __syncthreads();
+    unsigned long long before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kMT / 64; w++) {
+        const unsigned long long v = s[w];
+        before += (w < wv) ? v : 0ull;
+        tot += v;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + inc - x;
+}
+
+// span_run[level][b] = the run holding position min(b * kSpan, n - 1), for b
+// in [0, spans]: the first run of span b, and (b + 1) an upper bound on its
+// last.  One thread per (level, span).
+__global__ __launch_bounds__(kMT) void k_span_runs(MergeArgs a) {
+    const uint32_t i = blockIdx.y, k = a.levels - i;
+    const uint64_t b = (uint64_t)blockIdx.x * kMT + threadIdx.x;
+    if (b > a.wg_per_level) return;
+    const uint64_t p = (b * kSpan < a.n) ? b * kSpan : a.n - 1;
+    a.span_run[(uint64_t)i * (a.wg_per_level + 1) + b] = find_run(a, k, (uint64_t)a.nbuf << i, 0, p);
+}
+
+// Source words of the piece of run x at position p, for positions [p, e).
+__device__ __forceinline__ const uint64_t *piece_src(const MergeArgs &a, uint32_t i, const Run &x, uint64_t p,
+                                                     uint64_t e, uint64_t *s_out, bool *ok) {
+    const uint64_t s = x.src + (p - x.d0);
+    const uint64_t pw = (x.q + 1 == a.nbuf) ? a.pwords_last : a.pwords;
+    *ok = ((s + (e - p) - 1) >> 6) < pw;
+    *s_out = s;
+    return reinterpret_cast<const uint64_t *>(a.ptrees + (uint64_t)x.q * a.pstride + a.pbits_off) + (uint64_t)i * pw;
+}
+
+__device__ __forceinline__ uint64_t piece_bits(uint64_t lo_w, uint64_t hi_w, uint64_t s, uint32_t m) {
+    const uint32_t sh = (uint32_t)(s & 63);
+    uint64_t val = lo_w >> sh;
+    if (sh + m > 64) val |= hi_w << (64 - sh);
+    if (m < 64) val &= (1ull << m) - 1;
+    return val;
+}
+
+// The pieces of word w0 (positions [w0, wend)) after the first one, which
+// ended at p, with next(p, x) -> the run holding p.
+template <class Next>
+__device__ __forceinline__ uint64_t gather_rest(const MergeArgs &a, uint32_t i, uint64_t w0, uint64_t wend,
+                                                uint64_t p, Run x, uint64_t word, Next next) {
+    while (p < wend) {
+        if (x.d1 <= p) {  // the run is used up: the next non-empty one starts at p
+            if (!next(p, x)) break;  // inconsistent tables: leave the rest zero
+        }
+        const uint64_t e = (x.d1 < wend) ? x.d1 : wend;
+        uint64_t s;
+        bool ok;
+        const uint64_t *src = piece_src(a, i, x, p, e, &s, &ok);
+        if (!ok) break;
+        const uint32_t m = (uint32_t)(e - p);
+        const uint64_t hi_w = ((s & 63) + m > 64) ? src[(s >> 6) + 1] : 0ull;
+        word |= piece_bits(src[s >> 6], hi_w, s, m) << (p - w0);
+        p = e;
+    }
+    return word;
+}
+
+// One merge workgroup: the kMW words of span blockIdx.x of level
+// blockIdx.y (kMW / 8 rank-directory blocks).  The runs the span touches
+// are [span_run[b], span_run[b + 1]]; when there are at most kMT of them
+// (almost always: runs are long unless the level has millions of nodes)
+// they are decoded once into LDS and every word finds its runs there, so
+// the offset table is read a few times per workgroup rather than several
+// times per word.  Otherwise each thread gallops over the run order from the
+// span's first run.  The loads of the first piece of all kWPT words of a
+// thread are issued before any is used.
+__global__ __launch_bounds__(kMT) void k_merge(MergeArgs a) {
+    __shared__ unsigned long long s_scan[kMT / 64];
+    __shared__ uint64_t s_d0[kMT], s_d1[kMT], s_src[kMT];
+    __shared__ uint32_t s_q[kMT];
+    const uint32_t i = blockIdx.y, k = a.levels - i;
+    const uint64_t R = (uint64_t)a.nbuf << i;
+    const uint64_t wbase = (uint64_t)blockIdx.x * kMW;
+    const uint64_t nw = ceil_div(a.n, 64);
+    const uint64_t *sr = a.span_run + (uint64_t)i * (a.wg_per_level + 1) + blockIdx.x;
+    const uint64_t lo = sr[0], hi = sr[1];
+    const bool in_lds = hi - lo < (uint64_t)kMT;  // workgroup-uniform
+    if (in_lds) {
+        if (threadIdx.x <= hi - lo) {
+            const Run x = run_at(a, k, lo + threadIdx.x);
+            s_d0[threadIdx.x] = x.d0;
+            s_d1[threadIdx.x] = x.d1;
+            s_src[threadIdx.x] = x.src;
+            s_q[threadIdx.x] = x.q;
+        }
+        __syncthreads();
+    }
+    const uint32_t nr = (uint32_t)(hi - lo + 1);
+    uint64_t words[kWPT];
+    uint32_t jj[kWPT];
+    uint64_t rr[kWPT];
+    Run xs[kWPT];
+    uint64_t lo_w[kWPT], hi_w[kWPT], ss[kWPT], ee[kWPT];
+    // first piece of every word: locate, then load
+#pragma unroll
+    for (int u = 0; u < kWPT; u++) {
+        const uint64_t wi = wbase + (uint64_t)u * kMT + threadIdx.x;
+        const uint64_t w0 = wi * 64;
+        const uint64_t wend = (w0 + 64 < a.n) ? w0 + 64 : a.n;
+        words[u] = 0;
+        ee[u] = w0;  // no piece
+        lo_w[u] = hi_w[u] = 0;
+        ss[u] = 0;
+        if (wi >= nw) continue;
+        Run x;
+        if (in_lds) {
+            uint32_t j = 0, top = nr;  // last j with s_d0[j] <= w0 (s_d0[0] <= w0)
+            while (top - j > 1) {
+                const uint32_t mid = (j + top) / 2;
+                if (s_d0[mid] <= w0) j = mid;
+                else top = mid;
+            }
+            jj[u] = j;
+            x.d0 = s_d0[j];
+            x.d1 = s_d1[j];
+            x.src = s_src[j];
+            x.q = s_q[j];
+        } else {
+            rr[u] = find_run(a, k, R, lo, w0);
+            x = run_at(a, k, rr[u]);
+        }
+        xs[u] = x;
+        if (x.d1 <= w0 || x.d0 > w0) continue;  // inconsistent tables: leave the word zero
+        const uint64_t e = (x.d1 < wend) ? x.d1 : wend;
+        bool ok;
+        const uint64_t *src = piece_src(a, i, x, w0, e, &ss[u], &ok);
+        if (!ok) continue;
+        ee[u] = e;
+        lo_w[u] = src[ss[u] >> 6];
+        if ((ss[u] & 63) + (e - w0) > 64) hi_w[u] = src[(ss[u] >> 6) + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kWPT; u++) {
+        const uint64_t wi = wbase + (uint64_t)u * kMT + threadIdx.x;
+        const uint64_t w0 = wi * 64;
+        const uint64_t wend = (w0 + 64 < a.n) ? w0 + 64 : a.n;
+        uint64_t word = 0;
+        if (wi < nw && ee[u] > w0) {
+            word = piece_bits(lo_w[u], hi_w[u], ss[u], (uint32_t)(ee[u] - w0));
+            if (ee[u] < wend) {  // more runs inside this word
+                if (in_lds) {
+                    uint32_t j = jj[u];
+                    word = gather_rest(a, i, w0, wend, ee[u], xs[u], word, [&](uint64_t p, Run &y) {
+                        while (j + 1 < nr && s_d1[j] <= p) j++;
+                        if (s_d1[j] <= p || s_d0[j] > p) return false;
+                        y.d0 = s_d0[j];
+                        y.d1 = s_d1[j];
+                        y.src = s_src[j];
+                        y.q = s_q[j];
+                        return true;
+                    });
+                } else {
+                    uint64_t r = rr[u];
+                    word = gather_rest(a, i, w0, wend, ee[u], xs[u], word, [&](uint64_t p, Run &y) {
+                        if (r + 1 >= R) return false;
+                        r = find_run(a, k, R, r + 1, p);
+                        y = run_at(a, k, r);
+                        return !(y.d1 <= p || y.d0 > p);
+                    });
+                }
+            }
+        }
+        // words from nw up to the level's padded end are zero
+        if (wi < a.words) a.bits[(uint64_t)i * a.words + wi] = word;
+        words[u] = word;
+    }
+    // rank directory: block blk = wi / 8 holds words of one u (kMT is a
+    // multiple of 8); its local prefix is the ones of every earlier word of
+    // the span
+    unsigned long long carry = 0;
+#pragma unroll
+    for (int u = 0; u < kWPT; u++) {
+        const uint64_t wi = wbase + (uint64_t)u * kMT + threadIdx.x;
+        unsigned long long sub_total;
+        const unsigned long long before = block_excl_scan_w((unsigned long long)__popcll(words[u]), s_scan, &sub_total);
+        const uint64_t blk = wi >> 3;
+        if ((wi & 7) == 0 && blk < a.nblk) a.ranks[(uint64_t)i * a.rank_stride + blk] = carry + before;
+        carry += sub_total;
+    }
+    if (threadIdx.x == 0) a.csum[(uint64_t)i * a.wg_per_level + blockIdx.x] = carry;
 }
 
 // One workgroup per level: exclusive scan of the workgroup ones in place,
@@ -210,11 +369,13 @@ __global__ __launch_bounds__(kMT) void k_rank_fix(MergeArgs a) {
     for (uint64_t t = a.nblk + threadIdx.x; t < a.rank_stride; t += kMT) R[t] = (t == a.nblk) ? total : 0ull;
 }
 
-// Adds each workgroup's base to the local rank prefixes of its blocks.
+// Adds each merge workgroup's base (kMW / 8 blocks each) to the local rank
+// prefixes of its blocks.
 __global__ __launch_bounds__(kMT) void k_rank_apply(MergeArgs a) {
     const uint32_t i = blockIdx.y;
     const uint64_t blk = (uint64_t)blockIdx.x * kMT + threadIdx.x;
-    if (blk < a.nblk) a.ranks[(uint64_t)i * a.rank_stride + blk] += a.csum[(uint64_t)i * a.wg_per_level + blockIdx.x];
+    if (blk < a.nblk)
+        a.ranks[(uint64_t)i * a.rank_stride + blk] += a.csum[(uint64_t)i * a.wg_per_level + blk / (kMW / 8)];
 }
 
 }  // namespace
@@ -233,13 +394,16 @@ hipError_t launch_merge(const MergeArgs &a, hipStream_t s) {
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (a.levels) {
+        hipLaunchKernelGGL(k_span_runs, dim3((unsigned)ceil_div(a.wg_per_level + 1, kMT), a.levels), dim3(kMT), 0, s,
+                           a);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
         hipLaunchKernelGGL(k_merge, dim3((unsigned)a.wg_per_level, a.levels), dim3(kMT), 0, s, a);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
     hipLaunchKernelGGL(k_rank_fix, dim3(a.levels ? a.levels : 1u), dim3(kMT), 0, s, a);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     if (a.levels) {
-        hipLaunchKernelGGL(k_rank_apply, dim3((unsigned)a.wg_per_level, a.levels), dim3(kMT), 0, s, a);
+        hipLaunchKernelGGL(k_rank_apply, dim3((unsigned)ceil_div(a.nblk, kMT), a.levels), dim3(kMT), 0, s, a);
         err = hipGetLastError();
     }
     return err;

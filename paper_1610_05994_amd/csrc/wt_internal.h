@@ -222,6 +222,7 @@ struct MergeArgs {
     uint64_t *ranks;                 // final rank directories, `rank_stride` per level
     uint32_t *tree_status;           // final status word
     unsigned long long *csum;        // per level, wg_per_level workgroup sums
+    uint64_t *span_run;              // per level, wg_per_level + 1 first runs of the merge spans
     uint64_t n, words, rank_stride, nblk, wg_per_level, row;
     uint32_t levels, nbuf;
 };
