@@ -997,12 +997,19 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         else stage_split<W, B, false>(s_stage, raw, mb, zc, oc, nval);
         wave_sync();
         // Write the two runs out (zeros at slots [a0, a0+Z) -> g0.., ones at
-        // [a1, a1+O) -> g1..), one 16-byte chunk per lane and step; the slot
-        // and destination phases agree, so chunks are aligned in both.  A run
-        // holds at most TILE symbols, so it touches at most two consecutive
-        // destination tiles: next-level ones are counted per (run, tile).
+        // [a1, a1+O) -> g1..); the slot and destination phases agree, so
+        // chunks are aligned in both.  Chunks wholly inside a run leave as
+        // one 16-byte store per lane and step; the at most two partial
+        // chunks of each run (its first and last) are written afterwards,
+        // one symbol per lane (4 x CH <= 64 lanes), so no lane runs a
+        // per-symbol loop while the others wait.  A run holds at most TILE
+        // symbols, so it touches at most two consecutive destination tiles:
+        // next-level ones are counted per (run, tile).
         const uint32_t lowbits = (W == 1) ? 0x01010101u : (W == 2) ? 0x00010001u : 1u;
         const uint32_t mk = counting ? lowbits << sh2 : 0u;  // next-level bit of every symbol
+        uint32_t cnt[4] = {0u, 0u, 0u, 0u};                   // (run, destination-tile parity)
+        uint32_t lo_r[2], len_r[2], edge_r[2][2];
+        uint64_t gb_r[2], dt0_r[2], cs_r[2];
 #pragma unroll
         for (int r = 0; r < 2; r++) {
             const uint32_t lo = r ? a1 : a0;
@@ -1012,36 +1019,49 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
             const uint32_t fb = (lo + CH - 1) / CH, fe = (lo + len) / CH;  // chunks inside the run
             const uint64_t dt0 = (gb + (uint64_t)cb * CH) / TILE;
             const uint64_t cs = ((dt0 + 1) * TILE - gb) / CH;  // first chunk in tile dt0 + 1
-            uint32_t cnt0 = 0, cnt1 = 0;
-            for (uint32_t c = cb + lane; c < ce; c += 64) {
+            lo_r[r] = lo;
+            len_r[r] = len;
+            gb_r[r] = gb;
+            dt0_r[r] = dt0;
+            cs_r[r] = cs;
+            // partial chunks (0xffffffff: none): the first when the run starts
+            // inside it, the last when the run ends inside it (once, if the two
+            // are the same chunk)
+            edge_r[r][0] = (cb < ce && cb < fb) ? cb : 0xffffffffu;
+            edge_r[r][1] = (cb < ce && fe < ce && ce - 1 != edge_r[r][0]) ? ce - 1 : 0xffffffffu;
+            for (uint32_t c = fb + lane; c < fe; c += 64) {  // whole chunks [fb, fe)
                 const uint32_t s = c * CH;
                 const uint4 v = *reinterpret_cast<const uint4 *>(&s_stage[s]);
-                uint32_t ones = 0;
                 // (destinations beyond n only arise from inconsistent tables;
                 // they are dropped rather than written)
-                if (c >= fb && c < fe && gb + s + CH <= a.n) {
+                if (gb + s + CH <= a.n) {
                     *reinterpret_cast<uint4 *>(tout + (gb + s)) = v;
-                    ones = __popc(v.x & mk) + __popc(v.y & mk) + __popc(v.z & mk) + __popc(v.w & mk);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < CH; e++) {
-                        if (s + e >= lo && s + e < lo + len && gb + s + e < a.n) {
-                            const uint32_t x = chunk_elem<W>(v, e);
-                            tout[gb + s + e] = (T)x;
-                            ones += (x >> sh2) & 1u;
-                        }
-                    }
+                    const uint32_t ones = __popc(v.x & mk) + __popc(v.y & mk) + __popc(v.z & mk) + __popc(v.w & mk);
+                    cnt[2 * r + (c < cs ? 0 : 1)] += ones;
                 }
-                if (c < cs) cnt0 += ones;
-                else cnt1 += ones;
             }
-            if (counting) {
-                const uint32_t t0 = wave_sum32(cnt0), t1 = wave_sum32(cnt1);
+        }
+        {
+            // lane -> (run, which partial chunk, symbol): 16 lanes per chunk
+            const int r = lane >> 5, which = (lane >> 4) & 1, e = lane & 15;
+            const uint32_t c = edge_r[r][which];
+            if (e < CH && c != 0xffffffffu) {
+                const uint32_t s = c * CH + (uint32_t)e;
+                const uint64_t d = gb_r[r] + s;
+                if (s >= lo_r[r] && s < lo_r[r] + len_r[r] && d < a.n) {
+                    const uint32_t x = (uint32_t)s_stage[s];
+                    tout[d] = (T)x;
+                    if (counting) cnt[2 * r + (c < cs_r[r] ? 0 : 1)] += (x >> sh2) & 1u;
+                }
+            }
+        }
+        if (counting) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const uint32_t tq = wave_sum32(cnt[q]);
                 if (lane == 0) {
-                    rec->dt[2 * r] = (uint32_t)dt0;
-                    rec->cnt[2 * r] = t0;
-                    rec->dt[2 * r + 1] = (uint32_t)dt0 + 1;
-                    rec->cnt[2 * r + 1] = t1;
+                    rec->dt[q] = (uint32_t)dt0_r[q >> 1] + (uint32_t)(q & 1);
+                    rec->cnt[q] = tq;
                 }
             }
         }
