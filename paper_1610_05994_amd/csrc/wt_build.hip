@@ -1037,22 +1037,38 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
                 if (gb + s + CH <= a.n) {
                     *reinterpret_cast<uint4 *>(tout + (gb + s)) = v;
                     const uint32_t ones = __popc(v.x & mk) + __popc(v.y & mk) + __popc(v.z & mk) + __popc(v.w & mk);
-                    cnt[2 * r + (c < cs ? 0 : 1)] += ones;
+                    const bool second = c >= cs;
+                    cnt[2 * r] += second ? 0u : ones;
+                    cnt[2 * r + 1] += second ? ones : 0u;
                 }
             }
         }
         {
-            // lane -> (run, which partial chunk, symbol): 16 lanes per chunk
-            const int r = lane >> 5, which = (lane >> 4) & 1, e = lane & 15;
-            const uint32_t c = edge_r[r][which];
+            // lane -> (run, which partial chunk, symbol): 16 lanes per chunk.
+            // Plain selects between the two runs' values (a lane-indexed
+            // private array would live in scratch memory).
+            const bool r1 = lane >= 32, which = (lane >> 4) & 1;
+            const int e = lane & 15;
+            const uint32_t c = r1 ? (which ? edge_r[1][1] : edge_r[1][0]) : (which ? edge_r[0][1] : edge_r[0][0]);
+            const uint32_t lo = r1 ? lo_r[1] : lo_r[0], len = r1 ? len_r[1] : len_r[0];
+            const uint64_t gb = r1 ? gb_r[1] : gb_r[0], cs = r1 ? cs_r[1] : cs_r[0];
+            uint32_t one = 0;
+            bool second = false;
             if (e < CH && c != 0xffffffffu) {
                 const uint32_t s = c * CH + (uint32_t)e;
-                const uint64_t d = gb_r[r] + s;
-                if (s >= lo_r[r] && s < lo_r[r] + len_r[r] && d < a.n) {
+                const uint64_t d = gb + s;
+                if (s >= lo && s < lo + len && d < a.n) {
                     const uint32_t x = (uint32_t)s_stage[s];
                     tout[d] = (T)x;
-                    if (counting) cnt[2 * r + (c < cs_r[r] ? 0 : 1)] += (x >> sh2) & 1u;
+                    one = (x >> sh2) & 1u;
+                    second = c >= cs;
                 }
+            }
+            if (counting) {
+                cnt[0] += (!r1 && !second) ? one : 0u;
+                cnt[1] += (!r1 && second) ? one : 0u;
+                cnt[2] += (r1 && !second) ? one : 0u;
+                cnt[3] += (r1 && second) ? one : 0u;
             }
         }
         if (counting) {
