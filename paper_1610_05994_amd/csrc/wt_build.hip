@@ -644,7 +644,18 @@ __device__ __forceinline__ void stage_multi(const LevelArgs &a, const uint4 (&ra
         }
     }
     wave_sync();
-    // write the runs out, one 16-byte staging block per lane and step
+    // write the runs out, one 16-byte staging block per lane and step: first
+    // every block lying wholly inside its run, then the partial first / last
+    // blocks of the runs, one per lane (nruns < 32), so that no per-symbol
+    // loop runs under divergence in the block loop
+    auto add_ones = [&](uint32_t run, unsigned long long gfirst, uint32_t ones) {
+        if (counting && ones) {
+            const uint64_t dt = gfirst / TILE;  // a block's symbols share one destination tile
+            const uint32_t key = 2 * run + (uint32_t)(dt & 1);
+            atomicAdd(&tb->cnt[key], ones);
+            tb->tix[key] = (uint32_t)dt;
+        }
+    };
     const uint32_t nblk = tb->blk[nruns];
     for (uint32_t blk = (uint32_t)lane; blk < nblk; blk += 64) {
         uint32_t lo = 0, hi = nruns - 1;  // last run whose first block is <= blk
@@ -657,30 +668,35 @@ __device__ __forceinline__ void stage_multi(const LevelArgs &a, const uint4 (&ra
         const unsigned long long g = tb->g[lo];
         const uint32_t s = blk * CH;
         if (s + CH > kStage) continue;  // (only with inconsistent tables)
+        if (!(s >= st && s + CH <= st + len && g + (s - st) + CH <= a.n)) continue;  // partial: below
         const uint4 v = *reinterpret_cast<const uint4 *>(&s_stage[s]);
-        uint32_t ones = 0;
-        unsigned long long gfirst;
-        if (s >= st && s + CH <= st + len && g + (s - st) + CH <= a.n) {
-            gfirst = g + (s - st);
-            *reinterpret_cast<uint4 *>(tout + gfirst) = v;
-            if (counting) ones = chunk_bit_count<W>(v, sh2);
-        } else {
-            gfirst = g + ((s > st ? s : st) - st);
+        const unsigned long long gfirst = g + (s - st);
+        *reinterpret_cast<uint4 *>(tout + gfirst) = v;
+        add_ones(lo, gfirst, counting ? chunk_bit_count<W>(v, sh2) : 0u);
+    }
+    {
+        const uint32_t run = (uint32_t)lane >> 1;
+        if (run < nruns) {
+            const uint32_t st = tb->st[run], len = tb->len[run];
+            const unsigned long long g = tb->g[run];
+            const uint32_t bfirst = tb->blk[run], bend = tb->blk[run + 1];
+            const uint32_t blk = (lane & 1) ? bend - 1 : bfirst;
+            const uint32_t s = blk * CH;
+            const bool take = len > 0 && bend > bfirst && !((lane & 1) && bend - 1 == bfirst) && s + CH <= kStage;
+            if (take && !(s >= st && s + CH <= st + len && g + (s - st) + CH <= a.n)) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(&s_stage[s]);
+                uint32_t ones = 0;
 #pragma unroll
-            for (int e = 0; e < (int)CH; e++) {
-                const uint32_t q = s + e;
-                if (q >= st && q < st + len && g + (q - st) < a.n) {
-                    const uint32_t x = chunk_elem<W>(v, e);
-                    tout[g + (q - st)] = (T)x;
-                    ones += (x >> sh2) & 1u;
+                for (int e = 0; e < (int)CH; e++) {
+                    const uint32_t q = s + e;
+                    if (q >= st && q < st + len && g + (q - st) < a.n) {
+                        const uint32_t x = chunk_elem<W>(v, e);
+                        tout[g + (q - st)] = (T)x;
+                        ones += (x >> sh2) & 1u;
+                    }
                 }
+                add_ones(run, g + ((s > st ? s : st) - st), ones);
             }
-        }
-        if (counting && ones) {
-            const uint64_t dt = gfirst / TILE;  // a block's symbols share one destination tile
-            const uint32_t key = 2 * lo + (uint32_t)(dt & 1);
-            atomicAdd(&tb->cnt[key], ones);
-            tb->tix[key] = (uint32_t)dt;
         }
     }
     if (!counting) return;
@@ -845,18 +861,23 @@ __device__ __forceinline__ void split_dense(const LevelArgs &a, const uint4 (&ra
     }
     flush();
     wave_sync();
-    // the interior block, aligned chunks (tile positions and destinations agree)
-    for (uint32_t c = ia_u / CH + lane; c * CH < ib_u; c += 64) {
-        const uint32_t s0 = c * CH;
-        const uint4 v4 = *reinterpret_cast<const uint4 *>(&s_stage[s0]);
-        if (s0 >= ia_u && s0 + CH <= ib_u && base + s0 + CH <= a.n) {
-            *reinterpret_cast<uint4 *>(tout + (base + s0)) = v4;
-        } else {
-#pragma unroll
-            for (int e = 0; e < (int)CH; e++) {
-                const uint32_t q = s0 + e;
-                if (q >= ia_u && q < ib_u && base + q < a.n) tout[base + q] = (T)chunk_elem<W>(v4, e);
-            }
+    // the interior block [ia_u, ib_u): whole aligned chunks (tile positions
+    // and destinations agree), then the at most 2 (CH - 1) symbols of its
+    // partial first and last chunk, one per lane
+    {
+        const uint32_t ca = (ia_u + CH - 1) / CH, cb = ib_u / CH;  // whole chunks [ca, cb)
+        for (uint32_t c = ca + lane; c < cb; c += 64) {
+            const uint32_t s0 = c * CH;
+            if (base + s0 + CH <= a.n)
+                *reinterpret_cast<uint4 *>(tout + (base + s0)) = *reinterpret_cast<const uint4 *>(&s_stage[s0]);
+        }
+        if (ia_u < ib_u) {
+            // head [ia_u, min(ca CH, ib_u)) on lanes 0..CH-2, tail [max(cb CH, ca CH), ib_u) on lanes 32..
+            const uint32_t he = (ca * CH < ib_u) ? ca * CH : ib_u;
+            const uint32_t tb0 = (cb * CH > ca * CH) ? cb * CH : ((ca * CH < ib_u) ? ca * CH : ib_u);
+            const uint32_t q = (lane < 32) ? ia_u + (uint32_t)lane : tb0 + (uint32_t)(lane - 32);
+            const uint32_t qe = (lane < 32) ? he : ib_u;
+            if (q < qe && base + q < a.n) tout[base + q] = s_stage[q];
         }
     }
     if (!counting) return;
