@@ -68,6 +68,18 @@ def lib():
         L.wto_matrix_rank.restype = ctypes.c_int
         L.wto_matrix_select.argtypes = [vp, vp, u64, u32, u32, u64, vp]
         L.wto_matrix_select.restype = ctypes.c_int
+        L.wto_levels4.argtypes = [u32]
+        L.wto_levels4.restype = u32
+        L.wto_words4.argtypes = [u64]
+        L.wto_words4.restype = u64
+        L.wto_build4.argtypes = [vp, u64, u32, u32, vp, vp]
+        L.wto_build4.restype = ctypes.c_int
+        L.wto_access4.argtypes = [vp, u64, u32, u64, vp]
+        L.wto_access4.restype = ctypes.c_int
+        L.wto_rank4.argtypes = [vp, u64, u32, u32, u64, vp]
+        L.wto_rank4.restype = ctypes.c_int
+        L.wto_select4.argtypes = [vp, u64, u32, u32, u64, vp]
+        L.wto_select4.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -212,4 +224,65 @@ def matrix_select(t: OracleMatrix, c: int, j: int):
         return None
     if rc != OK:
         raise ValueError("matrix select status %d" % rc)
+    return int(out.value)
+
+
+# ------------------------------------------------------- 4-ary tree ---
+
+def levels4(sigma: int) -> int:
+    """Levels of the 4-ary tree: ceil(ceil(lg sigma) / 2)."""
+    return int(lib().wto_levels4(sigma))
+
+
+def words4(n: int) -> int:
+    """64-bit words per 4-ary level (32 two-bit digits each, padded to 8)."""
+    return int(lib().wto_words4(n))
+
+
+@dataclass
+class OracleTree4:
+    n: int
+    sigma: int
+    levels: int
+    digits: np.ndarray          # (levels, words4(n)) uint64, 2-bit digits
+    dir: np.ndarray | None      # (levels, rank_stride(n), 4) uint64 counts of digits 0..3
+
+
+def build4(S: np.ndarray, sigma: int, with_dir: bool = True) -> OracleTree4:
+    """Sequential 4-ary wavelet-tree construction (pwt with four-way nodes)."""
+    S = np.ascontiguousarray(S)
+    width = S.dtype.itemsize
+    n = int(S.shape[0])
+    lv = levels4(sigma)
+    D = np.zeros((lv, words4(n)), dtype=np.uint64)
+    R = np.zeros((lv, rank_stride(n), 4), dtype=np.uint64) if with_dir else None
+    rc = lib().wto_build4(_ptr(S), n, sigma, width, _ptr(D), _ptr(R) if R is not None else None)
+    if rc != OK:
+        raise ValueError("oracle wto_build4 status %d" % rc)
+    return OracleTree4(n, sigma, lv, D, R)
+
+
+def access4(t: OracleTree4, i: int) -> int:
+    sym = ctypes.c_uint32()
+    rc = lib().wto_access4(_ptr(t.digits), t.n, t.sigma, i, ctypes.byref(sym))
+    if rc != OK:
+        raise ValueError("access4 status %d" % rc)
+    return int(sym.value)
+
+
+def rank4(t: OracleTree4, c: int, i: int) -> int:
+    out = ctypes.c_uint64()
+    rc = lib().wto_rank4(_ptr(t.digits), t.n, t.sigma, c, i, ctypes.byref(out))
+    if rc != OK:
+        raise ValueError("rank4 status %d" % rc)
+    return int(out.value)
+
+
+def select4(t: OracleTree4, c: int, j: int):
+    out = ctypes.c_uint64()
+    rc = lib().wto_select4(_ptr(t.digits), t.n, t.sigma, c, j, ctypes.byref(out))
+    if rc == ENOTFOUND:
+        return None
+    if rc != OK:
+        raise ValueError("select4 status %d" % rc)
     return int(out.value)

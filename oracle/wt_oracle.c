@@ -423,3 +423,177 @@ int wto_matrix_select(const uint64_t *B, const uint64_t *Z, uint64_t n, uint32_t
     *out = p;
     return WTO_OK;
 }
+
+/* ------------------------------------------------------- 4-ary tree ---- */
+/*
+ * Multiary wavelet tree of fan-out 4 (Section 5 names multiary trees, where
+ * a node has more than two children, as future work; this is the plain
+ * generalisation of the one-pointer-per-level representation).  With
+ * l = ceil(lg sigma), symbols are read as codes of L4 = ceil(l / 2) base-4
+ * digits (one zero bit on top when l is odd).  Level i lists, node after
+ * node in order, digit i of every symbol (bits 2(L4-1-i) + 1 .. 2(L4-1-i));
+ * the node of s at level i is s >> 2(L4-i), and the symbols of a node keep
+ * their input order.  The construction is Algorithm pwt with four-way nodes,
+ * run sequentially: count the symbols of every node, take the exclusive
+ * prefix sum of the counts, then sweep S in order writing each symbol's
+ * digit at its node's running offset.
+ *
+ * Conventions (as for the binary tree, unpinned by the paper): digit p of a
+ * level sits in 64-bit word p / 32 at bits 2 (p % 32) and 2 (p % 32) + 1;
+ * each level owns round_up(ceil(n / 32), 8) words and every digit at a
+ * position >= n is 0.  The directory of a level holds K = ceil(n/512) + 1
+ * entries of four counts, entry k giving the number of digits 0, 1, 2, 3 in
+ * positions [0, min(512k, n)), in a slot of round_up(K, 8) entries whose
+ * padding entries are zero.
+ */
+uint32_t wto_levels4(uint32_t sigma) { return (wto_levels(sigma) + 1) / 2; }
+uint64_t wto_words4(uint64_t n) { return round_up((n + 31) / 32, 8); }
+
+static uint32_t get_digit(const uint64_t *D, uint64_t p) { return (uint32_t)((D[p >> 5] >> (2 * (p & 31))) & 3u); }
+
+int wto_build4(const void *S, uint64_t n, uint32_t sigma, uint32_t width, uint64_t *D, uint64_t *R)
+{
+    if (sigma == 0 || (width != 1 && width != 2 && width != 4)) return WTO_EINVAL;
+    if (width < 4 && (uint64_t)sigma > (1ull << (8 * width))) return WTO_EINVAL;
+    for (uint64_t j = 0; j < n; j++)
+        if (sym_at(S, width, j) >= sigma) return WTO_ERANGE;
+
+    uint32_t L4 = wto_levels4(sigma);
+    uint64_t W = wto_words4(n);
+    uint64_t K = wto_rank_entries(n), KS = wto_rank_stride(n);
+    uint64_t maxnodes = L4 ? (1ull << (2 * (L4 - 1))) : 1;
+    uint64_t *C = (uint64_t *)malloc(maxnodes * sizeof(uint64_t));
+    if (!C) return WTO_ENOMEM;
+    for (uint32_t i = 0; i < L4; i++) {
+        uint64_t nodes = 1ull << (2 * i);
+        uint32_t shift = 2 * (L4 - i);     /* node of s at level i */
+        uint64_t *Di = D + (uint64_t)i * W;
+        memset(C, 0, nodes * sizeof(uint64_t));
+        for (uint64_t j = 0; j < n; j++) C[sym_at(S, width, j) >> shift]++;
+        uint64_t acc = 0;
+        for (uint64_t v = 0; v < nodes; v++) {
+            uint64_t c = C[v];
+            C[v] = acc;
+            acc += c;
+        }
+        memset(Di, 0, W * sizeof(uint64_t));
+        for (uint64_t j = 0; j < n; j++) {
+            uint64_t s = sym_at(S, width, j);
+            uint64_t v = s >> shift;
+            uint64_t d = (s >> (shift - 2)) & 3u;
+            uint64_t pos = C[v];
+            Di[pos >> 5] |= d << (2 * (pos & 31));
+            C[v]++;
+        }
+        if (R) {
+            uint64_t *Ri = R + (uint64_t)i * KS * 4;
+            memset(Ri, 0, KS * 4 * sizeof(uint64_t));
+            uint64_t cnt[4] = {0, 0, 0, 0};
+            for (uint64_t p = 0; p < n; p++) {
+                if ((p & 511) == 0)
+                    for (int d = 0; d < 4; d++) Ri[(p >> 9) * 4 + d] = cnt[d];
+                cnt[get_digit(Di, p)]++;
+            }
+            for (int d = 0; d < 4; d++) Ri[(K - 1) * 4 + d] = cnt[d];
+        }
+    }
+    free(C);
+    return WTO_OK;
+}
+
+/* digits equal to d in positions [a, b) of one level, counted one by one */
+static uint64_t digits_in(const uint64_t *Di, uint64_t a, uint64_t b, uint32_t d)
+{
+    uint64_t c = 0;
+    for (uint64_t p = a; p < b; p++) c += get_digit(Di, p) == d;
+    return c;
+}
+
+/*
+ * Queries walk the levels: the current node is a range [b, e) of the level;
+ * its child of digit d occupies, at the next level, the part of [b, e)
+ * after the digits smaller than d of [b, e), as long as the digits equal to
+ * d of [b, e).
+ */
+int wto_access4(const uint64_t *D, uint64_t n, uint32_t sigma, uint64_t i, uint32_t *sym)
+{
+    if (i >= n) return WTO_EINVAL;
+    uint32_t L4 = wto_levels4(sigma);
+    uint64_t W = wto_words4(n);
+    uint64_t b = 0, e = n, p = i;
+    uint32_t s = 0;
+    for (uint32_t k = 0; k < L4; k++) {
+        const uint64_t *Dk = D + (uint64_t)k * W;
+        uint32_t d = get_digit(Dk, p);
+        uint64_t below = 0;
+        for (uint32_t x = 0; x < d; x++) below += digits_in(Dk, b, e, x);
+        uint64_t nb = b + below;
+        uint64_t ne = nb + digits_in(Dk, b, e, d);
+        p = nb + digits_in(Dk, b, p, d);
+        b = nb;
+        e = ne;
+        s = (s << 2) | d;
+    }
+    *sym = s;
+    return WTO_OK;
+}
+
+int wto_rank4(const uint64_t *D, uint64_t n, uint32_t sigma, uint32_t c, uint64_t i, uint64_t *out)
+{
+    if (c >= sigma || i > n) return WTO_EINVAL;
+    uint32_t L4 = wto_levels4(sigma);
+    uint64_t W = wto_words4(n);
+    uint64_t b = 0, e = n, p = i;
+    for (uint32_t k = 0; k < L4; k++) {
+        const uint64_t *Dk = D + (uint64_t)k * W;
+        uint32_t d = (c >> (2 * (L4 - 1 - k))) & 3u;
+        uint64_t below = 0;
+        for (uint32_t x = 0; x < d; x++) below += digits_in(Dk, b, e, x);
+        uint64_t nb = b + below;
+        uint64_t ne = nb + digits_in(Dk, b, e, d);
+        p = nb + digits_in(Dk, b, p, d);
+        b = nb;
+        e = ne;
+    }
+    *out = p - b;
+    return WTO_OK;
+}
+
+int wto_select4(const uint64_t *D, uint64_t n, uint32_t sigma, uint32_t c, uint64_t j, uint64_t *out)
+{
+    if (c >= sigma) return WTO_EINVAL;
+    uint32_t L4 = wto_levels4(sigma);
+    uint64_t W = wto_words4(n);
+    uint64_t bs[32];
+    uint64_t b = 0, e = n;
+    for (uint32_t k = 0; k < L4; k++) {
+        const uint64_t *Dk = D + (uint64_t)k * W;
+        uint32_t d = (c >> (2 * (L4 - 1 - k))) & 3u;
+        bs[k] = b;
+        uint64_t below = 0;
+        for (uint32_t x = 0; x < d; x++) below += digits_in(Dk, b, e, x);
+        uint64_t nb = b + below;
+        e = nb + digits_in(Dk, b, e, d);
+        b = nb;
+    }
+    if (j == 0 || j > e - b) return WTO_ENOTFOUND;
+    uint64_t p = b + j - 1;   /* position inside the leaf range */
+    uint64_t child = b;
+    for (uint32_t k = L4; k-- > 0;) {
+        const uint64_t *Dk = D + (uint64_t)k * W;
+        uint32_t d = (c >> (2 * (L4 - 1 - k))) & 3u;
+        uint64_t t = p - child;   /* the wanted digit's rank inside the node */
+        uint64_t seen = 0, q;
+        for (q = bs[k]; q < n; q++) {
+            if (get_digit(Dk, q) == d) {
+                if (seen == t) break;
+                seen++;
+            }
+        }
+        p = q;
+        /* the node of level k starts at bs[k]; its parent node starts at bs[k-1] */
+        child = bs[k];
+    }
+    *out = p;
+    return WTO_OK;
+}
