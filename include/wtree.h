@@ -114,6 +114,33 @@ int wt_build_matrix(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t
 int wt_matrix_zeros(const wt_tree *tree, uint64_t *zeros);
 
 /*
+ * 4-ary wavelet tree of S (multiary trees, whose nodes have more than two
+ * children, are future work in Section 5; this is the one-pointer-per-level
+ * representation with fan-out 4).  With l = ceil(lg sigma), symbols are read
+ * as codes of L4 = ceil(l / 2) base-4 digits (a zero bit on top when l is
+ * odd).  Digit level i lists, node after node, digit i of every symbol
+ * (bits 2(L4-1-i) + 1 and 2(L4-1-i)); the node of s at level i is
+ * s >> 2(L4-i) and the symbols of a node keep their input order.
+ *
+ * Layout (tree memory of wt_multiary_footprint bytes): the 256-byte header
+ * (status word first); then L4 digit levels of round_up(ceil(n/32), 8)
+ * 64-bit words, digit p in word p/32 at bits 2(p%32) and 2(p%32)+1, every
+ * digit at a position >= n zero; then L4 directories of round_up(K, 8)
+ * entries, K = ceil(n/512) + 1, each entry four u64 counts: entry k holds
+ * the number of digits 0, 1, 2, 3 in positions [0, min(512k, n)); padding
+ * entries are zero.  Same arguments, memory rules and status reporting as
+ * wt_build; the workspace is wt_multiary_footprint's.  The queries below
+ * accept a 4-ary handle (digit walks: the child of digit d of node [b, e)
+ * follows the digits smaller than d of [b, e) at the next level); wt_levels
+ * does not (WT_EINVAL), wt_multiary_levels gives the digit levels instead.
+ */
+int wt_multiary_footprint(const wt_desc *desc, uint64_t *tree_bytes, uint64_t *work_bytes);
+int wt_build_multiary(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t tree_bytes,
+                      void *d_work, uint64_t work_bytes, void *stream, wt_tree **out);
+int wt_multiary_levels(const wt_tree *tree, uint32_t *levels, const uint64_t **d_digits,
+                       uint64_t *words_per_level, const uint64_t **d_dir, uint64_t *dir_stride);
+
+/*
  * Buffered build (the extension for inputs that do not fit, Section 5, on
  * Algorithm dd of Section 3.2 and Function mergeBA): S is read in buffers of
  * buffer_syms symbols; each buffer is copied to the device and built as a

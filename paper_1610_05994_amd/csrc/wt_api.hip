@@ -176,6 +176,43 @@ static SmallJob make_small_job(const Layout &L, const void *S, void *tree) {
     return j;
 }
 
+// 4-ary tree: the binary passes of a tiled build (the one-workgroup build
+// writes binary levels only), with the tree holding digit levels and their
+// directories and the workspace the directory's workgroup sums.
+static uint64_t dir_wgs(uint64_t n) { return ceil_div(ceil_div(n, 512), kDirBlocksPerWG); }
+
+static void make_layout4(uint64_t n, uint32_t sigma, uint32_t width, Layout *L) {
+    uint32_t g = tuned_geometry(n, sigma, width, false);
+    if (g == kGeomSmall || g == kGeomMid) g = 32;
+    make_layout_geom(n, sigma, width, g, L);
+    L->arity = 4;
+    L->levels4 = (L->levels + 1) / 2;
+    L->dwords = round_up(ceil_div(n, 32), 8);
+    L->tree_bits_off = L->tree_ranks_off = 0;  // no binary levels
+    L->tree_digits_off = kHeaderBytes;
+    L->tree_dir_off = L->tree_digits_off + (uint64_t)L->levels4 * L->dwords * 8;
+    L->tree_bytes = L->tree_dir_off + (uint64_t)L->levels4 * L->rank_stride * 32;
+    L->ws_dsum = L->work_bytes;
+    L->work_bytes += round_up((uint64_t)(L->levels4 ? L->levels4 : 1) * (dir_wgs(n) ? dir_wgs(n) : 1) * 32, 256);
+}
+
+// Binary passes a 4-ary build runs: up to the one whose T_i is the order of
+// the last digit level.  Digit level k (k >= 1) lists the symbols in the
+// order of their top 2k bits of the code padded to 2 L4 bits, i.e. the top
+// 2k - pad bits of the symbol: that order is T_{2k - pad}.
+static uint32_t multiary_passes(const Layout &L) {
+    if (L.levels4 <= 1) return L.levels4;
+    const uint32_t pad = 2 * L.levels4 - L.levels;
+    return 2 * (L.levels4 - 1) - pad + 1;
+}
+
+static int digit_level(const Layout &L, uint32_t i) {  // -1: pass i emits no digit level
+    const uint32_t pad = 2 * L.levels4 - L.levels;
+    if (i == 0) return 0;
+    if ((i + pad) % 2) return -1;
+    return (int)((i + pad) / 2);
+}
+
 // Enqueue every kernel of one build.  Arguments are already validated.
 static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, uint8_t *work,
                                 hipStream_t st) {
@@ -197,9 +234,10 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
     uint64_t *start = reinterpret_cast<uint64_t *>(work + L.ws_start);
     uint64_t *partials = reinterpret_cast<uint64_t *>(work + L.ws_partials);
 
+    const bool four = L.arity == 4;
     long pr = prof_begin(st, "zero", 0, L.width, L.n, L.ws_ctrl_bytes);
-    hipError_t err = launch_zero(work + L.ws_ctrl, L.ws_ctrl_bytes, tree_status, L.n == 0 ? ranks : nullptr,
-                                 (uint64_t)l * L.rank_stride, st);
+    hipError_t err = launch_zero(work + L.ws_ctrl, L.ws_ctrl_bytes, tree_status,
+                                 (L.n == 0 && !four) ? ranks : nullptr, (uint64_t)l * L.rank_stride, st);
     prof_end(pr, st);
     if (err == hipSuccess && L.n == 0 && L.matrix && l)  // the zeros of an empty matrix
         err = launch_zero(tree + kZerosOff, (uint64_t)l * 8, tree_status, nullptr, 0, st);
@@ -230,7 +268,8 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
     if (l == 0) return hipSuccess;
 
     uint8_t *tbuf[2] = {work + L.ws_ta, work + L.ws_tb};
-    for (uint32_t i = 0; i < l; i++) {
+    const uint32_t lrun = four ? multiary_passes(L) : l;  // binary passes to run
+    for (uint32_t i = 0; i < lrun; i++) {
         PlanArgs pa;
         pa.start = start + start_offset(i);
         pa.ones = ones + ones_offset(i);
@@ -265,14 +304,19 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
 
         LevelArgs a;
         a.tin = (i == 0) ? S : tbuf[(i - 1) & 1];  // T_i for i >= 1 alternates ta, tb
-        a.tout = (i + 1 < l) ? tbuf[i & 1] : nullptr;
-        a.bits = bits + (uint64_t)i * L.words;
-        a.ranks = ranks + (uint64_t)i * L.rank_stride;
+        a.tout = (i + 1 < lrun) ? tbuf[i & 1] : nullptr;
+        a.bits = four ? nullptr : bits + (uint64_t)i * L.words;
+        a.ranks = four ? nullptr : ranks + (uint64_t)i * L.rank_stride;
+        const int dl = four ? digit_level(L, i) : -1;
+        a.digits = (dl >= 0) ? reinterpret_cast<uint64_t *>(tree + L.tree_digits_off) + (uint64_t)dl * L.dwords
+                             : nullptr;
+        a.dwords = L.dwords;
+        a.dsh = (dl >= 0) ? 2 * (L.levels4 - 1 - (uint32_t)dl) : 0u;
         a.zo = zo + zo_offset(i);
         a.tile_ones = tile_ones + (uint64_t)i * tile_stride(L.ntiles);
         a.sup = sup + (uint64_t)i * L.nsup;
-        a.tile_ones_next = (i + 1 < l) ? tile_ones + (uint64_t)(i + 1) * tile_stride(L.ntiles) : nullptr;
-        a.ones_next = (i + 1 < l) ? ones + ones_offset(i + 1) : nullptr;
+        a.tile_ones_next = (i + 1 < lrun) ? tile_ones + (uint64_t)(i + 1) * tile_stride(L.ntiles) : nullptr;
+        a.ones_next = (i + 1 < lrun) ? ones + ones_offset(i + 1) : nullptr;
         a.nodes_next = L.matrix ? 1ull : 2ull << i;
         a.slots_next = L.matrix ? kSlotSpan : level_slots(i + 1);
         a.n = L.n;
@@ -285,13 +329,35 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         a.symmask = (uint32_t)((1ull << l) - 1);
         a.matrix = L.matrix;
         a.zeros = L.matrix ? reinterpret_cast<unsigned long long *>(tree + kZerosOff) : nullptr;
-        const uint64_t lbytes = L.n * L.width * (a.tout ? 2 : 1) + L.words * 8 + L.rank_stride * 8;
+        const uint64_t lbytes = L.n * L.width * (a.tout ? 2 : 1) + (a.bits ? L.words * 8 + L.rank_stride * 8 : 0) +
+                                (a.digits ? L.dwords * 8 : 0);
         pr = prof_begin(st, "level", i, L.width, L.n, lbytes);
         err = launch_level(a, L.width, L.lane_bytes, !L.matrix && level_multi(L.n, i, L.width, L.lane_bytes), st);
         prof_end(pr, st);
         if (err != hipSuccess) return err;
     }
     return hipSuccess;
+}
+
+// A 4-ary build: the binary passes with digit emission, then the digit
+// directories (also for n = 0: the level totals and padding).
+static hipError_t enqueue_multiary(const void *S, const Layout &L, uint8_t *tree, uint8_t *work, hipStream_t st) {
+    hipError_t err = enqueue_build(S, L, tree, work, st);
+    if (err != hipSuccess) return err;
+    DigitDirArgs d;
+    d.digits = reinterpret_cast<const uint64_t *>(tree + L.tree_digits_off);
+    d.dir = reinterpret_cast<uint64_t *>(tree + L.tree_dir_off);
+    d.wsum = reinterpret_cast<unsigned long long *>(work + L.ws_dsum);
+    d.n = L.n;
+    d.dwords = L.dwords;
+    d.dir_stride = L.rank_stride;
+    d.nblk = ceil_div(L.n, 512);
+    d.wg_per_level = dir_wgs(L.n);
+    d.levels = L.levels4;
+    long pr = prof_begin(st, "digit_dir", 0, L.width, L.n, (uint64_t)L.levels4 * (L.dwords * 8 + L.rank_stride * 32));
+    err = launch_digit_dir(d, st);
+    prof_end(pr, st);
+    return err;
 }
 
 static int check_desc(const wt_desc *d) {
@@ -314,6 +380,12 @@ static TreeView view_of(const wt_tree *t) {
     v.sigma = t->L.sigma;
     v.levels = t->L.levels;
     v.zeros = t->L.matrix ? reinterpret_cast<const unsigned long long *>(t->tree + kZerosOff) : nullptr;
+    const bool four = t->L.arity == 4;
+    v.digits = four ? reinterpret_cast<const uint64_t *>(t->tree + t->L.tree_digits_off) : nullptr;
+    v.dir = four ? reinterpret_cast<const uint64_t *>(t->tree + t->L.tree_dir_off) : nullptr;
+    v.dwords = t->L.dwords;
+    v.levels4 = t->L.levels4;
+    if (four) v.bits = v.ranks = nullptr;
     return v;
 }
 
@@ -621,6 +693,49 @@ int wt_build_matrix(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t
     return build_one(d_S, desc, d_tree, tree_bytes, d_work, work_bytes, stream, out, 1u);
 }
 
+int wt_multiary_footprint(const wt_desc *desc, uint64_t *tree_bytes, uint64_t *work_bytes) {
+    int rc = check_desc(desc);
+    if (rc != WT_OK) return rc;
+    Layout L;
+    make_layout4(desc->n, desc->sigma, desc->width, &L);
+    if (tree_bytes) *tree_bytes = L.tree_bytes;
+    if (work_bytes) *work_bytes = L.work_bytes;
+    return WT_OK;
+}
+
+int wt_build_multiary(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t tree_bytes, void *d_work,
+                      uint64_t work_bytes, void *stream, wt_tree **out) {
+    if (out) *out = nullptr;
+    int rc = check_desc(desc);
+    if (rc != WT_OK) return rc;
+    if (!out || !d_tree || !d_work || (desc->n > 0 && !d_S)) return WT_EINVAL;
+    if (((uintptr_t)d_S & 15) || ((uintptr_t)d_tree & 255) || ((uintptr_t)d_work & 255)) return WT_EINVAL;
+    Layout L;
+    make_layout4(desc->n, desc->sigma, desc->width, &L);
+    if (tree_bytes < L.tree_bytes || work_bytes < L.work_bytes) return WT_ENOMEM;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    wt_tree *h = new_handle(L, d_tree, st);
+    if (!h) return WT_ENOMEM;
+    if (enqueue_multiary(d_S, L, reinterpret_cast<uint8_t *>(d_tree), reinterpret_cast<uint8_t *>(d_work), st) !=
+        hipSuccess) {
+        delete h;
+        return WT_EDEVICE;
+    }
+    *out = h;
+    return WT_OK;
+}
+
+int wt_multiary_levels(const wt_tree *t, uint32_t *levels, const uint64_t **d_digits, uint64_t *words_per_level,
+                       const uint64_t **d_dir, uint64_t *dir_stride) {
+    if (!t || t->L.arity != 4) return WT_EINVAL;
+    if (levels) *levels = t->L.levels4;
+    if (d_digits) *d_digits = reinterpret_cast<const uint64_t *>(t->tree + t->L.tree_digits_off);
+    if (words_per_level) *words_per_level = t->L.dwords;
+    if (d_dir) *d_dir = reinterpret_cast<const uint64_t *>(t->tree + t->L.tree_dir_off);
+    if (dir_stride) *dir_stride = t->L.rank_stride;
+    return WT_OK;
+}
+
 int wt_matrix_zeros(const wt_tree *t, uint64_t *zeros) {
     if (!t || !zeros || !t->L.matrix) return WT_EINVAL;
     if (t->L.levels == 0) return WT_OK;
@@ -815,7 +930,7 @@ void wt_free(wt_tree *t) {
 
 int wt_levels(const wt_tree *t, uint32_t *levels, const uint64_t **d_bitmaps, uint64_t *words_per_level,
               const uint64_t **d_ranks, uint64_t *rank_stride, uint64_t *rank_entries) {
-    if (!t) return WT_EINVAL;
+    if (!t || t->L.arity == 4) return WT_EINVAL;  // a 4-ary tree has digit levels (wt_multiary_levels)
     if (levels) *levels = t->L.levels;
     if (d_bitmaps) *d_bitmaps = reinterpret_cast<const uint64_t *>(t->tree + t->L.tree_bits_off);
     if (words_per_level) *words_per_level = t->L.words;

@@ -958,8 +958,8 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
     const uint32_t lr1 = incl - pc;  // ones in the tile before this lane
     const unsigned long long r_lane = prefix + lr1;
 
-    // bitmap words: 64 / E consecutive lanes form one word
-    {
+    if (a.bits) {
+        // bitmap words: 64 / E consecutive lanes form one word
         uint64_t wd = (uint64_t)mb;
 #pragma unroll
         for (int d = 1; d < 64 / E; d++) wd |= (uint64_t)__shfl_down((uint32_t)mb, d, 64) << (d * E);
@@ -967,16 +967,43 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
             const uint64_t widx = pos0 / 64;
             if (widx < a.words) a.bits[widx] = wd;
         }
-    }
-    // rank directory: entry k = ones before position 512k
-    if ((pos0 & 511) == 0) {
-        const uint64_t k = pos0 >> 9;
-        if (k < a.rank_stride) a.ranks[k] = (k < a.rank_entries) ? r_lane : 0ull;
+        // rank directory: entry k = ones before position 512k
+        if ((pos0 & 511) == 0) {
+            const uint64_t k = pos0 >> 9;
+            if (k < a.rank_stride) a.ranks[k] = (k < a.rank_entries) ? r_lane : 0ull;
+        }
+        if (t == a.ntiles - 1 && lane < 8) {  // entries past the last tile
+            const uint64_t k = (base + TILE) / 512 + lane;
+            if (k < a.rank_stride) a.ranks[k] = (k < a.rank_entries) ? prefix + agg : 0ull;
+        }
     }
     if (a.zeros && t == a.ntiles - 1 && lane == 0) a.zeros[a.level] = a.n - (prefix + agg);
-    if (t == a.ntiles - 1 && lane < 8) {  // entries past the last tile
-        const uint64_t k = (base + TILE) / 512 + lane;
-        if (k < a.rank_stride) a.ranks[k] = (k < a.rank_entries) ? prefix + agg : 0ull;
+    if (a.digits) {
+        // 4-ary tree: T_i is also the order of a digit level; its digits,
+        // 32 per word (positions >= n read as 0, so padding digits are 0)
+        constexpr int DPW = 32;
+        if (E >= DPW) {
+#pragma unroll
+            for (int w = 0; w < E / DPW; w++) {
+                uint64_t wd = 0;
+#pragma unroll
+                for (int k = 0; k < DPW; k++)
+                    wd |= (uint64_t)((raw_elem<W, B>(raw, w * DPW + k) >> a.dsh) & 3u) << (2 * k);
+                const uint64_t widx = pos0 / DPW + w;
+                if (widx < a.dwords) a.digits[widx] = wd;
+            }
+        } else {
+            uint32_t part = 0;  // 2E <= 32 bits
+#pragma unroll
+            for (int k = 0; k < E; k++) part |= ((raw_elem<W, B>(raw, k) >> a.dsh) & 3u) << (2 * k);
+            uint64_t wd = part;
+#pragma unroll
+            for (int d = 1; d < DPW / E; d++) wd |= (uint64_t)__shfl_down(part, d, 64) << (d * 2 * E);
+            if ((lane % (DPW / E)) == 0) {
+                const uint64_t widx = pos0 / DPW;
+                if (widx < a.dwords) a.digits[widx] = wd;
+            }
+        }
     }
 
     if (a.tout == nullptr) return;  // last level: no next order, no counts
@@ -1240,6 +1267,9 @@ __device__ __forceinline__ LevelArgs job_level(const BatchJob &j, uint32_t i) {
     a.symmask = (uint32_t)((1ull << l) - 1);
     a.matrix = 0;
     a.zeros = nullptr;
+    a.digits = nullptr;
+    a.dwords = 0;
+    a.dsh = 0;
     return a;
 }
 

@@ -70,6 +70,11 @@ struct Layout {
     uint32_t sigma, width, levels, lane_bytes;
     uint32_t small;         // 0, or kGeomSmall / kGeomMid: built by one workgroup (no workspace)
     uint32_t matrix;        // a wavelet matrix rather than a wavelet tree
+    uint32_t arity;         // 4: a 4-ary tree (digit levels and per-digit directories), else binary
+    uint32_t levels4;       // 4-ary levels: ceil(levels / 2)
+    uint64_t dwords;        // 4-ary: 64-bit words per digit level (32 digits each, padded to 8)
+    uint64_t tree_digits_off, tree_dir_off;  // 4-ary: digit levels, then directories (4 u64 per entry)
+    uint64_t ws_dsum;       // 4-ary: per level and directory workgroup, four digit counts (u64)
     uint64_t words;         // W: bitmap words per level
     uint64_t rank_entries;  // K
     uint64_t rank_stride;   // round_up(K, 8)
@@ -124,6 +129,11 @@ struct LevelArgs {
     // wavelet matrix: one node per level; zeros[level] receives z_i
     uint32_t matrix;
     unsigned long long *zeros;
+    // 4-ary tree: digit level written from T_i when non-null (digit of x is
+    // (x >> dsh) & 3); the binary bitmap and directory are then not written
+    uint64_t *digits;
+    uint64_t dwords;
+    uint32_t dsh;
 };
 
 struct IngestArgs {
@@ -230,6 +240,18 @@ hipError_t launch_leaf_prefix(const uint64_t *start_last, const ulonglong2 *zo_l
                               unsigned long long *row, hipStream_t s);
 hipError_t launch_merge(const MergeArgs &a, hipStream_t s);  // column prefix, merge, rank directory, status
 
+// 4-ary tree directories (wt_multiary.hip): entry k of a level holds the
+// counts of digits 0..3 in positions [0, min(512 k, n)).
+struct DigitDirArgs {
+    const uint64_t *digits;         // levels x dwords words
+    uint64_t *dir;                  // levels x dir_stride entries x 4 counts
+    unsigned long long *wsum;       // levels x wg_per_level x 4 counts
+    uint64_t n, dwords, dir_stride, nblk, wg_per_level;
+    uint32_t levels;
+};
+constexpr uint64_t kDirBlocksPerWG = 256;  // 512-position blocks per directory workgroup
+hipError_t launch_digit_dir(const DigitDirArgs &a, hipStream_t s);
+
 // query launchers (wt_query.hip)
 struct TreeView {
     const uint64_t *bits;
@@ -237,6 +259,12 @@ struct TreeView {
     const unsigned long long *zeros;  // wavelet matrix: zeros of every level (else null)
     uint64_t n, words, rank_entries, rank_stride;
     uint32_t sigma, levels;
+    // 4-ary tree (digits non-null): levels4 digit levels of dwords words and
+    // their directories (rank_stride entries of four counts each)
+    const uint64_t *digits;
+    const uint64_t *dir;
+    uint64_t dwords;
+    uint32_t levels4;
 };
 hipError_t launch_access(const TreeView &t, const uint64_t *i, uint32_t *sym, uint64_t m,
                          hipStream_t s);

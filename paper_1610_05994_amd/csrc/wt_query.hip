@@ -1,4 +1,5 @@
-// Batched access / rank / select on a built pointerless wavelet tree.
+// Batched access / rank / select on a built pointerless wavelet tree (and
+// on the wavelet-matrix and 4-ary variants).
 //
 // Section 2.3: queries walk the tree top-down; with one bitmap per level the
 // current node is a range [b, e) of the level, its left child is the first
@@ -120,10 +121,150 @@ __device__ uint64_t matrix_select(const TreeView &t, uint32_t c, uint64_t j) {
     return p;
 }
 
+// 4-ary tree: level k lists 2-bit digits (32 per word); the child of digit
+// d of node [b, e) occupies, at the next level, the part of [b, e) after the
+// digits smaller than d, as long as the digits equal to d.  Counts come from
+// the per-digit directory plus popcounts over the two bit planes of at most
+// fifteen words.
+constexpr uint64_t kEvenBits = 0x5555555555555555ull;
+
+struct DLevel {
+    const uint64_t *D, *R;  // digit words; directory entries of four counts
+};
+
+struct DCounts {
+    uint64_t c[4];
+};
+
+__device__ __forceinline__ DLevel dlevel_of(const TreeView &t, uint32_t k) {
+    return DLevel{t.digits + (uint64_t)k * t.dwords, t.dir + (uint64_t)k * t.rank_stride * 4};
+}
+
+__device__ __forceinline__ uint64_t pick(const DCounts &x, uint32_t d) {
+    return d == 0 ? x.c[0] : (d == 1 ? x.c[1] : (d == 2 ? x.c[2] : x.c[3]));
+}
+
+__device__ __forceinline__ uint32_t digit_at(const DLevel &L, uint64_t p) {
+    return (uint32_t)((L.D[p >> 5] >> (2 * (p & 31))) & 3ull);
+}
+
+// even-bit mask of the digits equal to d in word w
+__device__ __forceinline__ uint64_t digit_mask(uint64_t w, uint32_t d) {
+    const uint64_t lo = w & kEvenBits, hi = (w >> 1) & kEvenBits;
+    return ((d & 1) ? lo : (~lo & kEvenBits)) & ((d & 2) ? hi : (~hi & kEvenBits));
+}
+
+// counts of every digit in positions [0, p), 0 <= p <= n
+__device__ DCounts rank_digits(const DLevel &L, uint64_t p) {
+    const uint64_t k = p >> 9, w1 = p >> 5;
+    uint64_t c1 = 0, c2 = 0, c3 = 0;
+    for (uint64_t w = k * 16; w <= w1; w++) {
+        if (w == w1 && (p & 31) == 0) break;
+        uint64_t x = L.D[w];
+        if (w == w1) x &= (1ull << (2 * (p & 31))) - 1ull;
+        const uint64_t lo = x & kEvenBits, hi = (x >> 1) & kEvenBits;
+        c1 += __popcll(lo & ~hi);
+        c2 += __popcll(hi & ~lo);
+        c3 += __popcll(lo & hi);
+    }
+    const uint64_t *E = L.R + k * 4;
+    DCounts r;
+    r.c[0] = E[0] + (p - k * 512) - c1 - c2 - c3;
+    r.c[1] = E[1] + c1;
+    r.c[2] = E[2] + c2;
+    r.c[3] = E[3] + c3;
+    return r;
+}
+
+// position of the m-th (1-based) digit d of the level; requires 1 <= m <=
+// the digits d in [0, n)
+__device__ uint64_t select_digit(const DLevel &L, uint64_t K, uint64_t n, uint32_t d, uint64_t m) {
+    uint64_t lo = 0, hi = K - 1;
+    while (lo < hi) {  // largest k with R[k][d] < m (R[0][d] = 0 < m)
+        const uint64_t mid = (lo + hi + 1) / 2;
+        if (L.R[mid * 4 + d] < m) lo = mid; else hi = mid - 1;
+    }
+    uint64_t r = L.R[lo * 4 + d], w = lo * 16;
+    const uint64_t nw = (n + 31) / 32;
+    while (w < nw) {
+        uint64_t mk = digit_mask(L.D[w], d);
+        if (w * 32 + 32 > n) mk &= (1ull << (2 * (n - w * 32))) - 1ull;  // digits past n are padding
+        const uint64_t pc = __popcll(mk);
+        if (r + pc >= m) return w * 32 + select_in_word(mk, (uint32_t)(m - r - 1)) / 2;
+        r += pc;
+        w++;
+    }
+    return ~0ull;  // only for a corrupted directory
+}
+
+__device__ uint32_t access4(const TreeView &t, uint64_t i) {
+    uint64_t b = 0, e = t.n, p = i;
+    uint32_t s = 0;
+    for (uint32_t k = 0; k < t.levels4; k++) {
+        const DLevel L = dlevel_of(t, k);
+        const uint32_t d = digit_at(L, p);
+        const DCounts rb = rank_digits(L, b), re = rank_digits(L, e), rp = rank_digits(L, p);
+        uint64_t below = 0;
+        for (uint32_t x = 0; x < d; x++) below += pick(re, x) - pick(rb, x);
+        const uint64_t nb = b + below;
+        e = nb + (pick(re, d) - pick(rb, d));
+        p = nb + (pick(rp, d) - pick(rb, d));
+        b = nb;
+        s = (s << 2) | d;
+        if (p >= e || e > t.n) return 0xFFFFFFFEu;  // corrupted tree only
+    }
+    return s;
+}
+
+__device__ uint64_t rank4(const TreeView &t, uint32_t c, uint64_t i) {
+    uint64_t b = 0, e = t.n, p = i;
+    for (uint32_t k = 0; k < t.levels4; k++) {
+        const DLevel L = dlevel_of(t, k);
+        const uint32_t d = (c >> (2 * (t.levels4 - 1 - k))) & 3u;
+        const DCounts rb = rank_digits(L, b), re = rank_digits(L, e), rp = rank_digits(L, p);
+        uint64_t below = 0;
+        for (uint32_t x = 0; x < d; x++) below += pick(re, x) - pick(rb, x);
+        const uint64_t nb = b + below;
+        e = nb + (pick(re, d) - pick(rb, d));
+        p = nb + (pick(rp, d) - pick(rb, d));
+        b = nb;
+        if (p > e || e > t.n) return ~1ull;  // corrupted tree only
+    }
+    return p - b;
+}
+
+__device__ uint64_t select4(const TreeView &t, uint32_t c, uint64_t j) {
+    uint64_t bs[16];
+    uint64_t b = 0, e = t.n;
+    for (uint32_t k = 0; k < t.levels4; k++) {  // node ranges of c, top-down
+        const DLevel L = dlevel_of(t, k);
+        const uint32_t d = (c >> (2 * (t.levels4 - 1 - k))) & 3u;
+        bs[k] = b;
+        const DCounts rb = rank_digits(L, b), re = rank_digits(L, e);
+        uint64_t below = 0;
+        for (uint32_t x = 0; x < d; x++) below += pick(re, x) - pick(rb, x);
+        b = b + below;
+        e = b + (pick(re, d) - pick(rb, d));
+        if (e > t.n) return ~1ull;  // corrupted tree only
+    }
+    if (j == 0 || j > e - b) return ~0ull;
+    uint64_t idx = j - 1;
+    for (uint32_t k = t.levels4; k-- > 0;) {  // bottom-up back to S
+        const DLevel L = dlevel_of(t, k);
+        const uint32_t d = (c >> (2 * (t.levels4 - 1 - k))) & 3u;
+        const uint64_t bb = bs[k];
+        const uint64_t pos = select_digit(L, t.rank_entries, t.n, d, pick(rank_digits(L, bb), d) + idx + 1);
+        if (pos >= t.n) return ~0ull;
+        idx = pos - bb;
+    }
+    return idx;
+}
+
 // access(i): the symbol at position i (0xFFFFFFFF if i >= n).
 __device__ uint32_t access_one(const TreeView &t, uint64_t i) {
     if (i >= t.n) return 0xFFFFFFFFu;
     if (t.zeros) return matrix_access(t, i);
+    if (t.digits) return access4(t, i);
     uint64_t b = 0, e = t.n, p = i;
     uint32_t s = 0;
     for (uint32_t k = 0; k < t.levels; k++) {
@@ -149,6 +290,7 @@ __device__ uint64_t rank_one(const TreeView &t, uint32_t c, uint64_t i) {
         matrix_range(t, c, i, b, e);
         return e - b;
     }
+    if (t.digits) return rank4(t, c, i);
     uint64_t b = 0, e = t.n, cnt = i;
     for (uint32_t k = 0; k < t.levels; k++) {
         const Level L = level_of(t, k);
@@ -166,6 +308,7 @@ __device__ uint64_t rank_one(const TreeView &t, uint32_t c, uint64_t i) {
 __device__ uint64_t select_one(const TreeView &t, uint32_t c, uint64_t j) {
     if (c >= t.sigma) return ~0ull;
     if (t.zeros) return matrix_select(t, c, j);
+    if (t.digits) return select4(t, c, j);
     uint64_t bs[32];
     uint64_t b = 0, e = t.n;
     for (uint32_t k = 0; k < t.levels; k++) {  // node ranges of c, top-down

@@ -26,6 +26,7 @@ EXPORTED = [
     "wt_free", "wt_levels", "wt_access_batch", "wt_rank_batch", "wt_select_batch",
     "wt_access", "wt_rank", "wt_select", "wt_query_multi_footprint", "wt_query_multi", "wt_strerror",
     "wt_tune_set", "wt_tune_get", "wt_buffered_footprint", "wt_build_buffered",
+    "wt_multiary_footprint", "wt_build_multiary", "wt_multiary_levels",
     "wt_prof_enable", "wt_prof_read",
 ]
 
@@ -64,6 +65,9 @@ def lib():
         "wt_build_matrix": ([vp, P(wt_desc), vp, u64, vp, u64, vp, P(vp)], i32),
         "wt_matrix_zeros": ([vp, P(u64)], i32),
         "wt_buffered_footprint": ([P(wt_desc), u64, P(u64), P(u64)], i32),
+        "wt_multiary_footprint": ([P(wt_desc), P(u64), P(u64)], i32),
+        "wt_build_multiary": ([vp, P(wt_desc), vp, u64, vp, u64, vp, P(vp)], i32),
+        "wt_multiary_levels": ([vp, P(u32), P(vp), P(u64), P(vp), P(u64)], i32),
         "wt_build_buffered": ([vp, P(wt_desc), u64, vp, u64, vp, u64, vp, P(vp)], i32),
         "wt_batch_footprint": ([u32, P(wt_desc), P(u64)], i32),
         "wt_build_batch": ([u32, P(vp), P(wt_desc), P(vp), P(u64), vp, u64, vp, P(vp)], i32),
@@ -143,6 +147,31 @@ def wt_matrix_zeros(h: int, levels: int):
     z = (ctypes.c_uint64 * max(1, levels))()
     rc = lib().wt_matrix_zeros(h, z)
     return rc, np.array(z[:levels], dtype=np.uint64)
+
+
+def wt_multiary_footprint(n: int, sigma: int, width: int):
+    d = wt_desc(n, sigma, width)
+    tb, wb = ctypes.c_uint64(), ctypes.c_uint64()
+    rc = lib().wt_multiary_footprint(ctypes.byref(d), ctypes.byref(tb), ctypes.byref(wb))
+    return rc, tb.value, wb.value
+
+
+def wt_build_multiary(d_S: int, n: int, sigma: int, width: int, d_tree: int, tree_bytes: int, d_work: int,
+                      work_bytes: int, stream: int):
+    d = wt_desc(n, sigma, width)
+    h = ctypes.c_void_p()
+    rc = lib().wt_build_multiary(d_S, ctypes.byref(d), d_tree, tree_bytes, d_work, work_bytes, stream,
+                                 ctypes.byref(h))
+    return rc, h.value
+
+
+def wt_multiary_levels(h: int):
+    lv, wpl, ds = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
+    dig, dr = ctypes.c_void_p(), ctypes.c_void_p()
+    rc = lib().wt_multiary_levels(h, ctypes.byref(lv), ctypes.byref(dig), ctypes.byref(wpl), ctypes.byref(dr),
+                                  ctypes.byref(ds))
+    return rc, dict(levels=lv.value, digits=dig.value or 0, words=wpl.value, dir=dr.value or 0,
+                    dir_stride=ds.value)
 
 
 def wt_buffered_footprint(n: int, sigma: int, width: int, buffer_syms: int):
@@ -281,17 +310,18 @@ class Tree:
     """A built tree whose memory is a torch tensor; owns the C handle."""
 
     def __init__(self, handle: int, tree_mem, work_mem, S, n: int, sigma: int, width: int, stream,
-                 matrix: bool = False):
+                 matrix: bool = False, arity: int = 2):
         self.handle = handle
         self.matrix = matrix
+        self.arity = arity
         self.tree_mem = tree_mem
         self.work_mem = work_mem   # kept alive until the build has finished
         self.S = S
         self.n, self.sigma, self.width = n, sigma, width
         self.stream = stream
-        rc, info = wt_levels(handle)
+        rc, info = wt_multiary_levels(handle) if arity == 4 else wt_levels(handle)
         if rc != WT_OK:
-            raise WtError(rc, "wt_levels")
+            raise WtError(rc, "wt_multiary_levels" if arity == 4 else "wt_levels")
         self.info = info
 
     @property
@@ -335,6 +365,18 @@ class Tree:
     def bitmaps(self) -> np.ndarray:
         self.check()
         return self.bitmaps_device().cpu().numpy().view(np.uint64)
+
+    def digits(self) -> np.ndarray:
+        """4-ary tree: (levels, words) uint64 digit levels, 32 two-bit digits per word."""
+        self.check()
+        l, W = self.levels, self.info["words"]
+        return self._region(self.info["digits"], l * W).view(l, W).cpu().numpy().view(np.uint64)
+
+    def digit_dir(self) -> np.ndarray:
+        """4-ary tree: (levels, dir_stride, 4) uint64 counts of digits 0..3 before 512k."""
+        self.check()
+        l, K = self.levels, self.info["dir_stride"]
+        return self._region(self.info["dir"], l * K * 4).view(l, K, 4).cpu().numpy().view(np.uint64)
 
     def ranks(self) -> np.ndarray:
         self.check()
@@ -394,25 +436,27 @@ def to_device(S: np.ndarray, device="cuda"):
 
 
 def build(S, sigma: int, width: int | None = None, stream=None, tree_mem=None, work_mem=None,
-          matrix: bool = False) -> Tree:
-    """Build the tree (or, with matrix=True, the wavelet matrix) of a device
-    tensor S (uint8 / int16 / int32 storage)."""
+          matrix: bool = False, arity: int = 2) -> Tree:
+    """Build the tree (with matrix=True the wavelet matrix, with arity=4 the
+    4-ary tree) of a device tensor S (uint8 / int16 / int32 storage)."""
     torch = _torch()
     width = width or S.element_size()
     n = S.numel()
-    rc, tb, wb = wt_footprint(n, sigma, width)
+    if arity not in (2, 4) or (arity == 4 and matrix):
+        raise WtError(WT_EINVAL, "build")
+    rc, tb, wb = (wt_multiary_footprint if arity == 4 else wt_footprint)(n, sigma, width)
     if rc != WT_OK:
         raise WtError(rc, "wt_footprint")
     dev = S.device
     tree_mem = tree_mem if tree_mem is not None else _alloc(tb, dev)
     work_mem = work_mem if work_mem is not None else _alloc(wb, dev)
     st = stream if stream is not None else torch.cuda.current_stream(dev)
-    fn = wt_build_matrix if matrix else wt_build
+    fn = wt_build_multiary if arity == 4 else (wt_build_matrix if matrix else wt_build)
     rc, h = fn(S.data_ptr() if n else 0, n, sigma, width, tree_mem.data_ptr(), tree_mem.numel(),
                work_mem.data_ptr(), work_mem.numel(), int(st.cuda_stream))
     if rc != WT_OK:
-        raise WtError(rc, "wt_build_matrix" if matrix else "wt_build")
-    return Tree(h, tree_mem, work_mem, S, n, sigma, width, st, matrix)
+        raise WtError(rc, fn.__name__)
+    return Tree(h, tree_mem, work_mem, S, n, sigma, width, st, matrix, arity)
 
 
 def build_buffered(S, sigma: int, buffer_syms: int, width: int | None = None, device="cuda", stream=None,

@@ -208,3 +208,20 @@ def test_buffered_footprint_and_argument_checks():
     bad = wt.wt_desc(10, 0, 1)
     assert wt.lib().wt_build_buffered(None, ctypes.byref(bad), 4, None, 0, None, 0, None, ctypes.byref(h)) == wt.WT_EINVAL
     assert wt.lib().wt_build_buffered(None, ctypes.byref(d), 1 << 20, None, 0, None, 0, None, ctypes.byref(h)) == wt.WT_EINVAL
+
+
+def test_multiary_footprint_and_argument_checks():
+    wt = _wt()
+    for n, sigma, width in [(0, 1, 1), (1, 2, 1), (1000, 256, 1), (5000, 1 << 20, 4), (777, 20, 2)]:
+        rc, tb, wb = wt.wt_multiary_footprint(n, sigma, width)
+        assert rc == wt.WT_OK
+        l4 = (max(0, (sigma - 1).bit_length()) + 1) // 2
+        Wd = ((n + 31) // 32 + 7) // 8 * 8
+        KS = ((n + 511) // 512 + 1 + 7) // 8 * 8
+        assert tb == 256 + l4 * (8 * Wd + 32 * KS)
+        assert wb >= 256 and wb % 256 == 0
+    d = wt.wt_desc(10, 0, 1)
+    h = ctypes.c_void_p()
+    assert wt.lib().wt_build_multiary(None, ctypes.byref(d), None, 0, None, 0, None, ctypes.byref(h)) == wt.WT_EINVAL
+    lv = ctypes.c_uint32()
+    assert wt.lib().wt_multiary_levels(None, ctypes.byref(lv), None, None, None, None) == wt.WT_EINVAL
