@@ -64,10 +64,10 @@ def load_traffic(workload: str):
     return ent.get("bytes_per_level_launch")
 
 
-def cpu_baseline(workload: str, lg: int, runs: int, matrix: bool = False):
+def cpu_baseline(workload: str, lg: int, runs: int, matrix: bool = False, arity: int = 2):
     import oracle
     S, sigma = wtgen.workload("%s@lg%d" % (workload, lg))
-    build = oracle.build_matrix if matrix else oracle.build
+    build = oracle.build_matrix if matrix else (oracle.build4 if arity == 4 else oracle.build)
     build(S[:4096], sigma)  # load + warm the library
     times = []
     for _ in range(runs):
@@ -75,6 +75,17 @@ def cpu_baseline(workload: str, lg: int, runs: int, matrix: bool = False):
         build(S, sigma)
         times.append(time.perf_counter() - t0)
     med = statistics.median(times)
+    # the paper times construction without the rank structures: the same
+    # oracle with the directories switched off
+    plain = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        if arity == 4:
+            build(S, sigma, with_dir=False)
+        else:
+            build(S, sigma, with_ranks=False)
+        plain.append(time.perf_counter() - t0)
+    med_plain = statistics.median(plain)
     return {
         "value": S.shape[0] / med,
         "unit": "symbols/s",
@@ -83,6 +94,7 @@ def cpu_baseline(workload: str, lg: int, runs: int, matrix: bool = False):
         "sample": "first-principles sequential oracle (gcc -O2, one thread) on n=2^%d symbols of the same "
                   "generator and distribution, median of %d runs of %.2f s each, bitmaps + rank directories"
                   % (lg, runs, med),
+        "value_without_directories": S.shape[0] / med_plain,
     }
 
 
@@ -117,6 +129,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--matrix", action="store_true",
                     help="build the wavelet matrix of the workload instead of the wavelet tree (c1-c3)")
+    ap.add_argument("--arity", type=int, default=2, choices=[2, 4],
+                    help="4: build the 4-ary wavelet tree of the workload (c1-c3)")
     ap.add_argument("--buffered", type=int, default=0, metavar="LG",
                     help="buffered build of the workload (c1-c3) in buffers of 2^LG symbols, read from "
                          "page-locked host memory (PCIe included in the step) or, with --buffered-source "
@@ -158,8 +172,8 @@ def main() -> int:
             os.makedirs(args.input_cache, exist_ok=True)
             np.save(os.path.join(args.input_cache, "%s.npy" % args.workload), S)
     n, width = S.shape[0], S.dtype.itemsize
-    if args.buffered and args.matrix:
-        print("bench.py: --buffered builds wavelet trees only", file=sys.stderr)
+    if (args.buffered or args.arity == 4) and args.matrix or (args.buffered and args.arity == 4):
+        print("bench.py: --matrix, --arity 4 and --buffered are separate variants", file=sys.stderr)
         return 2
     if args.buffered and args.buffered_source == "host":
         view = {1: np.uint8, 2: np.int16, 4: np.int32}[width]
@@ -168,6 +182,8 @@ def main() -> int:
         dS = wtree.to_device(S, dev)
     if args.buffered:
         rc, tb, wb = wtree.wt_buffered_footprint(n, sigma, width, 1 << args.buffered)
+    elif args.arity == 4:
+        rc, tb, wb = wtree.wt_multiary_footprint(n, sigma, width)
     else:
         rc, tb, wb = wtree.wt_footprint(n, sigma, width)
     assert rc == wtree.WT_OK
@@ -183,11 +199,11 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
-    build_fn = wtree.wt_build_matrix if args.matrix else wtree.wt_build
+    build_fn = wtree.wt_build_matrix if args.matrix else (wtree.wt_build_multiary if args.arity == 4 else wtree.wt_build)
     if args.buffered:
         def build_fn(S_ptr, n, sigma, width, t_ptr, tb, w_ptr, wb, sh):
             return wtree.wt_build_buffered(S_ptr, n, sigma, width, 1 << args.buffered, t_ptr, tb, w_ptr, wb, sh)
-    fn_name = "wt_build_buffered" if args.buffered else ("wt_build_matrix" if args.matrix else "wt_build")
+    fn_name = "wt_build_buffered" if args.buffered else build_fn.__name__
 
     def one_build():
         rc, h = build_fn(dS.data_ptr(), n, sigma, width, tree_mem.data_ptr(), tb, work_mem.data_ptr(), wb, sh)
@@ -247,7 +263,7 @@ def main() -> int:
         f["avg_us"] = round(f["ms"] * 1e3 / f["launches"], 2)
         f["ms_per_step"] = round(f["ms"] / args.steps, 4)
         del f["ms"]
-    traffic = None if (args.matrix or args.buffered) else load_traffic(args.workload)
+    traffic = None if (args.matrix or args.buffered or args.arity == 4) else load_traffic(args.workload)
     levels = max(0, (sigma - 1).bit_length())
     qmin = n * width + (tb - 256)  # read S once + write every bitmap word and rank entry once
     qmin_gbps = qmin / (p50 / 1e3) / 1e9
@@ -266,7 +282,8 @@ def main() -> int:
         "dtype": {1: "u8", 2: "u16", 4: "u32"}[width],
         "data": "synthetic",
         "config": {"workload": "%s: %s%s%s" % (args.workload, WORKLOADS[args.workload],
-                                               "; wavelet matrix" if args.matrix else "",
+                                               ("; wavelet matrix" if args.matrix else "") +
+                                               ("; 4-ary wavelet tree" if args.arity == 4 else ""),
                                                ("; buffered build, 2^%d-symbol buffers from %s" % (
                                                    args.buffered, "page-locked host memory (PCIe included)"
                                                    if args.buffered_source == "host" else "HBM"))
@@ -301,7 +318,7 @@ def main() -> int:
         }
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline on n=2^%d" % args.cpu_sample_lg, file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_lg, args.cpu_runs, args.matrix)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_lg, args.cpu_runs, args.matrix, args.arity)
         out["cpu_multicore"] = cpu_multicore(args.workload, args.cpu_sample_lg, args.cpu_runs)
     print(json.dumps(out), flush=True)
     return 0
