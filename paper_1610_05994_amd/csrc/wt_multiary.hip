@@ -3,10 +3,11 @@
 // rank structure of the one-pointer-per-level representation (Section 2.3)
 // with four symbols per level instead of two.
 //
-// One thread per 512-position block (sixteen 32-digit words) counts its
-// digits with popcounts over the two bit planes of the words; the workgroup
-// scans the counts of its blocks, the workgroup totals of a level are scanned
-// by one workgroup, and a last pass adds each workgroup's base.
+// Sixteen lanes count one 512-position block (sixteen 32-digit words) with
+// popcounts over the two bit planes of the words; each wave scans the counts
+// of its 64 blocks, the workgroup combines its waves, the workgroup totals
+// of a level are scanned by one workgroup, and a last pass adds each
+// workgroup's base.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -16,7 +17,7 @@ namespace wt {
 
 namespace {
 
-constexpr int kDT = (int)kDirBlocksPerWG;  // threads per workgroup
+constexpr int kDT = 256;  // threads per workgroup
 constexpr uint64_t kEven = 0x5555555555555555ull;
 
 // Exclusive scan of one u64 per thread over the workgroup (wave shuffles,
@@ -44,35 +45,72 @@ __device__ __forceinline__ unsigned long long excl_scan(unsigned long long x, un
     return before + inc - x;
 }
 
-// Counts of digits 1, 2, 3 in a 32-digit word (padding digits are 0).
-__device__ __forceinline__ void count123(uint64_t w, uint32_t &c1, uint32_t &c2, uint32_t &c3) {
-    const uint64_t lo = w & kEven, hi = (w >> 1) & kEven;
-    c1 += (uint32_t)__popcll(lo & ~hi);
-    c2 += (uint32_t)__popcll(hi & ~lo);
-    c3 += (uint32_t)__popcll(lo & hi);
-}
+// Block counts and their workgroup-local prefixes.  Each wave covers 64
+// blocks (1024 words): lane l reads words l, l + 64, ... (coalesced), counts
+// digits 1, 2, 3 of each word (packed in 16-bit fields), and the 16 lanes
+// holding one block's words add their counts with shuffles.  Lane b then
+// scans block b's counts across the wave, counts (0, 1) and (2, 3)
+// travelling as the two 32-bit halves of a u64, and the four waves' totals
+// give each wave its base inside the workgroup.
+constexpr int kWaveBlocks = 64;
+constexpr int kWordsPerLane = kWaveBlocks * 16 / 64;
+static_assert(kDirBlocksPerWG == (uint64_t)(kDT / 64) * kWaveBlocks, "directory tiling");
 
-// Block counts and their workgroup-local prefixes: counts (0, 1) and (2, 3)
-// travel packed as two 32-bit halves of a u64 (a workgroup holds at most
-// kDT * 512 < 2^32 positions).
 __global__ __launch_bounds__(kDT) void k_digit_dir(DigitDirArgs a) {
-    __shared__ unsigned long long s_scan[kDT / 64];
+    __shared__ unsigned long long s_blk[kDT / 64][kWaveBlocks];
+    __shared__ unsigned long long s_tot[kDT / 64][2];
     const uint32_t i = blockIdx.y;
-    const uint64_t blk = (uint64_t)blockIdx.x * kDT + threadIdx.x;
-    uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-    if (blk < a.nblk) {
-        const uint64_t *D = a.digits + (uint64_t)i * a.dwords;
-#pragma unroll 4
-        for (int q = 0; q < 16; q++) {
-            const uint64_t w = blk * 16 + q;
-            if (w < a.dwords) count123(D[w], c1, c2, c3);
-        }
-        const uint64_t valid = (a.n - blk * 512 < 512) ? a.n - blk * 512 : 512;
-        c0 = (uint32_t)valid - c1 - c2 - c3;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t *D = a.digits + (uint64_t)i * a.dwords;
+    const uint64_t blk0 = (uint64_t)blockIdx.x * kDirBlocksPerWG + (uint64_t)wv * kWaveBlocks;
+    const uint64_t w0 = blk0 * 16;
+    uint64_t x[kWordsPerLane];
+#pragma unroll
+    for (int u = 0; u < kWordsPerLane; u++) {
+        const uint64_t w = w0 + (uint64_t)u * 64 + lane;
+        x[u] = (w < a.dwords) ? D[w] : 0ull;
     }
-    unsigned long long t01, t23;
-    const unsigned long long b01 = excl_scan((unsigned long long)c0 | ((unsigned long long)c1 << 32), s_scan, &t01);
-    const unsigned long long b23 = excl_scan((unsigned long long)c2 | ((unsigned long long)c3 << 32), s_scan, &t23);
+#pragma unroll
+    for (int u = 0; u < kWordsPerLane; u++) {
+        const uint64_t lo = x[u] & kEven, hi = (x[u] >> 1) & kEven;
+        unsigned long long c = (unsigned long long)__popcll(lo & ~hi) |
+                               ((unsigned long long)__popcll(hi & ~lo) << 16) |
+                               ((unsigned long long)__popcll(lo & hi) << 32);
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) c += __shfl_xor(c, off, 64);
+        if ((lane & 15) == 0) s_blk[wv][u * 4 + (lane >> 4)] = c;
+    }
+    __syncthreads();
+    const uint64_t blk = blk0 + lane;
+    const unsigned long long c = s_blk[wv][lane];
+    const uint64_t c1 = c & 0xFFFF, c2 = (c >> 16) & 0xFFFF, c3 = (c >> 32) & 0xFFFF;
+    uint64_t valid = 0;
+    if (blk < a.nblk) valid = (a.n - blk * 512 < 512) ? a.n - blk * 512 : 512;
+    const uint64_t c0 = valid - c1 - c2 - c3;  // padding digits are 0 and never counted
+    const unsigned long long v01 = c0 | (c1 << 32), v23 = c2 | (c3 << 32);
+    unsigned long long i01 = v01, i23 = v23;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned long long y01 = __shfl_up(i01, d, 64), y23 = __shfl_up(i23, d, 64);
+        if (lane >= d) {
+            i01 += y01;
+            i23 += y23;
+        }
+    }
+    if (lane == 63) {
+        s_tot[wv][0] = i01;
+        s_tot[wv][1] = i23;
+    }
+    __syncthreads();
+    unsigned long long base01 = 0, base23 = 0, t01 = 0, t23 = 0;
+#pragma unroll
+    for (int w = 0; w < kDT / 64; w++) {
+        base01 += (w < wv) ? s_tot[w][0] : 0ull;
+        base23 += (w < wv) ? s_tot[w][1] : 0ull;
+        t01 += s_tot[w][0];
+        t23 += s_tot[w][1];
+    }
+    const unsigned long long b01 = base01 + i01 - v01, b23 = base23 + i23 - v23;
     if (blk < a.nblk) {
         uint64_t *E = a.dir + ((uint64_t)i * a.dir_stride + blk) * 4;
         E[0] = b01 & 0xFFFFFFFFull;
@@ -120,7 +158,7 @@ __global__ __launch_bounds__(kDT) void k_digit_dir_apply(DigitDirArgs a) {
     const uint32_t i = blockIdx.y;
     const uint64_t blk = (uint64_t)blockIdx.x * kDT + threadIdx.x;
     if (blk >= a.nblk) return;
-    const unsigned long long *ws = a.wsum + ((uint64_t)i * a.wg_per_level + blockIdx.x) * 4;
+    const unsigned long long *ws = a.wsum + ((uint64_t)i * a.wg_per_level + blk / kDirBlocksPerWG) * 4;
     uint64_t *E = a.dir + ((uint64_t)i * a.dir_stride + blk) * 4;
 #pragma unroll
     for (int d = 0; d < 4; d++) E[d] += ws[d];
@@ -138,7 +176,7 @@ hipError_t launch_digit_dir(const DigitDirArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_digit_dir_fix, dim3(a.levels), dim3(kDT), 0, s, a);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     if (a.nblk) {
-        hipLaunchKernelGGL(k_digit_dir_apply, dim3((unsigned)a.wg_per_level, a.levels), dim3(kDT), 0, s, a);
+        hipLaunchKernelGGL(k_digit_dir_apply, dim3((unsigned)ceil_div(a.nblk, kDT), a.levels), dim3(kDT), 0, s, a);
         err = hipGetLastError();
     }
     return err;
