@@ -50,9 +50,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str):
-    """HBM bytes per level launch from the committed rocprofv3 counter runs,
-    or None when the kernel source changed since they were taken."""
+def load_traffic_entry(workload: str):
+    """The committed rocprofv3 counter figures of a workload, or None when the
+    kernel source changed since they were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -61,7 +61,27 @@ def load_traffic(workload: str):
     ent = data.get(workload)
     if not ent or ent.get("kernel_hash") != kernel_source_hash():
         return None
-    return ent.get("bytes_per_level_launch")
+    return ent
+
+
+def load_traffic(workload: str):
+    """HBM bytes per level launch (counters), or None."""
+    ent = load_traffic_entry(workload)
+    return ent.get("bytes_per_level_launch") if ent else None
+
+
+def whole_build_traffic(args, ms_per_step: float):
+    """HBM bytes that every kernel of one build moves (rocprofv3 FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy's readings) over the measured time per
+    build, or None for variants and when the counters are stale."""
+    if args.matrix or args.buffered or args.arity == 4:
+        return None
+    ent = load_traffic_entry(args.workload)
+    if not ent or "bytes_per_build" not in ent:
+        return None
+    b = ent["bytes_per_build"]
+    gbps = b / (ms_per_step / 1e3) / 1e9
+    return {"bytes": b, "gbps": gbps, "frac_of_peak": gbps / HBM_PEAK_GBPS}
 
 
 def cpu_baseline(workload: str, lg: int, runs: int, matrix: bool = False, arity: int = 2):
@@ -302,6 +322,7 @@ def main() -> int:
         },
         "build_latency_ms": {"p50": p50, "p99": p99},
         "compulsory_bytes": {"bytes": qmin, "gbps_at_p50": qmin_gbps, "frac_of_peak": qmin_gbps / HBM_PEAK_GBPS},
+        "whole_build_traffic": whole_build_traffic(args, ms_per_step),
         "kernels": fams,
     }
     if args.buffered:
