@@ -923,6 +923,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
     constexpr int E = B / W;                    // symbols per lane
     constexpr int CH = 16 / W;                  // symbols per 16-byte chunk
     constexpr uint64_t TILE = tile_syms(W, B);  // 64 * E
+    static_assert(TILE < 65536, "per-tile counts travel in 16-bit fields");
     typedef typename MaskT<E>::T M;
     const int lane = threadIdx.x & 63;
     T *s_stage = reinterpret_cast<T *>(s_wave);
@@ -1029,7 +1030,8 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
     T *tout = reinterpret_cast<T *>(a.tout);
     const bool counting = a.tile_ones_next != nullptr;
     const uint32_t sh2 = sh - 1;  // bit of the next level (when counting)
-    unsigned long long *ones_next = a.ones_next + (t % a.slots_next) * a.nodes_next;
+    // (slot counts are powers of two)
+    unsigned long long *ones_next = a.ones_next + (t & (a.slots_next - 1)) * a.nodes_next;
     if (vf == vl) {
         // Single node: zeros keep their order at g0.., ones at g1...
         const ulonglong2 zo = a.zo[vf];
@@ -1077,12 +1079,14 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
             // are the same chunk)
             edge_r[r][0] = (cb < ce && cb < fb) ? cb : 0xffffffffu;
             edge_r[r][1] = (cb < ce && fe < ce && ce - 1 != edge_r[r][0]) ? ce - 1 : 0xffffffffu;
+            // (destinations beyond n only arise from inconsistent tables;
+            // they are dropped rather than written; checked per chunk only
+            // when the run's last whole chunk would pass n)
+            const bool inside = gb + (uint64_t)fe * CH <= a.n;
             for (uint32_t c = fb + lane; c < fe; c += 64) {  // whole chunks [fb, fe)
                 const uint32_t s = c * CH;
                 const uint4 v = *reinterpret_cast<const uint4 *>(&s_stage[s]);
-                // (destinations beyond n only arise from inconsistent tables;
-                // they are dropped rather than written)
-                if (gb + s + CH <= a.n) {
+                if (inside || gb + s + CH <= a.n) {
                     *reinterpret_cast<uint4 *>(tout + (gb + s)) = v;
                     const uint32_t ones = __popc(v.x & mk) + __popc(v.y & mk) + __popc(v.z & mk) + __popc(v.w & mk);
                     const bool second = c >= cs;
@@ -1120,9 +1124,11 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
             }
         }
         if (counting) {
+            // two counts per 32-bit sum (each at most TILE < 2^16)
+            const uint32_t t01 = wave_sum32(cnt[0] | (cnt[1] << 16)), t23 = wave_sum32(cnt[2] | (cnt[3] << 16));
 #pragma unroll
             for (int q = 0; q < 4; q++) {
-                const uint32_t tq = wave_sum32(cnt[q]);
+                const uint32_t tq = ((q < 2 ? t01 : t23) >> (16 * (q & 1))) & 0xFFFFu;
                 if (lane == 0) {
                     rec->dt[q] = (uint32_t)dt0_r[q >> 1] + (uint32_t)(q & 1);
                     rec->cnt[q] = tq;
@@ -1220,7 +1226,7 @@ __device__ __forceinline__ void flush_split_recs(const LevelArgs &a, const Split
     }
     if (first_dt) atomicAdd(&a.tile_ones_next[dt], sum_dt);
     if (first_ch) {
-        unsigned long long *ones_next = a.ones_next + (t0 % a.slots_next) * a.nodes_next;
+        unsigned long long *ones_next = a.ones_next + (t0 & (a.slots_next - 1)) * a.nodes_next;
         atomicAdd(&ones_next[child], (unsigned long long)sum_ch);
     }
 }
