@@ -41,8 +41,11 @@ static hipEvent_t prof_event() {
         g_event_pool.pop_back();
         return e;
     }
+    // Timing only, on the device: without the system-scope fence a record
+    // costs no cache writeback and invalidate, which would otherwise stall
+    // the stream for several microseconds at every record.
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
@@ -495,11 +498,16 @@ static BatchJob make_job(const Layout &L, const void *S, void *tree, uint8_t *wo
 // S is read in buffers of b symbols; each becomes a partial tree in the
 // workspace, built with a tiled geometry so that its last-level node tables
 // (the leaf offsets of the buffer) are left in the partial workspace.
+// Staging slots of the buffered build: the copy of buffer q + kStages waits
+// until the partial build of buffer q has consumed slot q % kStages, so the
+// copies can run that many buffers ahead of the builds.
+constexpr int kStages = 4;
+
 struct BufPlan {
     Layout L;          // the final tree
     Layout Lb, Llast;  // a full partial tree and the last (ragged) one
     uint64_t b, nbuf;
-    uint64_t stage_bytes, off_stage[2], off_pwork, off_ptrees, pstride, off_C, off_csum, off_span, row, wg_per_level;
+    uint64_t stage_bytes, off_stage[kStages], off_pwork, off_ptrees, pstride, off_C, off_csum, off_span, row, wg_per_level;
     uint64_t work_bytes;
 };
 
@@ -525,10 +533,10 @@ static int plan_buffered(const wt_desc *d, uint64_t b, BufPlan *P) {
     make_layout_geom(d->n - (P->nbuf - 1) * P->b, d->sigma, d->width, g, &P->Llast);
     const uint32_t l = P->L.levels;
     uint64_t off = 0;
-    P->off_stage[0] = off;
-    off += P->stage_bytes;
-    P->off_stage[1] = off;
-    off += P->stage_bytes;
+    for (int s = 0; s < kStages; s++) {
+        P->off_stage[s] = off;
+        off += P->stage_bytes;
+    }
     P->off_pwork = off;
     off += P->Lb.work_bytes;
     P->pstride = round_up(P->Lb.tree_bytes, 256);
@@ -559,9 +567,9 @@ static hipStream_t copy_stream() {
     return streams[dev];
 }
 
-// Copies buffer q of S into staging slot q & 1 (on the copy stream) and
-// builds its partial tree on `st`.  Double buffered: the copy of buffer q + 2
-// waits until the build of buffer q has consumed the slot.
+// Copies buffer q of S into staging slot q % kStages (on the copy stream)
+// and builds its partial tree on `st`; the copy of buffer q + kStages waits
+// until the build of buffer q has consumed the slot.
 static hipError_t enqueue_buffered(const uint8_t *S, const BufPlan &P, uint8_t *tree, uint8_t *work, hipStream_t st) {
     const uint64_t w = P.L.width;
     if (P.nbuf == 1) {
@@ -579,9 +587,10 @@ static hipError_t enqueue_buffered(const uint8_t *S, const BufPlan &P, uint8_t *
     }
     hipStream_t cs = copy_stream();
     if (!cs) return hipErrorInvalidValue;
-    hipEvent_t ev[5] = {};  // start, copied[2], used[2]
+    constexpr int kEv = 1 + 2 * kStages;  // start, copied[kStages], used[kStages]
+    hipEvent_t ev[kEv] = {};
     hipError_t err = hipSuccess;
-    for (int e = 0; e < 5 && err == hipSuccess; e++) err = hipEventCreateWithFlags(&ev[e], hipEventDisableTiming);
+    for (int e = 0; e < kEv && err == hipSuccess; e++) err = hipEventCreateWithFlags(&ev[e], hipEventDisableTiming);
     const uint32_t l = P.L.levels;
     unsigned long long *C = reinterpret_cast<unsigned long long *>(work + P.off_C);
     uint8_t *pwork = work + P.off_pwork;
@@ -589,11 +598,11 @@ static hipError_t enqueue_buffered(const uint8_t *S, const BufPlan &P, uint8_t *
     if (err == hipSuccess) err = hipStreamWaitEvent(cs, ev[0], 0);
     uint64_t copied = 0;  // buffers whose copy was enqueued
     for (uint64_t q = 0; q < P.nbuf && err == hipSuccess; q++) {
-        const int s = (int)(q & 1);
+        const int s = (int)(q % kStages);
         const Layout &Lq = (q + 1 == P.nbuf) ? P.Llast : P.Lb;
         uint8_t *stage = work + P.off_stage[s];
         uint8_t *ptree = work + P.off_ptrees + q * P.pstride;
-        if (q >= 2) err = hipStreamWaitEvent(cs, ev[3 + s], 0);
+        if (q >= kStages) err = hipStreamWaitEvent(cs, ev[1 + kStages + s], 0);
         if (err == hipSuccess) err = hipMemcpyAsync(stage, S + q * P.b * w, Lq.n * w, hipMemcpyDefault, cs);
         if (err == hipSuccess) copied = q + 1;
         if (err == hipSuccess) err = hipEventRecord(ev[1 + s], cs);
@@ -603,7 +612,7 @@ static hipError_t enqueue_buffered(const uint8_t *S, const BufPlan &P, uint8_t *
             err = launch_leaf_prefix(reinterpret_cast<const uint64_t *>(pwork + Lq.ws_start) + start_offset(l - 1),
                                      reinterpret_cast<const ulonglong2 *>(pwork + Lq.ws_zo) + zo_offset(l - 1), l, Lq.n,
                                      C + q * P.row, st);
-        if (err == hipSuccess && q + 2 < P.nbuf) err = hipEventRecord(ev[3 + s], st);
+        if (err == hipSuccess && q + kStages < P.nbuf) err = hipEventRecord(ev[1 + kStages + s], st);
     }
     if (err == hipSuccess) {
         MergeArgs a;
@@ -634,12 +643,12 @@ static hipError_t enqueue_buffered(const uint8_t *S, const BufPlan &P, uint8_t *
     // S has been read once every enqueued copy is done; every event recorded
     // above is complete by then, so they can be released.
     if (copied) {
-        hipError_t e2 = hipEventSynchronize(ev[1 + (int)((copied - 1) & 1)]);
+        hipError_t e2 = hipEventSynchronize(ev[1 + (int)((copied - 1) % kStages)]);
         if (err == hipSuccess) err = e2;
     } else {
         (void)hipStreamSynchronize(cs);
     }
-    for (int e = 0; e < 5; e++)
+    for (int e = 0; e < kEv; e++)
         if (ev[e]) (void)hipEventDestroy(ev[e]);
     return err;
 }
