@@ -337,6 +337,12 @@ __device__ __forceinline__ unsigned long long plan_chunk(const PlanArgs &a, cons
         loc[q] = (k0 + q < a.nodes) ? ov[k0 + q - b0] : 0ull;
         tsum += loc[q];
     }
+    // the thread's start entries, all loaded before the first table store
+    // (the stores may alias them, which would serialise one load per node)
+    uint64_t snext[kScanChunk / kThreads];
+    const uint64_t s_first = (k0 < a.nodes) ? a.start[k0] : 0ull;
+#pragma unroll
+    for (uint64_t q = 0; q < per; q++) snext[q] = (k0 + q < a.nodes) ? a.start[k0 + q + 1] : 0ull;
     unsigned long long tot;
     unsigned long long o1 = block_excl_scan64(tsum, s_w, &tot) + before;
 #pragma unroll
@@ -344,10 +350,10 @@ __device__ __forceinline__ unsigned long long plan_chunk(const PlanArgs &a, cons
         const uint64_t v = k0 + q;
         if (v < a.nodes) {
             const unsigned long long ones = loc[q];
-            const uint64_t s_next = a.start[v + 1];
+            const uint64_t s_next = snext[q];
             a.zo[v] = make_ulonglong2(o1, s_next - ones - o1);
             if (a.start_next && !a.matrix) {
-                a.start_next[2 * v] = a.start[v];
+                a.start_next[2 * v] = (q == 0) ? s_first : snext[q - 1];
                 a.start_next[2 * v + 1] = s_next - ones;
             }
             o1 += ones;
@@ -435,12 +441,12 @@ __device__ __forceinline__ unsigned long long slot_sum(const unsigned long long 
                                                        uint64_t slots, uint64_t v, uint64_t g, uint64_t step) {
     unsigned long long c = 0;
     uint64_t q = g;
-    for (; q + 7 * step < slots; q += 8 * step) {
-        unsigned long long x[8];
+    for (; q + 15 * step < slots; q += 16 * step) {
+        unsigned long long x[16];
 #pragma unroll
-        for (int r = 0; r < 8; r++) x[r] = ones[(q + r * step) * nodes + v];
+        for (int r = 0; r < 16; r++) x[r] = ones[(q + r * step) * nodes + v];
 #pragma unroll
-        for (int r = 0; r < 8; r++) c += x[r];
+        for (int r = 0; r < 16; r++) c += x[r];
     }
     for (; q < slots; q += step) c += ones[q * nodes + v];
     return c;
