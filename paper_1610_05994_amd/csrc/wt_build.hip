@@ -267,15 +267,14 @@ __device__ __forceinline__ uint32_t chunk_bit_count(const uint4 &v, uint32_t sh2
            __popc((v.w >> sh2) & lowbits);
 }
 
-// One tile of the ingest pass, run by one wave: returns the tile's level-0
-// ones (when they are counted) and sets bad if a symbol is >= sigma.
+// One tile of the ingest pass, run by one wave, from its loaded symbols:
+// returns the tile's level-0 ones (when they are counted) and sets bad if a
+// symbol is >= sigma.
 template <int W, int B>
-__device__ __forceinline__ uint32_t ingest_tile(const IngestArgs &a, uint64_t t, bool &bad) {
+__device__ __forceinline__ uint32_t ingest_tile(const IngestArgs &a, uint64_t t, const uint4 (&raw)[B / 16], int nval,
+                                                bool &bad) {
     constexpr int E = B / W;
-    constexpr uint64_t TILE = tile_syms(W, B);
     const int lane = threadIdx.x & 63;
-    uint4 raw[B / 16];
-    const int nval = load_lane<W, B>(a.S, t * TILE + (uint64_t)lane * E, a.n, raw);
     if (a.check) {
 #pragma unroll
         for (int k = 0; k < E; k++) bad |= (k < nval) && (raw_elem<W, B>(raw, k) >= a.sigma);
@@ -308,9 +307,21 @@ __global__ __launch_bounds__(kThreads) void k_ingest(IngestArgs a) {
     // this workgroup's tiles: [t0, t1); wave wv takes every kWaves-th one
     const uint64_t t0 = (uint64_t)blockIdx.x * a.tiles_per_block;
     const uint64_t t1 = (t0 + a.tiles_per_block < a.ntiles) ? t0 + a.tiles_per_block : a.ntiles;
+    // two tiles per step, both loaded before either is counted, so that a
+    // wave keeps two tiles' loads in flight
+    constexpr int E = B / W;
+    constexpr uint64_t TILE = tile_syms(W, B);
+    const uint64_t lofs = (uint64_t)(threadIdx.x & 63) * E;
     bool bad = false;
     unsigned long long ones_acc = 0;
-    for (uint64_t t = t0 + wv; t < t1; t += kWaves) ones_acc += ingest_tile<W, B>(a, t, bad);
+    for (uint64_t t = t0 + wv; t < t1; t += 2 * kWaves) {
+        const uint64_t u = t + kWaves;
+        uint4 ra[B / 16], rb[B / 16];
+        const int na = load_lane<W, B>(a.S, t * TILE + lofs, a.n, ra);
+        const int nb = (u < t1) ? load_lane<W, B>(a.S, u * TILE + lofs, a.n, rb) : 0;
+        ones_acc += ingest_tile<W, B>(a, t, ra, na, bad);
+        if (u < t1) ones_acc += ingest_tile<W, B>(a, u, rb, nb, bad);
+    }
     ingest_finish(a, bad, ones_acc, (uint64_t)blockIdx.x * kWaves + wv);
 }
 
@@ -1358,7 +1369,9 @@ __global__ __launch_bounds__(kThreads) void k_batch_ingest(BatchClass c) {
     const uint64_t t = blk * kWaves + wv;
     if (t >= j.ntiles) return;  // whole wave
     bool bad = false;
-    const uint32_t ones = ingest_tile<W, B>(a, t, bad);
+    uint4 raw[B / 16];
+    const int nval = load_lane<W, B>(a.S, t * tile_syms(W, B) + (uint64_t)(threadIdx.x & 63) * (B / W), a.n, raw);
+    const uint32_t ones = ingest_tile<W, B>(a, t, raw, nval, bad);
     ingest_finish(a, bad, ones, t);
 }
 
