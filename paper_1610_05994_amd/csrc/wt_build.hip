@@ -223,8 +223,71 @@ __device__ __forceinline__ typename MaskT<B / W>::T level_bits(const uint4 (&raw
     return mb;
 }
 
+// u8 level bits in "spread" order, without multiplies: dword q of a lane
+// holds symbols 4q..4q+3 in its bytes m = 0..3; bit sh of byte m lands on
+// bit 8m + (q mod 8) of the 32-bit half q / 8 (a rotation by sh - q mod 8
+// brings every byte's level bit to that column at once, one mask keeps
+// them).  Two full-rate operations per dword.
+template <int B>
+__device__ __forceinline__ typename MaskT<B>::T level_bits_spread(const uint4 (&raw)[B / 16], uint32_t sh) {
+    typedef typename MaskT<B>::T M;
+    constexpr int D = B / 4;
+    uint32_t h[(D + 7) / 8];
+#pragma unroll
+    for (int i = 0; i < (D + 7) / 8; i++) h[i] = 0;
+#pragma unroll
+    for (int q = 0; q < D; q++) {
+        const uint4 &c = raw[q / 4];
+        const uint32_t d = (q % 4 == 0) ? c.x : (q % 4 == 1) ? c.y : (q % 4 == 2) ? c.z : c.w;
+        const uint32_t r = (uint32_t)(q % 8);
+        h[q / 8] |= __builtin_amdgcn_alignbit(d, d, (sh - r) & 31u) & (0x01010101u << r);
+    }
+    M m = h[0];
+#pragma unroll
+    for (int i = 1; i < (D + 7) / 8; i++) m |= (M)h[i] << (32 * i);
+    return m;
+}
+
+// A lane's level bits for the split: the spread order for u8, else the
+// symbol order.
+template <int W, int B>
+__device__ __forceinline__ typename MaskT<B / W>::T level_bits_split(const uint4 (&raw)[B / 16], uint32_t sh) {
+    if constexpr (W == 1) return level_bits_spread<B>(raw, sh);
+    else return level_bits<W, B>(raw, sh);
+}
+
+// Bit of symbol k of a lane in the split's order.
+template <int W>
+__host__ __device__ constexpr int level_bit_pos(int k) {
+    return (W == 1) ? 32 * (k / 32) + 8 * (k % 4) + (k % 32) / 4 : k;
+}
+
+// Spread order -> symbol order in each 32-bit half: bit 8m + r moves to
+// 4r + m (a 4 x 8 bit-matrix transpose), as four exchanges of index bits
+// (4 <-> 2, 3 <-> 1, 2 <-> 0, 1 <-> 0), each one delta swap.
+__device__ __forceinline__ uint32_t spread_half_order(uint32_t x) {
+    uint32_t t;
+    t = ((x >> 12) ^ x) & 0x0000F0F0u;
+    x ^= t ^ (t << 12);
+    t = ((x >> 6) ^ x) & 0x00CC00CCu;
+    x ^= t ^ (t << 6);
+    t = ((x >> 3) ^ x) & 0x0A0A0A0Au;
+    x ^= t ^ (t << 3);
+    t = ((x >> 1) ^ x) & 0x22222222u;
+    x ^= t ^ (t << 1);
+    return x;
+}
+
+template <typename M>
+__device__ __forceinline__ M spread_order(M m) {
+    if (sizeof(M) == 8)
+        return (M)spread_half_order((uint32_t)m) | ((M)spread_half_order((uint32_t)((uint64_t)m >> 32)) << 32);
+    return (M)spread_half_order((uint32_t)m);
+}
+
 // Stable split of one lane's symbols into LDS: zeros to zc, zc+1, ...,
-// ones to oc, oc+1, ...  kFull: all E symbols are valid (no guards).
+// ones to oc, oc+1, ...  kFull: all E symbols are valid (no guards).  The
+// level bits come in the order of level_bit_pos.
 template <int W, int B, bool kFull>
 __device__ __forceinline__ void stage_split(typename ElemT<W>::T *s_stage, const uint4 (&raw)[B / 16],
                                             typename MaskT<B / W>::T mb, uint32_t zc, uint32_t oc, int nval) {
@@ -240,7 +303,7 @@ __device__ __forceinline__ void stage_split(typename ElemT<W>::T *s_stage, const
 #pragma unroll
     for (int k = 0; k < E; k++) {
         if (kFull || k < nval) {
-            const uint32_t b = (uint32_t)(mb >> k) & 1u;
+            const uint32_t b = (uint32_t)(mb >> level_bit_pos<W>(k)) & 1u;
             const int q = (k * W) >> 2;
             const uint4 &c = raw[q / 4];
             const uint32_t d = (q % 4 == 0) ? c.x : (q % 4 == 1) ? c.y : (q % 4 == 2) ? c.z : c.w;
@@ -282,7 +345,7 @@ __device__ __forceinline__ uint32_t ingest_tile(const IngestArgs &a, uint64_t t,
     uint32_t ones = 0;
     if (a.tile_ones0) {
         // symbols past n load as 0, so they add no ones
-        const typename MaskT<E>::T mb = level_bits<W, B>(raw, a.msb);
+        const typename MaskT<E>::T mb = level_bits_split<W, B>(raw, a.msb);  // (any order for a count)
         ones = wave_sum32((E == 64) ? (uint32_t)__popcll((uint64_t)mb) : (uint32_t)__popc((uint32_t)mb));
         if (lane == 0) a.tile_ones0[t] = ones;
     }
@@ -968,8 +1031,11 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
     }
     unsigned long long prefix = a.sup[t / kSup];
 
-    const M mb = level_bits<W, B>(raw, sh);
-    const uint32_t pc = (E == 64) ? (uint32_t)__popcll((uint64_t)mb) : (uint32_t)__popc((uint32_t)mb);
+    // u8: the split reads the spread order, everything else the symbol order
+    const M ms = level_bits_split<W, B>(raw, sh);
+    M mb = ms;
+    if constexpr (W == 1) mb = spread_order(ms);
+    const uint32_t pc = (E == 64) ? (uint32_t)__popcll((uint64_t)ms) : (uint32_t)__popc((uint32_t)ms);
     const uint32_t incl = wave_incl_scan(pc);
     const uint32_t agg = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     prefix += wave_sum32(pv);
@@ -1060,8 +1126,8 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         const uint32_t a1 = r1 + (uint32_t)(g1 % CH);
         const uint32_t zc = a0 + (uint32_t)lane * E - lr1;  // first zero slot of this lane
         const uint32_t oc = a1 + lr1;                       // first one slot of this lane
-        if (full) stage_split<W, B, true>(s_stage, raw, mb, zc, oc, nval);
-        else stage_split<W, B, false>(s_stage, raw, mb, zc, oc, nval);
+        if (full) stage_split<W, B, true>(s_stage, raw, ms, zc, oc, nval);
+        else stage_split<W, B, false>(s_stage, raw, ms, zc, oc, nval);
         wave_sync();
         // Write the two runs out (zeros at slots [a0, a0+Z) -> g0.., ones at
         // [a1, a1+O) -> g1..); the slot and destination phases agree, so
