@@ -1283,34 +1283,38 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
 
 
 // After the workgroup's tiles: add up the single-node tiles' records by
-// destination tile and by child node, one atomic per distinct key.
+// destination tile and by child node, one atomic per distinct key (the
+// record with the lowest index adds the key's total).  Wave 0 does it with
+// all its lanes: lane r + 16 g compares record r with the four records of
+// wave g, and the four partial results of record r meet by two lane
+// exchanges.  A partial result travels packed: the counts of the matching
+// records (each below 2^16, so 16 of them stay below 2^24) plus, from bit
+// 24, how many of them come before record r.
 __device__ __forceinline__ void flush_split_recs(const LevelArgs &a, const SplitRec *recs, uint64_t t0) {
+    static_assert(kWaves == 4, "16 records, four per wave, over the 64 lanes of wave 0");
     __syncthreads();
-    const uint32_t r = threadIdx.x;
-    if (r >= 4 * kWaves || a.tile_ones_next == nullptr) return;
+    if (threadIdx.x >= 64 || a.tile_ones_next == nullptr) return;
+    const uint32_t lane = threadIdx.x, r = lane & 15, g = lane >> 4;
     const uint32_t w = r / 4, q = r % 4;
     const uint32_t c = recs[w].cnt[q];
-    if (c == 0) return;
     const uint32_t dt = recs[w].dt[q], child = a.matrix ? 0u : recs[w].child + (q >> 1);
-    uint32_t sum_dt = 0, sum_ch = 0;
-    bool first_dt = true, first_ch = true;
-    for (uint32_t r2 = 0; r2 < 4 * kWaves; r2++) {
-        const uint32_t w2 = r2 / 4, q2 = r2 % 4;
-        const uint32_t c2 = recs[w2].cnt[q2];
-        if (c2 == 0) continue;
-        if (recs[w2].dt[q2] == dt) {
-            sum_dt += c2;
-            if (r2 < r) first_dt = false;
-        }
-        if ((a.matrix ? 0u : recs[w2].child + (q2 >> 1)) == child) {
-            sum_ch += c2;
-            if (r2 < r) first_ch = false;
-        }
+    uint32_t pdt = 0, pch = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; j++) {
+        const uint32_t c2 = recs[g].cnt[j];  // records with no count carry no key
+        const uint32_t before = (4 * g + j < r) ? (1u << 24) : 0u;
+        if (c2 != 0 && recs[g].dt[j] == dt) pdt += c2 + before;
+        if (c2 != 0 && (a.matrix ? 0u : recs[g].child + (j >> 1)) == child) pch += c2 + before;
     }
-    if (first_dt) atomicAdd(&a.tile_ones_next[dt], sum_dt);
-    if (first_ch) {
+    pdt += __shfl_xor(pdt, 16, 64);
+    pch += __shfl_xor(pch, 16, 64);
+    pdt += __shfl_xor(pdt, 32, 64);
+    pch += __shfl_xor(pch, 32, 64);
+    if (g != 0 || c == 0) return;
+    if ((pdt >> 24) == 0) atomicAdd(&a.tile_ones_next[dt], pdt & 0xFFFFFFu);
+    if ((pch >> 24) == 0) {
         unsigned long long *ones_next = a.ones_next + (t0 & (a.slots_next - 1)) * a.nodes_next;
-        atomicAdd(&ones_next[child], (unsigned long long)sum_ch);
+        atomicAdd(&ones_next[child], (unsigned long long)(pch & 0xFFFFFFu));
     }
 }
 
