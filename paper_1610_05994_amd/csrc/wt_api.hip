@@ -216,9 +216,21 @@ static int digit_level(const Layout &L, uint32_t i) {  // -1: pass i emits no di
     return (int)((i + pad) / 2);
 }
 
+// Whether the last level of a build is folded into the pass before it:
+// binary u8 trees whose level l-2 pass runs the plain kernel variant (whose
+// split paths can emit bits).  The pass then writes the last level's bitmap
+// directly, T_{l-1} is never written, the last pass is not run, and the
+// last directory comes from the bitmap.  Not for partial trees of a
+// buffered build, whose last-level node tables the merge reads.
+static bool fold_last_level(const Layout &L, bool partial) {
+    const uint32_t l = L.levels;
+    return !partial && !L.matrix && L.arity != 4 && L.width == 1 && l >= 2 && L.n > 0 &&
+           !level_multi(L.n, l - 2, L.width, L.lane_bytes);
+}
+
 // Enqueue every kernel of one build.  Arguments are already validated.
-static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, uint8_t *work,
-                                hipStream_t st) {
+static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, uint8_t *work, hipStream_t st,
+                                bool partial = false) {
     const uint32_t l = L.levels;
     if (L.small) {
         long pr = prof_begin(st, "small", 0, L.width, L.n, L.n * L.width + (L.words + L.rank_stride) * 8 * l);
@@ -238,9 +250,14 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
     uint64_t *partials = reinterpret_cast<uint64_t *>(work + L.ws_partials);
 
     const bool four = L.arity == 4;
-    long pr = prof_begin(st, "zero", 0, L.width, L.n, L.ws_ctrl_bytes);
-    hipError_t err = launch_zero(work + L.ws_ctrl, L.ws_ctrl_bytes, tree_status,
-                                 (L.n == 0 && !four) ? ranks : nullptr, (uint64_t)l * L.rank_stride, st);
+    const bool fold = fold_last_level(L, partial);
+    uint64_t *bits_last = fold ? bits + (uint64_t)(l - 1) * L.words : nullptr;  // zeroed: the fold ORs into it
+    long pr = prof_begin(st, "zero", 0, L.width, L.n, L.ws_ctrl_bytes + (fold ? L.words * 8 : 0));
+    hipError_t err = (L.n == 0 && !four)
+                         ? launch_zero(work + L.ws_ctrl, L.ws_ctrl_bytes, tree_status, ranks,
+                                       (uint64_t)l * L.rank_stride, st)
+                         : launch_zero(work + L.ws_ctrl, L.ws_ctrl_bytes, tree_status, bits_last,
+                                       fold ? L.words : 0, st);
     prof_end(pr, st);
     if (err == hipSuccess && L.n == 0 && L.matrix && l)  // the zeros of an empty matrix
         err = launch_zero(tree + kZerosOff, (uint64_t)l * 8, tree_status, nullptr, 0, st);
@@ -271,7 +288,7 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
     if (l == 0) return hipSuccess;
 
     uint8_t *tbuf[2] = {work + L.ws_ta, work + L.ws_tb};
-    const uint32_t lrun = four ? multiary_passes(L) : l;  // binary passes to run
+    const uint32_t lrun = four ? multiary_passes(L) : (fold ? l - 1 : l);  // binary passes to run
     for (uint32_t i = 0; i < lrun; i++) {
         PlanArgs pa;
         pa.start = start + start_offset(i);
@@ -332,14 +349,29 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         a.symmask = (uint32_t)((1ull << l) - 1);
         a.matrix = L.matrix;
         a.zeros = L.matrix ? reinterpret_cast<unsigned long long *>(tree + kZerosOff) : nullptr;
+        a.bits_next = (fold && i + 1 == lrun) ? bits_last : nullptr;  // (then tout is null)
         const uint64_t lbytes = L.n * L.width * (a.tout ? 2 : 1) + (a.bits ? L.words * 8 + L.rank_stride * 8 : 0) +
-                                (a.digits ? L.dwords * 8 : 0);
+                                (a.digits ? L.dwords * 8 : 0) + (a.bits_next ? L.words * 8 : 0);
         pr = prof_begin(st, "level", i, L.width, L.n, lbytes);
         err = launch_level(a, L.width, L.lane_bytes, !L.matrix && level_multi(L.n, i, L.width, L.lane_bytes), st);
         prof_end(pr, st);
         if (err != hipSuccess) return err;
     }
-    return hipSuccess;
+    if (fold) {
+        // the last level's directory from its bitmap; the partial sums use
+        // that level's tile-count slot, which the folded pass leaves unused
+        BitDirArgs d;
+        d.bits = bits_last;
+        d.ranks = ranks + (uint64_t)(l - 1) * L.rank_stride;
+        d.wsum = reinterpret_cast<unsigned long long *>(tile_ones + (uint64_t)(l - 1) * tile_stride(L.ntiles));
+        d.nblk = L.rank_entries - 1;
+        d.nwg = ceil_div(d.nblk, kBitDirBlocks);
+        d.rank_stride = L.rank_stride;
+        pr = prof_begin(st, "bitdir", l - 1, L.width, L.n, L.words * 8 + L.rank_stride * 8);
+        err = launch_bitdir(d, st);
+        prof_end(pr, st);
+    }
+    return err;
 }
 
 // A 4-ary build: the binary passes with digit emission, then the digit
@@ -607,7 +639,7 @@ static hipError_t enqueue_buffered(const uint8_t *S, const BufPlan &P, uint8_t *
         if (err == hipSuccess) copied = q + 1;
         if (err == hipSuccess) err = hipEventRecord(ev[1 + s], cs);
         if (err == hipSuccess) err = hipStreamWaitEvent(st, ev[1 + s], 0);
-        if (err == hipSuccess) err = enqueue_build(stage, Lq, ptree, pwork, st);
+        if (err == hipSuccess) err = enqueue_build(stage, Lq, ptree, pwork, st, true);
         if (err == hipSuccess && l)
             err = launch_leaf_prefix(reinterpret_cast<const uint64_t *>(pwork + Lq.ws_start) + start_offset(l - 1),
                                      reinterpret_cast<const ulonglong2 *>(pwork + Lq.ws_zo) + zo_offset(l - 1), l, Lq.n,

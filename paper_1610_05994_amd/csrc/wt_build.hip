@@ -173,13 +173,25 @@ __device__ __forceinline__ int load_lane(const void *src, uint64_t pos, uint64_t
 
 // ------------------------------------------------------------- zero fill --
 
-__global__ void k_zero(uint64_t *p, uint64_t words, uint32_t *tree_status, uint64_t *tree_ranks,
-                       uint64_t tree_ranks_count) {
+// Zeroes `words` 8-byte words at p (8-byte aligned): a leading word when p
+// is not 16-byte aligned, then two words per store, then a trailing word.
+__device__ __forceinline__ void zero_words(uint64_t *p, uint64_t words) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < words; k += stride) p[k] = 0;
-    if (tree_ranks)
-        for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < tree_ranks_count; k += stride)
-            tree_ranks[k] = 0;
+    if (words && ((uintptr_t)p & 15u)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) p[0] = 0;
+        p++;
+        words--;
+    }
+    const uint64_t pairs = words / 2;
+    ulonglong2 *q = reinterpret_cast<ulonglong2 *>(p);
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < pairs; k += stride)
+        q[k] = make_ulonglong2(0ull, 0ull);
+    if ((words & 1) && blockIdx.x == 0 && threadIdx.x == 0) p[words - 1] = 0;
+}
+
+__global__ void k_zero(uint64_t *p, uint64_t words, uint32_t *tree_status, uint64_t *p2, uint64_t count2) {
+    zero_words(p, words);
+    if (p2) zero_words(p2, count2);
     if (blockIdx.x == 0 && threadIdx.x == 0) *tree_status = 0;
 }
 
@@ -283,6 +295,26 @@ __device__ __forceinline__ M spread_order(M m) {
     if (sizeof(M) == 8)
         return (M)spread_half_order((uint32_t)m) | ((M)spread_half_order((uint32_t)((uint64_t)m >> 32)) << 32);
     return (M)spread_half_order((uint32_t)m);
+}
+
+// Bit sh of the 16 u8 symbols of a 16-byte chunk, symbol k at bit k.  The
+// spread gather puts symbol 4j + b at bit 8b + j; folding each byte pair
+// into one byte and keeping bytes 0 and 2 leaves it at bit 4b + j, and two
+// delta swaps (index bits 3 <-> 1, 2 <-> 0) transpose that 4 x 4 matrix.
+__device__ __forceinline__ uint32_t chunk_bits16(const uint4 &v, uint32_t sh) {
+    uint32_t h = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint32_t d = (j == 0) ? v.x : (j == 1) ? v.y : (j == 2) ? v.z : v.w;
+        h |= __builtin_amdgcn_alignbit(d, d, (sh - (uint32_t)j) & 31u) & (0x01010101u << j);
+    }
+    const uint32_t f = h | (h >> 4);
+    uint32_t x = (f & 0xFFu) | ((f >> 8) & 0xFF00u);
+    uint32_t t = ((x >> 6) ^ x) & 0x00CCu;
+    x ^= t ^ (t << 6);
+    t = ((x >> 3) ^ x) & 0x0A0Au;
+    x ^= t ^ (t << 3);
+    return x;
 }
 
 // Stable split of one lane's symbols into LDS: zeros to zc, zc+1, ...,
@@ -1090,7 +1122,11 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         }
     }
 
-    if (a.tout == nullptr) return;  // last level: no next order, no counts
+    // folded last level (u8, single-node and direct paths only): bits of
+    // T_{i+1} instead of its symbols
+    uint32_t *bnext = reinterpret_cast<uint32_t *>(a.bits_next);
+    const bool fold = (W == 1) && !kMulti && bnext != nullptr;
+    if (a.tout == nullptr && !fold) return;  // last level: no next order, no counts
 
     // node span of the tile (T_i is sorted by node)
     const bool full = (nvalid == TILE);  // every tile but a ragged last one
@@ -1114,7 +1150,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
     const bool counting = a.tile_ones_next != nullptr;
     const uint32_t sh2 = sh - 1;  // bit of the next level (when counting)
     // (slot counts are powers of two)
-    unsigned long long *ones_next = a.ones_next + (t & (a.slots_next - 1)) * a.nodes_next;
+    unsigned long long *ones_next = counting ? a.ones_next + (t & (a.slots_next - 1)) * a.nodes_next : nullptr;
     if (vf == vl) {
         // Single node: zeros keep their order at g0.., ones at g1...
         const ulonglong2 zo = a.zo[vf];
@@ -1170,7 +1206,10 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
                 const uint32_t s = c * CH;
                 const uint4 v = *reinterpret_cast<const uint4 *>(&s_stage[s]);
                 if (inside || gb + s + CH <= a.n) {
-                    *reinterpret_cast<uint4 *>(tout + (gb + s)) = v;
+                    if (fold)  // 16 bits at a multiple of 16
+                        reinterpret_cast<uint16_t *>(bnext)[(gb + s) >> 4] = (uint16_t)chunk_bits16(v, sh2);
+                    else
+                        *reinterpret_cast<uint4 *>(tout + (gb + s)) = v;
                     const uint32_t ones = __popc(v.x & mk) + __popc(v.y & mk) + __popc(v.z & mk) + __popc(v.w & mk);
                     const bool second = c >= cs;
                     cnt[2 * r] += second ? 0u : ones;
@@ -1194,9 +1233,18 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
                 const uint64_t d = gb + s;
                 if (s >= lo && s < lo + len && d < a.n) {
                     const uint32_t x = (uint32_t)s_stage[s];
-                    tout[d] = (T)x;
+                    if (!fold) tout[d] = (T)x;
                     one = (x >> sh2) & 1u;
                     second = c >= cs;
+                }
+            }
+            if (fold) {
+                // the 16 lanes of a partial chunk hold its slots in order:
+                // their ones go in with one OR (other runs share the word)
+                const uint32_t grp = (uint32_t)(__ballot(one != 0) >> (lane & 48)) & 0xFFFFu;
+                if (e == 0 && grp != 0) {
+                    const uint64_t p0 = gb + (uint64_t)c * CH;  // a multiple of 16
+                    atomicOr(&bnext[p0 >> 5], grp << (uint32_t)(p0 & 16));
                 }
             }
             if (counting) {
@@ -1253,7 +1301,8 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
             const uint64_t dst = b ? zo.y + r1 : p - r1 + zo.x;
             r1 += b;
             if (dst < a.n) {
-                tout[dst] = (T)x;
+                if (!fold) tout[dst] = (T)x;
+                else if ((x >> sh2) & 1u) atomicOr(&bnext[dst >> 5], 1u << (uint32_t)(dst & 31));
                 if (counting && ((x >> sh2) & 1u)) {
                     const uint64_t dt = dst / TILE;
                     if (lds_counts && v - vf <= vl - vf) {
@@ -1363,6 +1412,7 @@ __device__ __forceinline__ LevelArgs job_level(const BatchJob &j, uint32_t i) {
     a.digits = nullptr;
     a.dwords = 0;
     a.dsh = 0;
+    a.bits_next = nullptr;
     return a;
 }
 
@@ -1499,13 +1549,73 @@ static inline uint32_t grid_for(uint64_t items, uint64_t per_block, uint32_t cap
     return (uint32_t)g;
 }
 
-hipError_t launch_zero(void *p, uint64_t bytes, uint32_t *tree_status, uint64_t *tree_ranks,
-                       uint64_t tree_ranks_count, hipStream_t s) {
+hipError_t launch_zero(void *p, uint64_t bytes, uint32_t *tree_status, uint64_t *p2, uint64_t count2, hipStream_t s) {
     const uint64_t words = bytes / 8;
-    const uint64_t items = words > tree_ranks_count ? words : tree_ranks_count;
+    const uint64_t items = (words > count2 ? words : count2) / 2 + 1;
     hipLaunchKernelGGL(k_zero, dim3(grid_for(items, 256, 4096)), dim3(256), 0, s, (uint64_t *)p, words,
-                       tree_status, tree_ranks, tree_ranks_count);
+                       tree_status, p2, count2);
     return hipGetLastError();
+}
+
+// ------------------------------------------------ directory of a bitmap ---
+// Used for the last level when its bitmap comes out of the pass before it:
+// k_bitdir_blocks scans the popcounts of kBitDirBlocks 512-bit blocks per
+// workgroup, k_bitdir_fix scans the workgroup sums (one workgroup) and writes
+// the total and the padding, k_bitdir_apply adds each workgroup's base.
+
+__global__ __launch_bounds__(kThreads) void k_bitdir_blocks(BitDirArgs a) {
+    __shared__ unsigned long long s_w[kWaves];
+    static_assert(kBitDirBlocks == kThreads, "one block per thread");
+    const uint64_t blk = (uint64_t)blockIdx.x * kBitDirBlocks + threadIdx.x;
+    unsigned long long c = 0;
+    if (blk < a.nblk) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(a.bits + blk * 8);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const uint4 v = p[q];
+            c += (unsigned long long)(__popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w));
+        }
+    }
+    unsigned long long tot;
+    const unsigned long long ex = block_excl_scan64(c, s_w, &tot);
+    if (blk < a.nblk) a.ranks[blk] = ex;
+    if (threadIdx.x == 0) a.wsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kThreads) void k_bitdir_fix(BitDirArgs a) {
+    __shared__ unsigned long long s_w[kWaves];
+    const uint64_t per = (a.nwg + kThreads - 1) / kThreads;
+    const uint64_t k0 = (uint64_t)threadIdx.x * per;
+    unsigned long long sum = 0;
+    for (uint64_t k = k0; k < k0 + per && k < a.nwg; k++) sum += a.wsum[k];
+    unsigned long long tot;
+    unsigned long long off = block_excl_scan64(sum, s_w, &tot);
+    for (uint64_t k = k0; k < k0 + per && k < a.nwg; k++) {
+        const unsigned long long v = a.wsum[k];
+        a.wsum[k] = off;
+        off += v;
+    }
+    for (uint64_t k = a.nblk + threadIdx.x; k < a.rank_stride; k += kThreads) a.ranks[k] = (k == a.nblk) ? tot : 0ull;
+}
+
+__global__ __launch_bounds__(kThreads) void k_bitdir_apply(BitDirArgs a) {
+    const uint64_t blk = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (blk < a.nblk) a.ranks[blk] += a.wsum[blk / kBitDirBlocks];
+}
+
+hipError_t launch_bitdir(const BitDirArgs &a, hipStream_t s) {
+    hipError_t err;
+    if (a.nblk) {
+        hipLaunchKernelGGL(k_bitdir_blocks, dim3((uint32_t)a.nwg), dim3(kThreads), 0, s, a);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+    }
+    hipLaunchKernelGGL(k_bitdir_fix, dim3(1), dim3(kThreads), 0, s, a);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if (a.nblk) {
+        hipLaunchKernelGGL(k_bitdir_apply, dim3((uint32_t)ceil_div(a.nblk, kThreads)), dim3(kThreads), 0, s, a);
+        err = hipGetLastError();
+    }
+    return err;
 }
 
 // Launch KERNEL<width, lane_bytes> (every valid pair is instantiated).

@@ -134,7 +134,24 @@ struct LevelArgs {
     uint64_t *digits;
     uint64_t dwords;
     uint32_t dsh;
+    // last level folded into this pass (u8 trees, level l-2, single-node and
+    // direct split paths only): the bitmap of level i + 1, zeroed beforehand,
+    // receives bit sh - 1 of every symbol at its T_{i+1} position, and
+    // T_{i+1} itself is not written (tout is null); null otherwise
+    uint64_t *bits_next;
 };
+
+// Rank directory of one bitmap level from its words (entry k = ones before
+// position 512k for k < nblk, entry nblk = all ones, zero padding up to
+// rank_stride); wsum holds nwg = ceil(nblk / kBitDirBlocks) partial sums.
+constexpr uint64_t kBitDirBlocks = 256;
+struct BitDirArgs {
+    const uint64_t *bits;            // words = 8 * nblk
+    uint64_t *ranks;
+    unsigned long long *wsum;
+    uint64_t nblk, nwg, rank_stride;
+};
+hipError_t launch_bitdir(const BitDirArgs &a, hipStream_t s);
 
 struct IngestArgs {
     const void *S;
@@ -203,8 +220,8 @@ __host__ __device__ inline uint64_t ones_offset(uint32_t i) {
 }
 
 // kernel launchers (wt_build.hip)
-hipError_t launch_zero(void *p, uint64_t bytes, uint32_t *tree_status, uint64_t *tree_ranks,
-                       uint64_t tree_ranks_count, hipStream_t s);
+// Zeroes `bytes` at p, count2 words at p2 (when non-null) and the status word.
+hipError_t launch_zero(void *p, uint64_t bytes, uint32_t *tree_status, uint64_t *p2, uint64_t count2, hipStream_t s);
 hipError_t launch_ingest(const IngestArgs &a, uint32_t width, uint32_t lane_bytes, hipStream_t s);
 hipError_t launch_prep(const PrepArgs &a, hipStream_t s);  // k_supsum, then k_prep
 hipError_t launch_plan(const PlanArgs &a, hipStream_t s);

@@ -94,6 +94,17 @@ def test_parity_zipf(sigma, lg):
     t.close()
 
 
+@pytest.mark.parametrize("sigma,lg", [(4, 15), (4, 17), (5, 16), (16, 17), (128, 20), (256, 21)])
+def test_parity_last_level_from_previous_pass(sigma, lg):
+    # u8 lengths around the point where the pass of level l-2 also writes the
+    # last level's bitmap (its directory then comes from that bitmap); skewed
+    # input puts node boundaries inside tiles
+    for k, n in enumerate([(1 << lg) + 12345, (1 << lg) - 77]):
+        S = wtgen.zipf(n, sigma, 1.2, 600 + 7 * k + sigma)
+        t, _ = build_and_compare(S, sigma, tag="fold")
+        t.close()
+
+
 def test_parity_gauss_mix_large_alphabet():
     S, sigma = wtgen.workload("c3@lg22")
     t, _ = build_and_compare(S, sigma, tag="c3@lg22")
