@@ -71,6 +71,24 @@ def instrumented_pass(steps, step):
     return (t1 - t0) * 1e3 / steps, recs
 
 
+def per_level_rows(lvl):
+    """Level-pass launches grouped by tree level: average duration and
+    algorithmic GB/s (a folded pass, which also writes the next level's
+    bitmap, shows as the last row with fewer bytes)."""
+    by = {}
+    for r in lvl:
+        e = by.setdefault(r["level"], [0, 0.0, 0])
+        e[0] += 1
+        e[1] += r["ms"]
+        e[2] += r["bytes"]
+    rows = []
+    for level in sorted(by):
+        k, ms, b = by[level]
+        rows.append({"level": level, "avg_us": round(ms * 1e3 / k, 2),
+                     "gbps": round(b / (ms / 1e3) / 1e9, 1) if ms > 0 else None})
+    return rows
+
+
 def load_traffic_entry(workload: str):
     """The committed rocprofv3 counter figures of a workload, or None when the
     kernel source changed since they were taken."""
@@ -337,6 +355,7 @@ def main() -> int:
             "kernel": "k_level (one launch per tree level)",
             "avg_launch_us": lvl_ms * 1e3 / max(launches, 1),
             "algorithmic_bytes_per_launch": lvl_bytes / max(launches, 1),
+            "per_level": per_level_rows(lvl),
         },
         "build_latency_ms": {"p50": p50, "p99": p99},
         "instrumented_ms_per_step": ms_instrumented,
