@@ -1290,19 +1290,46 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         wave_sync();
     }
     unsigned long long r1 = r_lane;
+    // folded: a lane's destinations rise within each of its two current runs
+    // (zeros, ones; T_i is sorted by node), so each run's bits gather in one
+    // pending word and go out with one OR when the run moves past it
+    uint64_t fw0 = ~0ull, fw1 = ~0ull;
+    uint32_t fm0 = 0u, fm1 = 0u;
+    // a lane's nodes never decrease (T_i is sorted by node): its node table
+    // entry is loaded again only where the node changes, not per symbol
+    uint32_t cv = (raw_elem<W, B>(raw, 0) & a.symmask) >> nsh;
+    ulonglong2 zo = a.zo[nval > 0 ? cv : vf];
 #pragma unroll
     for (int k = 0; k < E; k++) {
         if (k < nval) {
             const uint32_t x = raw_elem<W, B>(raw, k) & a.symmask;
             const uint32_t v = x >> nsh;
-            const ulonglong2 zo = a.zo[v];
+            if (v != cv) {
+                cv = v;
+                zo = a.zo[v];
+            }
             const uint64_t p = pos0 + k;
             const uint32_t b = (uint32_t)(mb >> k) & 1u;
             const uint64_t dst = b ? zo.y + r1 : p - r1 + zo.x;
             r1 += b;
             if (dst < a.n) {
-                if (!fold) tout[dst] = (T)x;
-                else if ((x >> sh2) & 1u) atomicOr(&bnext[dst >> 5], 1u << (uint32_t)(dst & 31));
+                if (!fold) {
+                    tout[dst] = (T)x;
+                } else {
+                    const uint64_t wi = dst >> 5;
+                    uint64_t cw = b ? fw1 : fw0;
+                    uint32_t cm = b ? fm1 : fm0;
+                    if (wi != cw) {
+                        if (cm) atomicOr(&bnext[cw], cm);
+                        cw = wi;
+                        cm = 0u;
+                    }
+                    cm |= ((x >> sh2) & 1u) << (uint32_t)(dst & 31);
+                    fw1 = b ? cw : fw1;
+                    fm1 = b ? cm : fm1;
+                    fw0 = b ? fw0 : cw;
+                    fm0 = b ? fm0 : cm;
+                }
                 if (counting && ((x >> sh2) & 1u)) {
                     const uint64_t dt = dst / TILE;
                     if (lds_counts && v - vf <= vl - vf) {
@@ -1316,6 +1343,10 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
                 }
             }
         }
+    }
+    if (fold) {
+        if (fm0) atomicOr(&bnext[fw0], fm0);
+        if (fm1) atomicOr(&bnext[fw1], fm1);
     }
     if (lds_counts) {
         wave_sync();
