@@ -150,9 +150,9 @@ int wt_multiary_levels(const wt_tree *tree, uint32_t *levels, const uint64_t **d
  * written.  The tree is the one wt_build produces (same layout and
  * queries).
  *
- * S may be host memory (page-locked memory lets the copy of one buffer
- * overlap the build of the previous one; pageable memory works too) or
- * device memory, any alignment.  The device holds two staging buffers, one
+ * S may be host memory (page-locked memory lets the copies of the next
+ * buffers overlap the build of the current one; pageable memory works too)
+ * or device memory, any alignment.  The device holds four staging buffers, one
  * partial-build workspace, the partial trees (about the size of the final
  * tree's bitmaps) and an offset table of (buffers + 1) x (2^l + 1) u64, so
  * the workspace grows with n l / 8 + (n / buffer_syms) 2^l * 8 bytes rather

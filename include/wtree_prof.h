@@ -4,8 +4,11 @@
  * For benchmarks and tests.  While profiling is on, every kernel that a
  * build enqueues (wt_build, wt_build_batch) is bracketed by two hipEvents
  * recorded on the build's own stream, so the measured time is that
- * kernel's execution on that stream.  Records accumulate in a host-side
- * list owned by the library until wt_prof_enable is called again.
+ * kernel's execution on that stream.  The events carry no system-scope
+ * fence; still, each record between two kernels idles the stream for a
+ * few microseconds, so builds timed for throughput run with profiling
+ * off.  Records accumulate in a host-side list owned by the library until
+ * wt_prof_enable is called again.
  */
 #ifndef WTREE_PROF_H
 #define WTREE_PROF_H
@@ -36,7 +39,9 @@ int wt_prof_enable(int on);
  * out (may be NULL) and stores the number of records in *count.  The
  * algorithmic bytes of a level launch are: read the level's symbols,
  * write the next level's symbols (not on the last level), write the
- * level's bitmap words and rank directory.  Returns WT_OK or WT_EDEVICE.
+ * level's bitmap words and rank directory, and, for a pass that folds in
+ * the last level, that level's bitmap words instead of its symbols.
+ * Returns WT_OK or WT_EDEVICE.
  */
 int wt_prof_read(wt_prof_rec *out, uint64_t max, uint64_t *count);
 
