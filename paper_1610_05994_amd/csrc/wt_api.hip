@@ -251,13 +251,10 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
 
     const bool four = L.arity == 4;
     const bool fold = fold_last_level(L, partial);
-    uint64_t *bits_last = fold ? bits + (uint64_t)(l - 1) * L.words : nullptr;  // zeroed: the fold ORs into it
-    long pr = prof_begin(st, "zero", 0, L.width, L.n, L.ws_ctrl_bytes + (fold ? L.words * 8 : 0));
-    hipError_t err = (L.n == 0 && !four)
-                         ? launch_zero(work + L.ws_ctrl, L.ws_ctrl_bytes, tree_status, ranks,
-                                       (uint64_t)l * L.rank_stride, st)
-                         : launch_zero(work + L.ws_ctrl, L.ws_ctrl_bytes, tree_status, bits_last,
-                                       fold ? L.words : 0, st);
+    uint64_t *bits_last = fold ? bits + (uint64_t)(l - 1) * L.words : nullptr;  // zeroed by ingest: the fold ORs into it
+    long pr = prof_begin(st, "zero", 0, L.width, L.n, L.ws_ctrl_bytes);
+    hipError_t err = launch_zero(work + L.ws_ctrl, L.ws_ctrl_bytes, tree_status,
+                                 (L.n == 0 && !four) ? ranks : nullptr, (uint64_t)l * L.rank_stride, st);
     prof_end(pr, st);
     if (err == hipSuccess && L.n == 0 && L.matrix && l)  // the zeros of an empty matrix
         err = launch_zero(tree + kZerosOff, (uint64_t)l * 8, tree_status, nullptr, 0, st);
@@ -275,13 +272,15 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
     ia.sigma = L.sigma;
     ia.check = (L.width < 4 && (uint64_t)L.sigma == (1ull << (8 * L.width))) ? 0u : 1u;
     ia.msb = l ? l - 1 : 0;
+    ia.zero_p = bits_last;
+    ia.zero_words = fold ? L.words : 0;
     {
-        // contiguous tiles per ingest workgroup: ~2048 workgroups
+        // contiguous tiles per ingest workgroup: ~8192 workgroups
         uint64_t k = kWaves;
-        while (L.ntiles > 2048 * k) k <<= 1;
+        while (L.ntiles > 8192 * k) k <<= 1;
         ia.tiles_per_block = k;
     }
-    pr = prof_begin(st, "ingest", 0, L.width, L.n, L.n * L.width);
+    pr = prof_begin(st, "ingest", 0, L.width, L.n, L.n * L.width + (fold ? L.words * 8 : 0));
     err = launch_ingest(ia, L.width, L.lane_bytes, st);
     prof_end(pr, st);
     if (err != hipSuccess) return err;

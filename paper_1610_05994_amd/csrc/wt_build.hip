@@ -418,6 +418,7 @@ __global__ __launch_bounds__(kThreads) void k_ingest(IngestArgs a) {
         if (u < t1) ones_acc += ingest_tile<W, B>(a, u, rb, nb, bad);
     }
     ingest_finish(a, bad, ones_acc, (uint64_t)blockIdx.x * kWaves + wv);
+    if (a.zero_p) zero_words(a.zero_p, a.zero_words);  // (a pass that only reads has write bandwidth to spare)
 }
 
 // ----------------------------------------------------------- node tables --
@@ -1484,6 +1485,8 @@ __device__ __forceinline__ IngestArgs job_ingest(const BatchJob &j) {
     a.sigma = j.sigma;
     a.check = j.check;
     a.msb = j.levels ? j.levels - 1 : 0;
+    a.zero_p = nullptr;
+    a.zero_words = 0;
     return a;
 }
 

@@ -161,6 +161,8 @@ struct IngestArgs {
     uint32_t *tree_status;
     uint64_t n, ntiles, tiles_per_block, slots0;
     uint32_t sigma, check, msb;
+    uint64_t *zero_p;                  // zero_words words cleared on the way (8-byte aligned), or null
+    uint64_t zero_words;
 };
 
 // Node tables of one level (see k_plan_* and k_prep).
