@@ -432,8 +432,28 @@ __global__ __launch_bounds__(kThreads) void k_ingest(IngestArgs a) {
 
 // Node tables for entries [b0, b0 + kScanChunk) given the ones before b0;
 // ov[v - b0] holds the ones of node v.  Returns the ones of the chunk.
-__device__ __forceinline__ unsigned long long plan_chunk(const PlanArgs &a, const unsigned long long *ov, uint64_t b0,
-                                                         unsigned long long before) {
+// The thread's start entries of a chunk (entries k0 .. k0 + 16 and the one
+// before), loaded together; the table stores may alias them, which would
+// otherwise serialise one load per node.
+struct ChunkStarts {
+    uint64_t first;
+    uint64_t next[kScanChunk / kThreads];
+};
+
+__device__ __forceinline__ void load_chunk_starts(const PlanArgs &a, uint64_t b0, ChunkStarts &cs) {
+    const uint64_t per = kScanChunk / kThreads;
+    const uint64_t k0 = b0 + threadIdx.x * per;
+    cs.first = (k0 < a.nodes) ? a.start[k0] : 0ull;
+#pragma unroll
+    for (uint64_t q = 0; q < per; q++) cs.next[q] = (k0 + q < a.nodes) ? a.start[k0 + q + 1] : 0ull;
+}
+
+// Node tables for entries [b0, b0 + kScanChunk) given the ones before b0 and
+// the thread's start entries; ov[v - b0] holds the ones of node v.  Returns
+// the ones of the chunk.
+__device__ __forceinline__ unsigned long long plan_chunk_with(const PlanArgs &a, const unsigned long long *ov,
+                                                              uint64_t b0, unsigned long long before,
+                                                              const ChunkStarts &cs) {
     __shared__ unsigned long long s_w[kWaves];
     const uint64_t per = kScanChunk / kThreads;  // 16 consecutive entries per thread
     const uint64_t k0 = b0 + threadIdx.x * per;
@@ -444,12 +464,6 @@ __device__ __forceinline__ unsigned long long plan_chunk(const PlanArgs &a, cons
         loc[q] = (k0 + q < a.nodes) ? ov[k0 + q - b0] : 0ull;
         tsum += loc[q];
     }
-    // the thread's start entries, all loaded before the first table store
-    // (the stores may alias them, which would serialise one load per node)
-    uint64_t snext[kScanChunk / kThreads];
-    const uint64_t s_first = (k0 < a.nodes) ? a.start[k0] : 0ull;
-#pragma unroll
-    for (uint64_t q = 0; q < per; q++) snext[q] = (k0 + q < a.nodes) ? a.start[k0 + q + 1] : 0ull;
     unsigned long long tot;
     unsigned long long o1 = block_excl_scan64(tsum, s_w, &tot) + before;
 #pragma unroll
@@ -457,10 +471,10 @@ __device__ __forceinline__ unsigned long long plan_chunk(const PlanArgs &a, cons
         const uint64_t v = k0 + q;
         if (v < a.nodes) {
             const unsigned long long ones = loc[q];
-            const uint64_t s_next = snext[q];
+            const uint64_t s_next = cs.next[q];
             a.zo[v] = make_ulonglong2(o1, s_next - ones - o1);
             if (a.start_next && !a.matrix) {
-                a.start_next[2 * v] = (q == 0) ? s_first : snext[q - 1];
+                a.start_next[2 * v] = (q == 0) ? cs.first : cs.next[q - 1];
                 a.start_next[2 * v + 1] = s_next - ones;
             }
             o1 += ones;
@@ -471,6 +485,13 @@ __device__ __forceinline__ unsigned long long plan_chunk(const PlanArgs &a, cons
         a.start_next[a.matrix ? 1 : 2 * a.nodes] = a.n;
     }
     return tot;
+}
+
+__device__ __forceinline__ unsigned long long plan_chunk(const PlanArgs &a, const unsigned long long *ov, uint64_t b0,
+                                                         unsigned long long before) {
+    ChunkStarts cs;
+    load_chunk_starts(a, b0, cs);
+    return plan_chunk_with(a, ov, b0, before, cs);
 }
 
 // Chunk b of a level's nodes: partials[b] = its ones.
@@ -565,6 +586,35 @@ __device__ __forceinline__ void prep_level(const PrepArgs &a) {
     __shared__ unsigned long long s_w[kWaves];
     __shared__ unsigned long long s_n[kScanChunk];
     const uint32_t tid = threadIdx.x;
+    if (a.nsup <= kThreads && a.plan_here && a.plan.nodes < kThreads) {
+        // A small level (every level of sequences up to 2^28 u8 symbols):
+        // the superchunk sums, the node counter slots and the start entries
+        // are all loaded up front, so the step waits for memory once.
+        const PlanArgs &p = a.plan;
+        const uint64_t cn = p.nodes, groups = kThreads / cn, v = tid % cn, g = tid / cn;
+        const unsigned long long sv = (tid < a.nsup) ? a.supsum[tid] : 0ull;
+        unsigned long long x[16];  // slots * nodes <= kSlotSpan: 16 slots per thread
+#pragma unroll
+        for (uint64_t q = 0; q < 16; q++) {
+            const uint64_t sl = g + q * groups;
+            x[q] = (sl < p.slots) ? p.ones[sl * p.nodes + v] : 0ull;
+        }
+        ChunkStarts cs;
+        load_chunk_starts(p, 0, cs);
+        unsigned long long tot;
+        const unsigned long long ex = block_excl_scan64(sv, s_w, &tot);
+        if (tid < a.nsup) a.sup[tid] = ex;
+        if (tid < cn) s_n[tid] = 0;
+        __syncthreads();
+        unsigned long long c = 0;
+#pragma unroll
+        for (uint64_t q = 0; q < 16; q++) c += x[q];
+        for (uint64_t sl = g + 16 * groups; sl < p.slots; sl += groups) c += p.ones[sl * p.nodes + v];
+        if (c) atomicAdd(&s_n[v], c);
+        __syncthreads();
+        plan_chunk_with(p, s_n, 0, 0, cs);
+        return;
+    }
     unsigned long long carry = 0;
     for (uint64_t c0 = 0; c0 < a.nsup; c0 += kThreads) {
         const uint64_t c = c0 + tid;
