@@ -316,6 +316,7 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         pp.nsup = L.nsup;
         pp.plan = pa;
         pp.plan_here = big ? 0u : 1u;
+        pp.sums_here = (L.nsup <= kPrepSups && !big && pa.nodes < kThreads) ? 1u : 0u;
         pr = prof_begin(st, "prep", i, L.width, L.n, L.ntiles * 4 + L.nsup * 16);
         err = launch_prep(pp, st);
         prof_end(pr, st);

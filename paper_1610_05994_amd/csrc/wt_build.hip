@@ -589,10 +589,18 @@ __device__ __forceinline__ void prep_level(const PrepArgs &a) {
     if (a.nsup <= kThreads && a.plan_here && a.plan.nodes < kThreads) {
         // A small level (every level of sequences up to 2^28 u8 symbols):
         // the superchunk sums, the node counter slots and the start entries
-        // are all loaded up front, so the step waits for memory once.
+        // are all loaded up front, so the step waits for memory once.  With
+        // sums_here the superchunk sums come from the tile counts directly
+        // (thread t holds tile t of every superchunk), and no k_supsum ran.
         const PlanArgs &p = a.plan;
         const uint64_t cn = p.nodes, groups = kThreads / cn, v = tid % cn, g = tid / cn;
-        const unsigned long long sv = (tid < a.nsup) ? a.supsum[tid] : 0ull;
+        uint32_t tc[kPrepSups];
+#pragma unroll
+        for (uint64_t q = 0; q < kPrepSups; q++) {
+            const uint64_t t = q * kSup + tid;
+            tc[q] = (a.sums_here && q < a.nsup && t < a.ntiles) ? a.tile_ones[t] : 0u;
+        }
+        unsigned long long sv = (!a.sums_here && tid < a.nsup) ? a.supsum[tid] : 0ull;
         unsigned long long x[16];  // slots * nodes <= kSlotSpan: 16 slots per thread
 #pragma unroll
         for (uint64_t q = 0; q < 16; q++) {
@@ -601,6 +609,22 @@ __device__ __forceinline__ void prep_level(const PrepArgs &a) {
         }
         ChunkStarts cs;
         load_chunk_starts(p, 0, cs);
+        if (a.sums_here) {
+            // superchunk q's sum: its 256 tile counts over the workgroup
+            __shared__ uint32_t s_q[kWaves][kPrepSups];
+#pragma unroll
+            for (uint64_t q = 0; q < kPrepSups; q++) {
+                const uint32_t w = wave_sum32(tc[q]);  // (each count < 2^16: a superchunk sum fits 32 bits)
+                if ((tid & 63) == 0) s_q[tid >> 6][q] = w;
+            }
+            __syncthreads();
+            if (tid < kPrepSups) {
+                unsigned long long t = 0;
+#pragma unroll
+                for (int w = 0; w < kWaves; w++) t += s_q[w][tid];
+                sv = (tid < a.nsup) ? t : 0ull;
+            }
+        }
         unsigned long long tot;
         const unsigned long long ex = block_excl_scan64(sv, s_w, &tot);
         if (tid < a.nsup) a.sup[tid] = ex;
@@ -1517,6 +1541,7 @@ __device__ __forceinline__ PrepArgs job_prep(const BatchJob &j, uint32_t i) {
     p.plan.n = j.n;
     p.plan.matrix = 0;
     p.plan_here = (p.plan.nodes > kScanChunk) ? 0u : 1u;  // larger levels: the k_batch_plan_* kernels
+    p.sums_here = 0;                                       // (k_batch_supsum runs for every level)
     return p;
 }
 
@@ -1750,7 +1775,7 @@ hipError_t launch_ingest(const IngestArgs &a, uint32_t width, uint32_t lane_byte
 }
 
 hipError_t launch_prep(const PrepArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_supsum, dim3((uint32_t)a.nsup), dim3(kThreads), 0, s, a);
+    if (!a.sums_here) hipLaunchKernelGGL(k_supsum, dim3((uint32_t)a.nsup), dim3(kThreads), 0, s, a);
     hipLaunchKernelGGL(k_prep, dim3(1), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }

@@ -40,6 +40,7 @@ __host__ __device__ constexpr uint64_t tile_stride(uint64_t ntiles) { return (nt
 constexpr uint64_t kZerosOff = 8;
 // Tiles per superchunk of the tile-count scan (four counts per lane).
 constexpr uint64_t kSup = kThreads;
+constexpr uint64_t kPrepSups = 8;  // superchunks whose sums the prep takes itself
 // Node ones counters of shallow levels are spread over slots so that the
 // tiles adding into them do not pile onto a few addresses: level i keeps
 // max(1, kSlotSpan >> i) copies of its 2^i counters (picked by tile).
@@ -183,6 +184,8 @@ struct PrepArgs {
     uint64_t ntiles, nsup;
     PlanArgs plan;
     uint32_t plan_here;                  // node tables built here (levels up to kScanChunk nodes)
+    uint32_t sums_here;                  // superchunk sums taken here from tile_ones (no k_supsum):
+                                         // at most kPrepSups superchunks, plan_here, fewer than kThreads nodes
 };
 
 // One sequence of a batched build as the batch kernels see it (its layout,
