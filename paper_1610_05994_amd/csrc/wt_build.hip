@@ -1712,8 +1712,44 @@ __global__ __launch_bounds__(kThreads) void k_bitdir_apply(BitDirArgs a) {
     if (blk < a.nblk) a.ranks[blk] += a.wsum[blk / kBitDirBlocks];
 }
 
+// Short bitmaps (at most 8 * kBitDirBlocks blocks): the whole directory in
+// one workgroup, each thread a run of consecutive blocks.
+constexpr uint64_t kBitDirSmallPer = 8;
+__global__ __launch_bounds__(kThreads) void k_bitdir_small(BitDirArgs a) {
+    __shared__ unsigned long long s_w[kWaves];
+    const uint64_t per = (a.nblk + kThreads - 1) / kThreads;  // <= kBitDirSmallPer
+    const uint64_t b0 = (uint64_t)threadIdx.x * per;
+    uint32_t c[kBitDirSmallPer];
+    unsigned long long sum = 0;
+#pragma unroll
+    for (uint64_t q = 0; q < kBitDirSmallPer; q++) {
+        c[q] = 0;
+        if (q < per && b0 + q < a.nblk) {
+            const uint4 *p = reinterpret_cast<const uint4 *>(a.bits + (b0 + q) * 8);
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const uint4 v = p[j];
+                c[q] += (uint32_t)(__popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w));
+            }
+        }
+        sum += c[q];
+    }
+    unsigned long long tot;
+    unsigned long long off = block_excl_scan64(sum, s_w, &tot);
+#pragma unroll
+    for (uint64_t q = 0; q < kBitDirSmallPer; q++) {
+        if (q < per && b0 + q < a.nblk) a.ranks[b0 + q] = off;
+        off += c[q];
+    }
+    for (uint64_t k = a.nblk + threadIdx.x; k < a.rank_stride; k += kThreads) a.ranks[k] = (k == a.nblk) ? tot : 0ull;
+}
+
 hipError_t launch_bitdir(const BitDirArgs &a, hipStream_t s) {
     hipError_t err;
+    if (a.nblk <= kBitDirSmallPer * kThreads) {
+        hipLaunchKernelGGL(k_bitdir_small, dim3(1), dim3(kThreads), 0, s, a);
+        return hipGetLastError();
+    }
     if (a.nblk) {
         hipLaunchKernelGGL(k_bitdir_blocks, dim3((uint32_t)a.nwg), dim3(kThreads), 0, s, a);
         if ((err = hipGetLastError()) != hipSuccess) return err;
