@@ -136,6 +136,33 @@ __global__ __launch_bounds__(kDT) void k_digit_dir_fix(DigitDirArgs a) {
     const uint64_t per = (a.wg_per_level + kDT - 1) / kDT;
     const uint64_t k0 = (uint64_t)threadIdx.x * per;
     unsigned long long tot[4];
+    constexpr uint64_t kFixPer = 16;
+    if (per <= kFixPer) {
+        // up to 2^29 positions per level: every sum of the thread loaded at
+        // once (a loop of unknown length would wait for them one by one)
+        unsigned long long v[kFixPer][4];
+#pragma unroll
+        for (uint64_t q = 0; q < kFixPer; q++)
+#pragma unroll
+            for (int d = 0; d < 4; d++) v[q][d] = (q < per && k0 + q < a.wg_per_level) ? ws[(k0 + q) * 4 + d] : 0ull;
+#pragma unroll
+        for (int d = 0; d < 4; d++) {
+            unsigned long long sum = 0;
+#pragma unroll
+            for (uint64_t q = 0; q < kFixPer; q++) sum += v[q][d];
+            unsigned long long off = excl_scan(sum, s_scan, &tot[d]);
+#pragma unroll
+            for (uint64_t q = 0; q < kFixPer; q++) {
+                if (q < per && k0 + q < a.wg_per_level) ws[(k0 + q) * 4 + d] = off;
+                off += v[q][d];
+            }
+        }
+        uint64_t *E = a.dir + (uint64_t)i * a.dir_stride * 4;
+        for (uint64_t t = a.nblk + threadIdx.x; t < a.dir_stride; t += kDT)
+#pragma unroll
+            for (int d = 0; d < 4; d++) E[t * 4 + d] = (t == a.nblk) ? tot[d] : 0ull;
+        return;
+    }
 #pragma unroll
     for (int d = 0; d < 4; d++) {
         unsigned long long sum = 0;
