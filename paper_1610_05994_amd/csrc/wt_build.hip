@@ -706,13 +706,26 @@ __host__ __device__ constexpr uint32_t multi_stage_elems() {
 // LDS of a wave: without M, the single-node staging or the direct path's
 // counters; with M (no direct path), the single-node staging, or the run
 // tables and staging of the few-nodes split, or the dense split's staging
-// and symbol copy (two tiles), whichever is largest.
-template <int W, int B, bool M>
+// (one tile, or two with the symbol copy), whichever is largest.
+// The dense split of a single build keeps an LDS copy of the tile beside its
+// staging only where that fits in the slice the other paths need anyway;
+// elsewhere it reads the symbols back from T_i (just loaded, so from the
+// cache) and the slice, and with it the variant's occupancy, is set by the
+// other paths.  (The batched passes always keep the copy: their staged
+// launches are short, and the reads' latency showed more than occupancy.)
+template <int W, int B>
+__host__ __device__ constexpr bool dense_lds_copy() {
+    constexpr uint32_t split = (uint32_t)(tile_syms(W, B) + 4 * (16 / W)) * W;
+    constexpr uint32_t multi = kMultiTablesBytes + multi_stage_elems<W, B>() * W;
+    return 2u * (uint32_t)tile_syms(W, B) * W <= (split > multi ? split : multi);
+}
+
+template <int W, int B, bool M, bool kCopy>
 __host__ __device__ constexpr uint32_t level_wave_bytes() {
     constexpr uint32_t split = (uint32_t)(tile_syms(W, B) + 4 * (16 / W)) * W;
     constexpr uint32_t counters = 2u * 4u * kNodeCap * 4u;
     constexpr uint32_t multi = kMultiTablesBytes + multi_stage_elems<W, B>() * W;
-    constexpr uint32_t dense = 2u * (uint32_t)tile_syms(W, B) * W;
+    constexpr uint32_t dense = (kCopy ? 2u : 1u) * (uint32_t)tile_syms(W, B) * W;
     constexpr uint32_t plain = split > counters ? split : counters;
     constexpr uint32_t m1 = split > multi ? split : multi;
     return M ? (m1 > dense ? m1 : dense) : plain;
@@ -912,7 +925,7 @@ __device__ __forceinline__ void stage_multi(const LevelArgs &a, const uint4 (&ra
 // (node, bit, destination-tile parity).  Node starts and their tile ranks
 // travel between lanes as (position << 16 | rank) in a prefix maximum and a
 // suffix minimum.
-template <int W, int B>
+template <int W, int B, bool kCopy>
 __device__ __forceinline__ void split_dense(const LevelArgs &a, const uint4 (&raw)[B / 16],
                                             typename MaskT<B / W>::T mb, int nval, uint32_t lr1, uint32_t agg,
                                             unsigned long long prefix, uint64_t base, uint64_t nvalid, uint64_t t,
@@ -928,16 +941,24 @@ __device__ __forceinline__ void split_dense(const LevelArgs &a, const uint4 (&ra
     T *s_stage = reinterpret_cast<T *>(s_wave);
     const uint32_t p0 = (uint32_t)lane * E;
     const uint32_t nv = (uint32_t)nvalid;
-    // the lane's symbols go to LDS behind the staging area, so that the
-    // per-symbol loops run rolled (unrolled, they held too many registers)
-    T *s_sym = reinterpret_cast<T *>(s_wave + TILE * W) + p0;
+    // The per-symbol loops run rolled (unrolled, they held too many
+    // registers): over an LDS copy of the lane's symbols behind the staging
+    // area where it fits the variant's slice, else over T_i itself, which the
+    // wave has just loaded (only positions below n are read there).
+    const T *s_sym;
+    if constexpr (kCopy) {
+        T *c = reinterpret_cast<T *>(s_wave + TILE * W) + p0;
 #pragma unroll
-    for (int q = 0; q < B / 16; q++) reinterpret_cast<uint4 *>(s_sym)[q] = raw[q];
+        for (int q = 0; q < B / 16; q++) reinterpret_cast<uint4 *>(c)[q] = raw[q];
+        s_sym = c;
+    } else {
+        s_sym = reinterpret_cast<const T *>(a.tin) + base + p0;
+    }
 
     // node starts of this lane
     Mk fm = 0;
     {
-        uint32_t vprev = wave_prev_lane(((uint32_t)s_sym[E - 1] & a.symmask) >> nsh, 0xFFFFFFFFu);
+        uint32_t vprev = wave_prev_lane((raw_elem<W, B>(raw, E - 1) & a.symmask) >> nsh, 0xFFFFFFFFu);
 #pragma unroll 2
         for (int k = 0; k < E; k++) {
             if (k < nval) {
@@ -1104,7 +1125,7 @@ struct SplitRec {
 // One level pass over tile t, run by one wave (each lane B bytes = E = B/W
 // symbols of T_i); s_wave is the wave's own LDS slice.  Single-node tiles
 // leave their next-level counts in *rec; other tiles add theirs directly.
-template <int W, int B, bool kMulti>
+template <int W, int B, bool kMulti, bool kCopy>
 __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8_t *s_wave, SplitRec *rec) {
     typedef typename ElemT<W>::T T;
     constexpr int E = B / W;                    // symbols per lane
@@ -1353,7 +1374,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
     }
 
     if (kMulti) {
-        split_dense<W, B>(a, raw, mb, nval, lr1, agg, prefix, base, nvalid, t, vf, vl, nsh, s_wave, tout, counting,
+        split_dense<W, B, kCopy>(a, raw, mb, nval, lr1, agg, prefix, base, nvalid, t, vf, vl, nsh, s_wave, tout, counting,
                           sh2, ones_next);
         return;
     }
@@ -1475,12 +1496,13 @@ __device__ __forceinline__ void flush_split_recs(const LevelArgs &a, const Split
 
 template <int W, int B, bool M>
 __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
-    __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W, B, M>()];
+    constexpr bool kCopy = dense_lds_copy<W, B>();
+    __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W, B, M, kCopy>()];
     __shared__ SplitRec s_rec[kWaves];
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t t = (uint64_t)blockIdx.x * kWaves + wv;
     if ((threadIdx.x & 63) < 4) s_rec[wv].cnt[threadIdx.x & 63] = 0;
-    if (t < a.ntiles) level_tile<W, B, M>(a, t, s_all + wv * level_wave_bytes<W, B, M>(), &s_rec[wv]);
+    if (t < a.ntiles) level_tile<W, B, M, kCopy>(a, t, s_all + wv * level_wave_bytes<W, B, M, kCopy>(), &s_rec[wv]);
     flush_split_recs(a, s_rec, (uint64_t)blockIdx.x * kWaves);
 }
 
@@ -1636,14 +1658,15 @@ __global__ __launch_bounds__(kThreads) void k_batch_plan_apply(BatchClass c, uin
 
 template <int W, int B, bool M>
 __global__ __launch_bounds__(kThreads) void k_batch_level(BatchClass c, uint32_t level) {
-    __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W, B, M>()];
+    __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W, B, M, true>()];
     __shared__ SplitRec s_rec[kWaves];
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const BatchJob &j = c.jobs[c.blk_map[blockIdx.x]];
     const uint64_t t0 = (blockIdx.x - j.blk_base) * kWaves;
     const LevelArgs a = job_level(j, level);
     if ((threadIdx.x & 63) < 4) s_rec[wv].cnt[threadIdx.x & 63] = 0;
-    if (t0 + wv < j.ntiles) level_tile<W, B, M>(a, t0 + wv, s_all + wv * level_wave_bytes<W, B, M>(), &s_rec[wv]);
+    if (t0 + wv < j.ntiles)
+        level_tile<W, B, M, true>(a, t0 + wv, s_all + wv * level_wave_bytes<W, B, M, true>(), &s_rec[wv]);
     flush_split_recs(a, s_rec, t0);
 }
 
