@@ -61,6 +61,25 @@ def test_every_geometry_builds_the_oracle_tree(lane_bytes, restore_table):
         t.close()
 
 
+@pytest.mark.parametrize("lane_bytes", [32, 64, 128])
+def test_every_geometry_clustered_large_alphabet(lane_bytes, restore_table):
+    # Gaussian clusters over 2^20 symbols: deep levels hold tiles of many
+    # small nodes next to a few large ones (the few-node and dense split
+    # paths of the staged variant), with a ragged last tile
+    _, wt = _mods()
+    import torch
+    _force(lane_bytes)
+    for k, (n, width) in enumerate([(300_001, 4), (200_003, 2)]):
+        sigma = (1 << 20) if width == 4 else (1 << 16)
+        S = wtgen.gauss_mix(n, sigma, 950 + k, 16, max(1.0, sigma / 512), width)
+        print("geometry %d clustered: n=%d sigma=%d width=%d" % (lane_bytes, n, sigma, width), flush=True)
+        t = wt.build(wt.to_device(S, torch.device("cuda:0")), sigma)
+        ref = oracle.build(S, sigma)
+        assert tc.compare_levels(t.bitmaps(), ref.bitmaps) is None
+        assert tc.compare_levels(t.ranks(), ref.ranks, "rank") is None
+        t.close()
+
+
 @pytest.mark.parametrize("lane_bytes", [1, 2, 32, 128])
 def test_every_geometry_batched(lane_bytes, restore_table):
     _, wt = _mods()
