@@ -71,6 +71,33 @@ def instrumented_pass(steps, step):
     return (t1 - t0) * 1e3 / steps, recs
 
 
+def copy_reference(dev, stream, mib: int = 256, copies: int = 10, reps: int = 3):
+    """A plain device-to-device copy of `mib` MiB on the build's stream (read +
+    write bytes over its duration; `copies` back to back between one event
+    pair, so that the events' own cost is spread thin; median of `reps`): the
+    bandwidth a pass that reads and writes what it moves can reach on this
+    GPU, for scale beside the roofline's 8 TB/s."""
+    import torch
+    src = torch.empty(mib << 20, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    times = []
+    with torch.cuda.stream(stream):
+        dst.copy_(src)  # warm
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(copies):
+                dst.copy_(src)
+            b.record(stream)
+            b.synchronize()
+            times.append(a.elapsed_time(b) / copies)
+    del src, dst
+    ms = statistics.median(times)
+    return {"gbps": 2 * (mib << 20) / (ms / 1e3) / 1e9, "bytes": 2 * (mib << 20),
+            "how": "torch device-to-device copies of %d MiB on the build's stream, %d back to back per "
+                   "event pair, median of %d" % (mib, copies, reps)}
+
+
 def per_level_rows(lvl):
     """Level-pass launches grouped by tree level: average duration and
     algorithmic GB/s (a folded pass, which also writes the next level's
@@ -300,6 +327,7 @@ def main() -> int:
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     ms_instrumented, recs = instrumented_pass(args.steps, lambda: wtree.wt_free(one_build()))
+    copy_ref = copy_reference(dev, stream)
     step_ms = sorted(a.elapsed_time(b) for a, b in ev)
     p50 = float(np.percentile(step_ms, 50))
     p99 = float(np.percentile(step_ms, 99))
@@ -356,6 +384,8 @@ def main() -> int:
             "avg_launch_us": lvl_ms * 1e3 / max(launches, 1),
             "algorithmic_bytes_per_launch": lvl_bytes / max(launches, 1),
             "per_level": per_level_rows(lvl),
+            "copy_reference": copy_ref,
+            "frac_of_copy": (achieved / copy_ref["gbps"]) if copy_ref else None,
         },
         "build_latency_ms": {"p50": p50, "p99": p99},
         "instrumented_ms_per_step": ms_instrumented,
