@@ -4,9 +4,11 @@ TEST INFRASTRUCTURE ONLY.  Only the tests, ``__graft_entry__.smoke()`` and the
 benchmark's ``cpu_baseline`` leg may import this package.  The GPU library
 never calls it, and it never calls the GPU library: the two share no code.
 
-The C source follows the paper's per-level construction (Section 3.1, the
-pwt algorithm run sequentially) and the query walks of Section 2.3; see the
-header of ``wt_oracle.c`` for the readings taken where the paper is loose.
+The C source builds the tree from its recursive definition (Section 2.2:
+every node hands its symbols, in order, to the child of their next bit;
+each level is the concatenation of its nodes' bitmaps) and answers queries
+by the walks of Section 2.2; see the header of ``wt_oracle.c`` for the
+readings taken where the paper is loose.
 """
 from __future__ import annotations
 

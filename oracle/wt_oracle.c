@@ -7,25 +7,26 @@
  * What it follows (Fuentes-Sepulveda, Elejalde, Ferres, Seco, "Parallel
  * Construction of Wavelet Trees on Multicore Architectures"):
  *
- *  - Section 2.3 (wavelet trees): access / rank / select, the balanced binary
- *    tree whose node bitmaps mark with 0 the left half and with 1 the right
- *    half of the node's alphabet range, and the one-pointer-per-level
- *    representation where navigation is simulated with rank on each level's
- *    n-bit bitmap.
+ *  - Section 2.2 (wavelet trees): the balanced binary tree whose node
+ *    bitmaps mark with 0 the symbols of the first half and with 1 those of
+ *    the second half of the node's alphabet range, each child holding its
+ *    half's symbols in their original order; the one-pointer-per-level
+ *    representation, which concatenates the node bitmaps of every level from
+ *    left to right; access / rank / select, with the navigation simulated by
+ *    rank on each level's n-bit bitmap.  The construction below is that
+ *    recursive definition carried out level by level (every node split into
+ *    its two children in place).
+ *  - Section 2.3 (problem statement): S of n symbols over an alphabet of
+ *    sigma symbols in, the levels of the tree out.
  *  - Section 3, Proposition 1: the node of symbol s at level i is s >> (l-i),
- *    with l = ceil(lg sigma).
- *  - Section 3.1, Algorithm pwt with every parfor replaced by a sequential
- *    for (the paper's own sequential version): for each level, count the
- *    symbols of every node, take the prefix sum of the counts to get the node
- *    offsets, then sweep S in order writing the level bit of each symbol at
- *    its node's running offset, and finally build the rank structure.
+ *    with l = ceil(lg sigma); the halves of a node's range are therefore
+ *    taken by bit prefix, and the mark of level i is bit l-1-i.
  *
  * Readings taken where the paper is loose (each is listed in the design
- * notes): symbols are 0-based in [0, sigma); the bit test of the fill step is
- * "bit (l-1-i) of S[j] is set"; the prefix sum is exclusive (node start
- * offsets); non-power-of-two alphabets split by bit prefix over l bits;
- * positions are 0-based; rank(c, i) counts [0, i); select(c, j) takes a
- * 1-based j and returns a 0-based position.
+ * notes): symbols are 0-based in [0, sigma); non-power-of-two alphabets split
+ * by bit prefix over l bits (so "first half" of a node's range is the part
+ * whose next bit is 0); positions are 0-based; rank(c, i) counts [0, i);
+ * select(c, j) takes a 1-based j and returns a 0-based position.
  *
  * Conventions that the paper leaves open and that the library implements
  * independently (parity of these two is unpinned by the paper):
@@ -70,10 +71,37 @@ static uint64_t sym_at(const void *S, uint32_t width, uint64_t j)
 
 static int get_bit(const uint64_t *B, uint64_t p) { return (int)((B[p >> 6] >> (p & 63)) & 1u); }
 
+/* Rank directory of one level: ones before every multiple of 512, then the
+ * total, then zero padding up to the slot size. */
+static void rank_directory(const uint64_t *Bi, uint64_t n, uint64_t *Ri)
+{
+    uint64_t K = wto_rank_entries(n), KS = wto_rank_stride(n);
+    memset(Ri, 0, KS * sizeof(uint64_t));
+    uint64_t ones = 0;
+    for (uint64_t p = 0; p < n; p++) {
+        if ((p & 511) == 0) Ri[p >> 9] = ones;
+        ones += (uint64_t)get_bit(Bi, p);
+    }
+    Ri[K - 1] = ones;
+}
+
 /*
  * Build every level bitmap (and, when R != NULL, every rank directory).
  * B holds l * wto_words_per_level(n) words, R holds l * wto_rank_stride(n)
  * entries.  Returns WTO_ERANGE if some symbol is >= sigma.
+ *
+ * Straight from the recursive definition of Section 2.2: the root node holds
+ * all of S; a node's bitmap marks each of its symbols with 0 (lower half of
+ * the node's alphabet range) or 1 (upper half); its left child holds, in
+ * their original order, the symbols marked 0 and its right child those
+ * marked 1.  The halves are taken by bit prefix (the node of level i
+ * covering the symbols whose top i bits are v, Proposition 1), so the mark
+ * at level i is bit l-1-i.  The pointerless tree concatenates, level by
+ * level, the bitmaps of the nodes from left to right.  Here A holds that
+ * concatenation of the level's node sequences and len[v] the length of node
+ * v, so the level's bitmap is simply the mark of A[p] at position p, and the
+ * next level's A is every node split, in place of its parent, into its marked
+ * 0 and marked 1 symbols (each in order).
  */
 int wto_build(const void *S, uint64_t n, uint32_t sigma, uint32_t width,
               uint64_t *B, uint64_t *R)
@@ -85,58 +113,57 @@ int wto_build(const void *S, uint64_t n, uint32_t sigma, uint32_t width,
 
     uint32_t l = wto_levels(sigma);
     uint64_t W = wto_words_per_level(n);
-    uint64_t K = wto_rank_entries(n), KS = wto_rank_stride(n);
-    uint64_t maxnodes = l ? (1ull << (l - 1)) : 1;
-    uint64_t *C = (uint64_t *)malloc(maxnodes * sizeof(uint64_t));
-    if (!C) return WTO_ENOMEM;
+    uint64_t KS = wto_rank_stride(n);
+    uint64_t maxnodes = 1ull << l;        /* nodes of the level below the last */
+    uint32_t *A = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    uint32_t *Anext = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    uint64_t *len = (uint64_t *)malloc(maxnodes * sizeof(uint64_t));
+    uint64_t *lennext = (uint64_t *)malloc(maxnodes * sizeof(uint64_t));
+    if (!A || !Anext || !len || !lennext) {
+        free(A); free(Anext); free(len); free(lennext);
+        return WTO_ENOMEM;
+    }
+    for (uint64_t j = 0; j < n; j++) A[j] = (uint32_t)sym_at(S, width, j);
+    len[0] = n;                           /* level 0: the root holds S */
 
     for (uint32_t i = 0; i < l; i++) {
         uint64_t nodes = 1ull << i;
-        uint32_t shift = l - i;            /* node of s at level i: s >> (l-i) */
+        uint32_t mark = l - 1 - i;        /* level i marks with bit l-1-i */
         uint64_t *Bi = B + (uint64_t)i * W;
-
-        /* count the symbols of every node of level i */
-        memset(C, 0, nodes * sizeof(uint64_t));
-        for (uint64_t j = 0; j < n; j++) C[sym_at(S, width, j) >> shift]++;
-
-        /* exclusive prefix sum: C[v] becomes the offset of node v */
-        uint64_t acc = 0;
-        for (uint64_t v = 0; v < nodes; v++) {
-            uint64_t c = C[v];
-            C[v] = acc;
-            acc += c;
-        }
-
-        /* fill: in input order, write bit (l-1-i) at the node's running offset */
         memset(Bi, 0, W * sizeof(uint64_t));
-        for (uint64_t j = 0; j < n; j++) {
-            uint64_t s = sym_at(S, width, j);
-            uint64_t v = s >> shift;
-            uint64_t bit = (s >> (shift - 1)) & 1u;
-            uint64_t pos = C[v];
-            if (bit) Bi[pos >> 6] |= 1ull << (pos & 63);
-            C[v]++;
-        }
-
-        /* rank directory: ones before every multiple of 512, and the total */
-        if (R) {
-            uint64_t *Ri = R + (uint64_t)i * KS;
-            memset(Ri, 0, KS * sizeof(uint64_t));
-            uint64_t ones = 0;
-            for (uint64_t p = 0; p < n; p++) {
-                if ((p & 511) == 0) Ri[p >> 9] = ones;
-                ones += (uint64_t)get_bit(Bi, p);
+        uint64_t p = 0;                   /* first position of node v */
+        for (uint64_t v = 0; v < nodes; v++) {
+            uint64_t end = p + len[v];
+            uint64_t zeros = 0;
+            for (uint64_t k = p; k < end; k++) {
+                if ((A[k] >> mark) & 1u) Bi[k >> 6] |= 1ull << (k & 63);
+                else zeros++;
             }
-            Ri[K - 1] = ones;
+            /* children in place of the parent: the 0-marked symbols in
+             * order, then the 1-marked ones in order */
+            uint64_t zp = p, op = p + zeros;
+            for (uint64_t k = p; k < end; k++) {
+                if ((A[k] >> mark) & 1u) Anext[op++] = A[k];
+                else Anext[zp++] = A[k];
+            }
+            lennext[2 * v] = zeros;
+            lennext[2 * v + 1] = len[v] - zeros;
+            p = end;
         }
+        if (R) rank_directory(Bi, n, R + (uint64_t)i * KS);
+        uint32_t *ta = A; A = Anext; Anext = ta;
+        uint64_t *tl = len; len = lennext; lennext = tl;
     }
-    free(C);
+    free(A);
+    free(Anext);
+    free(len);
+    free(lennext);
     return WTO_OK;
 }
 
 /* ------------------------------------------------------------ queries ---- */
 /*
- * Queries walk the levels as Section 2.3 describes for the one-pointer-per-
+ * Queries walk the levels as Section 2.2 describes for the one-pointer-per-
  * level representation: the current node is a range [b, e) of the level's
  * bitmap; its left child occupies, at the next level, the first
  * zeros(b, e) positions of the same range and its right child the rest.
@@ -433,10 +460,10 @@ int wto_matrix_select(const uint64_t *B, const uint64_t *Z, uint64_t n, uint32_t
  * digits (one zero bit on top when l is odd).  Level i lists, node after
  * node in order, digit i of every symbol (bits 2(L4-1-i) + 1 .. 2(L4-1-i));
  * the node of s at level i is s >> 2(L4-i), and the symbols of a node keep
- * their input order.  The construction is Algorithm pwt with four-way nodes,
- * run sequentially: count the symbols of every node, take the exclusive
- * prefix sum of the counts, then sweep S in order writing each symbol's
- * digit at its node's running offset.
+ * their input order.  The construction is the recursive definition of
+ * Section 2.2 with four children per node, carried out level by level: each
+ * node's digit sequence is its level's contribution, and its symbols go, in
+ * order, to the child of their digit.
  *
  * Conventions (as for the binary tree, unpinned by the paper): digit p of a
  * level sits in 64-bit word p / 32 at bits 2 (p % 32) and 2 (p % 32) + 1;
@@ -461,43 +488,59 @@ int wto_build4(const void *S, uint64_t n, uint32_t sigma, uint32_t width, uint64
     uint32_t L4 = wto_levels4(sigma);
     uint64_t W = wto_words4(n);
     uint64_t K = wto_rank_entries(n), KS = wto_rank_stride(n);
-    uint64_t maxnodes = L4 ? (1ull << (2 * (L4 - 1))) : 1;
-    uint64_t *C = (uint64_t *)malloc(maxnodes * sizeof(uint64_t));
-    if (!C) return WTO_ENOMEM;
+    uint64_t maxnodes = 1ull << (2 * L4);
+    /* As for the binary tree: A is the level's node sequences concatenated,
+     * len[v] the length of node v; each node hands its symbols, in order, to
+     * its four children by digit. */
+    uint32_t *A = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    uint32_t *Anext = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    uint64_t *len = (uint64_t *)malloc(maxnodes * sizeof(uint64_t));
+    uint64_t *lennext = (uint64_t *)malloc(maxnodes * sizeof(uint64_t));
+    if (!A || !Anext || !len || !lennext) {
+        free(A); free(Anext); free(len); free(lennext);
+        return WTO_ENOMEM;
+    }
+    for (uint64_t j = 0; j < n; j++) A[j] = (uint32_t)sym_at(S, width, j);
+    len[0] = n;
     for (uint32_t i = 0; i < L4; i++) {
         uint64_t nodes = 1ull << (2 * i);
-        uint32_t shift = 2 * (L4 - i);     /* node of s at level i */
+        uint32_t dsh = 2 * (L4 - 1 - i);   /* digit i of a padded code */
         uint64_t *Di = D + (uint64_t)i * W;
-        memset(C, 0, nodes * sizeof(uint64_t));
-        for (uint64_t j = 0; j < n; j++) C[sym_at(S, width, j) >> shift]++;
-        uint64_t acc = 0;
-        for (uint64_t v = 0; v < nodes; v++) {
-            uint64_t c = C[v];
-            C[v] = acc;
-            acc += c;
-        }
         memset(Di, 0, W * sizeof(uint64_t));
-        for (uint64_t j = 0; j < n; j++) {
-            uint64_t s = sym_at(S, width, j);
-            uint64_t v = s >> shift;
-            uint64_t d = (s >> (shift - 2)) & 3u;
-            uint64_t pos = C[v];
-            Di[pos >> 5] |= d << (2 * (pos & 31));
-            C[v]++;
+        uint64_t p = 0;
+        for (uint64_t v = 0; v < nodes; v++) {
+            uint64_t end = p + len[v];
+            uint64_t cnt[4] = {0, 0, 0, 0};
+            for (uint64_t k = p; k < end; k++) {
+                uint64_t d = (A[k] >> dsh) & 3u;
+                Di[k >> 5] |= d << (2 * (k & 31));
+                cnt[d]++;
+            }
+            uint64_t at[4];
+            at[0] = p;
+            for (int d = 1; d < 4; d++) at[d] = at[d - 1] + cnt[d - 1];
+            for (uint64_t k = p; k < end; k++) Anext[at[(A[k] >> dsh) & 3u]++] = A[k];
+            for (int d = 0; d < 4; d++) lennext[4 * v + (uint64_t)d] = cnt[d];
+            p = end;
         }
         if (R) {
             uint64_t *Ri = R + (uint64_t)i * KS * 4;
             memset(Ri, 0, KS * 4 * sizeof(uint64_t));
-            uint64_t cnt[4] = {0, 0, 0, 0};
-            for (uint64_t p = 0; p < n; p++) {
-                if ((p & 511) == 0)
-                    for (int d = 0; d < 4; d++) Ri[(p >> 9) * 4 + d] = cnt[d];
-                cnt[get_digit(Di, p)]++;
+            uint64_t c4[4] = {0, 0, 0, 0};
+            for (uint64_t q = 0; q < n; q++) {
+                if ((q & 511) == 0)
+                    for (int d = 0; d < 4; d++) Ri[(q >> 9) * 4 + d] = c4[d];
+                c4[get_digit(Di, q)]++;
             }
-            for (int d = 0; d < 4; d++) Ri[(K - 1) * 4 + d] = cnt[d];
+            for (int d = 0; d < 4; d++) Ri[(K - 1) * 4 + d] = c4[d];
         }
+        uint32_t *ta = A; A = Anext; Anext = ta;
+        uint64_t *tl = len; len = lennext; lennext = tl;
     }
-    free(C);
+    free(A);
+    free(Anext);
+    free(len);
+    free(lennext);
     return WTO_OK;
 }
 
