@@ -45,9 +45,18 @@ WORKLOADS = {
 
 
 def kernel_source_hash() -> str:
+    """Hash of everything that decides what the build's kernels move: every
+    source under csrc/ (kernels, launch sequences, layouts, the fold decision)
+    and the tuning table (tile geometry)."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1610_05994_amd", "csrc", "wt_build.hip"), "rb") as f:
-        h.update(f.read())
+    pkg = os.path.join(ROOT, "paper_1610_05994_amd")
+    csrc = os.path.join(pkg, "csrc")
+    paths = [os.path.join(csrc, f) for f in sorted(os.listdir(csrc))] + [os.path.join(pkg, "tune_table.json")]
+    for path in paths:
+        if os.path.isfile(path):
+            h.update(os.path.basename(path).encode())
+            with open(path, "rb") as f:
+                h.update(f.read())
     return h.hexdigest()[:16]
 
 

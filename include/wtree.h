@@ -2,7 +2,7 @@
  * wtree.h -- C ABI of the MI355X wavelet-tree construction library.
  *
  * Problem (Fuentes-Sepulveda et al., "Parallel Construction of Wavelet Trees
- * on Multicore Architectures", Section 2.4 problem statement, Section 2.3
+ * on Multicore Architectures", Section 2.3 problem statement, Section 2.2
  * definitions): given a sequence S of n symbols over the alphabet [0, sigma),
  * build the pointerless wavelet tree -- one n-bit bitmap per level, l =
  * ceil(lg sigma) levels -- in which level i lists, node after node in prefix
@@ -74,8 +74,10 @@ typedef struct wt_desc {
 } wt_desc;
 
 /*
- * Bytes of tree memory and of workspace that wt_build needs for *desc.
- * Pure host computation (no device call).
+ * Bytes of tree memory and of workspace that wt_build needs for *desc (the
+ * memory question of Section 4.3: the tree itself is l n-bit levels plus
+ * their rank directories, the workspace two n-symbol order buffers and the
+ * per-level node tables).  Pure host computation (no device call).
  */
 int wt_footprint(const wt_desc *desc, uint64_t *tree_bytes, uint64_t *work_bytes);
 
@@ -174,7 +176,10 @@ int wt_build_buffered(const void *S, const wt_desc *desc, uint64_t buffer_syms, 
 int wt_batch_footprint(uint32_t m, const wt_desc *descs, uint64_t *work_bytes);
 
 /*
- * Build m independent trees in one batched launch sequence on `stream`.
+ * Build m independent trees in one batched launch sequence on `stream`: the
+ * construction of wt_build (Sections 3.1 and 3.2) for many sequences at
+ * once, the segments of all of them sharing each launch the way Algorithm
+ * dd's segments share the cores.
  * d_S[q], descs[q], d_trees[q] (of tree_bytes[q] bytes) describe sequence q;
  * sequences may mix lengths, alphabets and widths.  out[q] receives the
  * handle of tree q (each released with wt_free).  On error no handle is
@@ -194,7 +199,9 @@ int wt_tree_status(const wt_tree *tree);
 void wt_free(wt_tree *tree);
 
 /*
- * Layout of a built tree: number of levels, device pointer to level 0's
+ * The one-pointer-per-level representation of Section 2.2 (one n-bit bitmap
+ * per level, addressed from a single pointer).  Layout of a built tree:
+ * number of levels, device pointer to level 0's
  * bitmap (level i starts words_per_level * i words later) and to level 0's
  * rank directory (level i starts rank_stride * i entries later), and the
  * number of meaningful rank entries per level (K = ceil(n/512) + 1).
@@ -204,7 +211,7 @@ int wt_levels(const wt_tree *tree, uint32_t *levels, const uint64_t **d_bitmaps,
               uint64_t *rank_entries);
 
 /*
- * Batched queries (Section 2.3 access / rank / select, evaluated by walking
+ * Batched queries (Section 2.2 access / rank / select, evaluated by walking
  * the levels with rank and select on the bitmaps).  m queries, device
  * arrays, enqueued on `stream` after whatever the stream already holds.
  *  - access: d_sym[k] = S[d_i[k]];            d_i[k] >= n gives 0xFFFFFFFF

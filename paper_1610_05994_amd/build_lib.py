@@ -42,13 +42,34 @@ def build_cpu(verbose: bool = False) -> str:
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp, *srcs]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    """Compile every source to an object in parallel (one hipcc per file; each
+    file launches only its own kernels, so no relocatable device code is
+    needed), then link the shared library."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    cflags = [f for f in FLAGS if f != "-shared"]
+    with tempfile.TemporaryDirectory(prefix="wtree_build_") as tmpdir:
+        objs, cmds = [], []
+        for s in SOURCES:
+            obj = os.path.join(tmpdir, s.replace(".hip", ".o"))
+            objs.append(obj)
+            cmds.append([HIPCC, *cflags, *inc, "-c", "-o", obj, os.path.join(CSRC, s)])
+
+        def run(cmd):
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            subprocess.check_call(cmd)
+
+        workers = max(1, min(len(cmds), os.cpu_count() or 1, 16))
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            for f in [ex.submit(run, c) for c in cmds]:
+                f.result()
+        tmp = LIB + ".tmp%d" % os.getpid()
+        link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+        run(link)
+        os.replace(tmp, LIB)
     return LIB
 
 

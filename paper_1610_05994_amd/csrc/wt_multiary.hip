@@ -1,6 +1,6 @@
 // Directories of the 4-ary tree's digit levels.  Entry k of a level holds
 // the counts of digits 0, 1, 2 and 3 in positions [0, min(512 k, n)): the
-// rank structure of the one-pointer-per-level representation (Section 2.3)
+// rank structure of the one-pointer-per-level representation (Section 2.2)
 // with four symbols per level instead of two.
 //
 // Sixteen lanes count one 512-position block (sixteen 32-digit words) with

@@ -1,7 +1,7 @@
 // Batched access / rank / select on a built pointerless wavelet tree (and
 // on the wavelet-matrix and 4-ary variants).
 //
-// Section 2.3: queries walk the tree top-down; with one bitmap per level the
+// Section 2.2: queries walk the tree top-down; with one bitmap per level the
 // current node is a range [b, e) of the level, its left child is the first
 // zeros(b, e) positions of the same range at the next level and its right
 // child the rest, so every step needs rank on the level bitmap.  rank uses

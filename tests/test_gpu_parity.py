@@ -279,42 +279,6 @@ def test_full_size_c2_against_oracle():
     t.close()
 
 
-@pytest.mark.slow
-def test_full_size_c3_properties():
-    """n = 2^28, sigma = 2^20: too slow for the full oracle inside a test, so
-    every position is decoded on the GPU and per-level invariants are
-    checked; the same generator at n = 2^22 is compared bit-exactly above."""
-    import torch
-    wt = _wt()
-    S, sigma = wtgen.workload("c3")
-    n = S.shape[0]
-    _say("case c3 full: n=%d sigma=%d" % (n, sigma))
-    d = wt.to_device(S, _dev())
-    t = wt.build(d, sigma)
-    assert t.status() == wt.WT_OK
-    l = t.levels
-    B = t.bitmaps_device()
-    R = t.ranks_device()
-    s64 = d.to(torch.int64) & 0xFFFFFFFF
-    for i in range(l):
-        # popcount of level i = symbols with bit (l-1-i) set
-        ones = int(((s64 >> (l - 1 - i)) & 1).sum().item())
-        bits = B[i].view(torch.uint8).cpu().numpy()
-        pc = int(np.unpackbits(bits).sum())
-        assert pc == ones, "level %d popcount" % i
-        # rank directory = cumulative popcount at multiples of 512
-        r = R[i].cpu().numpy().view(np.uint64)[: (n + 511) // 512 + 1]
-        per = np.unpackbits(bits, bitorder="little").reshape(-1, 512).sum(axis=1)
-        assert np.array_equal(r[1:], np.cumsum(per)[: r.size - 1].astype(np.uint64)), "level %d ranks" % i
-    # decode every position through the tree
-    step = 1 << 24
-    for a in range(0, n, step):
-        pos = torch.arange(a, min(n, a + step), device=_dev())
-        got = t.access(pos).to(torch.int64) & 0xFFFFFFFF
-        assert torch.equal(got, s64[a: a + pos.numel()]), "access mismatch in [%d, %d)" % (a, a + step)
-    t.close()
-
-
 def test_query_multi_matches_per_tree_queries():
     """Mixed access/rank/select over several trees in one launch equals the
     per-tree calls (and the oracle), including out-of-range arguments."""

@@ -1,6 +1,6 @@
 """Pins of the CPU oracle against facts that do not come from the oracle.
 
-* the paper's worked example (Section 2.3 figure and access walk; Section
+* the paper's worked example (Section 2.2 figure and access walk; Section
   3.1 snapshot caption), stored in ``tests/golden/paper_example.json``;
 * the stable-sort characterisation of every level (numpy stable argsort);
 * brute-force access / rank / select computed directly on S;

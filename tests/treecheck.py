@@ -6,7 +6,7 @@ construction, so that they can pin it:
 
 * ``levels_by_stable_sort``: level i's bitmap is the bit (l-1-i) plane of S
   after a *stable* sort by the top i bits (each node's symbols stay in input
-  order, nodes in prefix order -- Section 2.3 and Proposition 1).  numpy's
+  order, nodes in prefix order -- Section 2.2 and Proposition 1).  numpy's
   stable argsort does the sorting.
 * ``ranks_by_cumsum``: the rank directory is a cumulative popcount.
 * ``compare_levels``: reports the first differing (level, word) or (level,
