@@ -148,6 +148,8 @@ void make_layout_geom(uint64_t n, uint32_t sigma, uint32_t width, uint32_t geom,
     off += round_up((uint64_t)l * tile_stride(L->ntiles) * 4, 256);
     L->ws_ones = off;
     off += round_up(ones_offset(l) * 8, 256);
+    L->ws_fold_cnt = off;
+    off += 256;
     L->ws_ctrl_bytes = off - L->ws_ctrl;
 
     L->ws_sup = off;
@@ -160,6 +162,13 @@ void make_layout_geom(uint64_t n, uint32_t sigma, uint32_t width, uint32_t geom,
     off += round_up(start_offset(l) * 8, 256);
     L->ws_partials = off;
     off += round_up(kMaxScanBlocks * 8, 256);
+    if (width == 1 && l >= 2) {  // a u8 build may fold its last level
+        L->fold_ovf_cap = fold_ovf_capacity(L->ntiles, l, tile_syms(width, L->lane_bytes));
+        L->ws_fold_own = off;
+        off += round_up(2 * L->ntiles * 8, 256);
+        L->ws_fold_ovf = off;
+        off += round_up(L->fold_ovf_cap * 8, 256);
+    }
     L->work_bytes = L->small ? 256 : off;  // the one-workgroup build needs no workspace
 }
 
@@ -251,7 +260,9 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
 
     const bool four = L.arity == 4;
     const bool fold = fold_last_level(L, partial);
-    uint64_t *bits_last = fold ? bits + (uint64_t)(l - 1) * L.words : nullptr;  // zeroed by ingest: the fold ORs into it
+    // folded: granules below n get one writer each (the pass or the stitch);
+    // the words from the one holding position n on are cleared by ingest
+    uint64_t *bits_last = fold ? bits + (uint64_t)(l - 1) * L.words : nullptr;
     long pr = prof_begin(st, "zero", 0, L.width, L.n, L.ws_ctrl_bytes);
     hipError_t err = launch_zero(work + L.ws_ctrl, L.ws_ctrl_bytes, tree_status,
                                  (L.n == 0 && !four) ? ranks : nullptr, (uint64_t)l * L.rank_stride, st);
@@ -272,15 +283,15 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
     ia.sigma = L.sigma;
     ia.check = (L.width < 4 && (uint64_t)L.sigma == (1ull << (8 * L.width))) ? 0u : 1u;
     ia.msb = l ? l - 1 : 0;
-    ia.zero_p = bits_last;
-    ia.zero_words = fold ? L.words : 0;
+    ia.zero_p = fold ? bits_last + L.n / 64 : nullptr;
+    ia.zero_words = fold ? L.words - L.n / 64 : 0;
     {
         // contiguous tiles per ingest workgroup: ~8192 workgroups
         uint64_t k = kWaves;
         while (L.ntiles > 8192 * k) k <<= 1;
         ia.tiles_per_block = k;
     }
-    pr = prof_begin(st, "ingest", 0, L.width, L.n, L.n * L.width + (fold ? L.words * 8 : 0));
+    pr = prof_begin(st, "ingest", 0, L.width, L.n, L.n * L.width);
     err = launch_ingest(ia, L.width, L.lane_bytes, st);
     prof_end(pr, st);
     if (err != hipSuccess) return err;
@@ -323,8 +334,10 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         if (err != hipSuccess) return err;
 
         LevelArgs a;
+        const bool fold_here = fold && i + 1 == lrun;
         a.tin = (i == 0) ? S : tbuf[(i - 1) & 1];  // T_i for i >= 1 alternates ta, tb
-        a.tout = (i + 1 < lrun) ? tbuf[i & 1] : nullptr;
+        // (folded: T_{l-1} receives the edge symbols of the split only)
+        a.tout = (i + 1 < lrun || fold_here) ? tbuf[i & 1] : nullptr;
         a.bits = four ? nullptr : bits + (uint64_t)i * L.words;
         a.ranks = four ? nullptr : ranks + (uint64_t)i * L.rank_stride;
         const int dl = four ? digit_level(L, i) : -1;
@@ -349,15 +362,36 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         a.symmask = (uint32_t)((1ull << l) - 1);
         a.matrix = L.matrix;
         a.zeros = L.matrix ? reinterpret_cast<unsigned long long *>(tree + kZerosOff) : nullptr;
-        a.bits_next = (fold && i + 1 == lrun) ? bits_last : nullptr;  // (then tout is null)
-        const uint64_t lbytes = L.n * L.width * (a.tout ? 2 : 1) + (a.bits ? L.words * 8 + L.rank_stride * 8 : 0) +
-                                (a.digits ? L.dwords * 8 : 0) + (a.bits_next ? L.words * 8 : 0);
+        a.bits_next = fold_here ? bits_last : nullptr;
+        a.fold_own = fold_here ? reinterpret_cast<uint64_t *>(work + L.ws_fold_own) : nullptr;
+        a.fold_ovf = fold_here ? reinterpret_cast<uint64_t *>(work + L.ws_fold_ovf) : nullptr;
+        a.fold_ovf_n = fold_here ? reinterpret_cast<unsigned int *>(work + L.ws_fold_cnt) : nullptr;
+        a.fold_ovf_cap = fold_here ? L.fold_ovf_cap : 0;
+        a.fold_status = tree_status;
+        const uint64_t lbytes = L.n * L.width * ((a.tout && !fold_here) ? 2 : 1) +
+                                (a.bits ? L.words * 8 + L.rank_stride * 8 : 0) + (a.digits ? L.dwords * 8 : 0) +
+                                (a.bits_next ? L.words * 8 : 0);
         pr = prof_begin(st, "level", i, L.width, L.n, lbytes);
         err = launch_level(a, L.width, L.lane_bytes, !L.matrix && level_multi(L.n, i, L.width, L.lane_bytes), st);
         prof_end(pr, st);
         if (err != hipSuccess) return err;
     }
     if (fold) {
+        // the granules the folded pass left to the stitch
+        StitchArgs sa;
+        sa.t = tbuf[(lrun - 1) & 1];
+        sa.own = reinterpret_cast<const uint64_t *>(work + L.ws_fold_own);
+        sa.ovf = reinterpret_cast<const uint64_t *>(work + L.ws_fold_ovf);
+        sa.ovf_n = reinterpret_cast<const unsigned int *>(work + L.ws_fold_cnt);
+        sa.bits16 = reinterpret_cast<uint16_t *>(bits_last);
+        sa.nown = 2 * L.ntiles;
+        sa.ovf_cap = L.fold_ovf_cap;
+        sa.n = L.n;
+        sa.sh = 0;
+        pr = prof_begin(st, "stitch", l - 1, L.width, L.n, sa.nown * 8);
+        err = launch_fold_stitch(sa, st);
+        prof_end(pr, st);
+        if (err != hipSuccess) return err;
         // the last level's directory from its bitmap; the partial sums use
         // that level's tile-count slot, which the folded pass leaves unused
         BitDirArgs d;
@@ -960,7 +994,7 @@ int wt_tree_status(const wt_tree *t) {
     if (hipStreamSynchronize(t->stream) != hipSuccess) return WT_EDEVICE;
     uint32_t flag = 0;
     if (hipMemcpy(&flag, t->tree, sizeof(flag), hipMemcpyDeviceToHost) != hipSuccess) return WT_EDEVICE;
-    return (flag & 1u) ? WT_ERANGE : WT_OK;
+    return (flag & 1u) ? WT_ERANGE : ((flag & 2u) ? WT_EDEVICE : WT_OK);
 }
 
 void wt_free(wt_tree *t) {

@@ -12,8 +12,10 @@
 //
 // T_i is S stably sorted by its top i bits (Proposition 1: the node of s at
 // level i is s >> (l-i)), so level i's bitmap is simply bit (l-1-i) of T_i,
-// position by position: a 64-position word is built by one workgroup from
-// 64 consecutive symbols and has exactly one writer (no atomics on bitmaps).
+// position by position: a 64-position word is built by one wave from 64
+// consecutive symbols and has exactly one writer (no atomics on bitmaps).
+// (The last level of a u8 tree can instead come out of the pass before it,
+// as 16-position granules with one writer each: see LevelArgs::bits_next.)
 //
 // Segments are tiles of kTile consecutive positions of T_i.  The ones count
 // of every tile of level i is known before level i runs: level 0's come from
@@ -1219,8 +1221,8 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
     }
 
     // folded last level (u8, single-node and direct paths only): bits of
-    // T_{i+1} instead of its symbols
-    uint32_t *bnext = reinterpret_cast<uint32_t *>(a.bits_next);
+    // T_{i+1} instead of its symbols, in 16-bit granules
+    uint16_t *bnext = reinterpret_cast<uint16_t *>(a.bits_next);
     const bool fold = (W == 1) && !kMulti && bnext != nullptr;
     if (a.tout == nullptr && !fold) return;  // last level: no next order, no counts
 
@@ -1302,8 +1304,8 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
                 const uint32_t s = c * CH;
                 const uint4 v = *reinterpret_cast<const uint4 *>(&s_stage[s]);
                 if (inside || gb + s + CH <= a.n) {
-                    if (fold)  // 16 bits at a multiple of 16
-                        reinterpret_cast<uint16_t *>(bnext)[(gb + s) >> 4] = (uint16_t)chunk_bits16(v, sh2);
+                    if (fold)  // the granule's 16 bits (gb + s is a multiple of 16)
+                        bnext[(gb + s) >> 4] = (uint16_t)chunk_bits16(v, sh2);
                     else
                         *reinterpret_cast<uint4 *>(tout + (gb + s)) = v;
                     const uint32_t ones = __popc(v.x & mk) + __popc(v.y & mk) + __popc(v.z & mk) + __popc(v.w & mk);
@@ -1324,24 +1326,24 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
             const uint64_t gb = r1 ? gb_r[1] : gb_r[0], cs = r1 ? cs_r[1] : cs_r[0];
             uint32_t one = 0;
             bool second = false;
+            uint64_t own = ~0ull;  // folded: the granule whose first position this lane's symbol lands on
             if (e < CH && c != 0xffffffffu) {
                 const uint32_t s = c * CH + (uint32_t)e;
                 const uint64_t d = gb + s;
                 if (s >= lo && s < lo + len && d < a.n) {
                     const uint32_t x = (uint32_t)s_stage[s];
-                    if (!fold) tout[d] = (T)x;
+                    tout[d] = (T)x;  // (folded: read back by the stitch)
                     one = (x >> sh2) & 1u;
                     second = c >= cs;
+                    if (fold && e == 0) own = d >> 4;
                 }
             }
             if (fold) {
-                // the 16 lanes of a partial chunk hold its slots in order:
-                // their ones go in with one OR (other runs share the word)
-                const uint32_t grp = (uint32_t)(__ballot(one != 0) >> (lane & 48)) & 0xFFFFu;
-                if (e == 0 && grp != 0) {
-                    const uint64_t p0 = gb + (uint64_t)c * CH;  // a multiple of 16
-                    atomicOr(&bnext[p0 >> 5], grp << (uint32_t)(p0 & 16));
-                }
+                // a run owns at most one shared granule: the one of its last
+                // partial chunk when that chunk starts inside the run (lanes
+                // 0 / 16 hold run 0's two edge chunks, 32 / 48 run 1's)
+                const uint64_t o2 = __shfl_down(own, 16, 64);
+                if ((lane & 31) == 0) a.fold_own[2 * t + (uint64_t)(lane >> 5)] = own < o2 ? own : o2;
             }
             if (counting) {
                 cnt[0] += (!r1 && !second) ? one : 0u;
@@ -1386,11 +1388,14 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         wave_sync();
     }
     unsigned long long r1 = r_lane;
-    // folded: a lane's destinations rise within each of its two current runs
-    // (zeros, ones; T_i is sorted by node), so each run's bits gather in one
-    // pending word and go out with one OR when the run moves past it
-    uint64_t fw0 = ~0ull, fw1 = ~0ull;
-    uint32_t fm0 = 0u, fm1 = 0u;
+    // folded: every symbol is stored at its T_{i+1} position, and the
+    // granules whose first position a symbol lands on are recorded for the
+    // stitch (counted here, appended below)
+    uint32_t nown = 0;
+    if (fold && lane == 0) {
+        a.fold_own[2 * t] = ~0ull;
+        a.fold_own[2 * t + 1] = ~0ull;
+    }
     // a lane's nodes never decrease (T_i is sorted by node): its node table
     // entry is loaded again only where the node changes, not per symbol
     uint32_t cv = (raw_elem<W, B>(raw, 0) & a.symmask) >> nsh;
@@ -1409,23 +1414,8 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
             const uint64_t dst = b ? zo.y + r1 : p - r1 + zo.x;
             r1 += b;
             if (dst < a.n) {
-                if (!fold) {
-                    tout[dst] = (T)x;
-                } else {
-                    const uint64_t wi = dst >> 5;
-                    uint64_t cw = b ? fw1 : fw0;
-                    uint32_t cm = b ? fm1 : fm0;
-                    if (wi != cw) {
-                        if (cm) atomicOr(&bnext[cw], cm);
-                        cw = wi;
-                        cm = 0u;
-                    }
-                    cm |= ((x >> sh2) & 1u) << (uint32_t)(dst & 31);
-                    fw1 = b ? cw : fw1;
-                    fm1 = b ? cm : fm1;
-                    fw0 = b ? fw0 : cw;
-                    fm0 = b ? fm0 : cm;
-                }
+                tout[dst] = (T)x;
+                nown += (fold && (dst & 15) == 0) ? 1u : 0u;
                 if (counting && ((x >> sh2) & 1u)) {
                     const uint64_t dt = dst / TILE;
                     if (lds_counts && v - vf <= vl - vf) {
@@ -1441,8 +1431,35 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         }
     }
     if (fold) {
-        if (fm0) atomicOr(&bnext[fw0], fm0);
-        if (fm1) atomicOr(&bnext[fw1], fm1);
+        // append this wave's records: one counter add per wave, then the
+        // destinations walked again (a rare path: tiles on node boundaries)
+        const uint32_t incl = wave_incl_scan(nown);
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        uint32_t at = 0;
+        if (lane == 0 && tot) at = atomicAdd(a.fold_ovf_n, tot);
+        at = (uint32_t)__builtin_amdgcn_readlane((int)at, 0) + incl - nown;
+        if (lane == 0 && (uint64_t)at + tot > a.fold_ovf_cap && tot) atomicOr(a.fold_status, 2u);
+        r1 = r_lane;
+        cv = (raw_elem<W, B>(raw, 0) & a.symmask) >> nsh;
+        zo = a.zo[nval > 0 ? cv : vf];
+#pragma unroll
+        for (int k = 0; k < E; k++) {
+            if (k < nval && nown) {
+                const uint32_t v = (raw_elem<W, B>(raw, k) & a.symmask) >> nsh;
+                if (v != cv) {
+                    cv = v;
+                    zo = a.zo[v];
+                }
+                const uint32_t b = (uint32_t)(mb >> k) & 1u;
+                const uint64_t dst = b ? zo.y + r1 : pos0 + k - r1 + zo.x;
+                r1 += b;
+                if (dst < a.n && (dst & 15) == 0) {
+                    if (at < a.fold_ovf_cap) a.fold_ovf[at] = dst >> 4;
+                    at++;
+                    nown--;
+                }
+            }
+        }
     }
     if (lds_counts) {
         wave_sync();
@@ -1541,6 +1558,10 @@ __device__ __forceinline__ LevelArgs job_level(const BatchJob &j, uint32_t i) {
     a.dwords = 0;
     a.dsh = 0;
     a.bits_next = nullptr;
+    a.fold_own = a.fold_ovf = nullptr;
+    a.fold_ovf_n = nullptr;
+    a.fold_ovf_cap = 0;
+    a.fold_status = nullptr;
     return a;
 }
 
@@ -1689,6 +1710,29 @@ hipError_t launch_zero(void *p, uint64_t bytes, uint32_t *tree_status, uint64_t 
     return hipGetLastError();
 }
 
+// ------------------------------------------------ folded last level -----
+// One thread per granule record of the folded pass (two per tile, then the
+// direct path's): the granule's 16 symbols are in T_{l-1} at its positions
+// (stored there by the runs that share it), and its 16 bits are written
+// once.  Every granule below n is written either by the pass (a whole chunk)
+// or here (exactly one record names it: the run holding its first position).
+__global__ __launch_bounds__(kThreads) void k_fold_stitch(StitchArgs a) {
+    const uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    uint64_t g = ~0ull;
+    if (k < a.nown) {
+        g = a.own[k];
+    } else {
+        const uint64_t o = k - a.nown, m = *a.ovf_n;
+        if (o < m && o < a.ovf_cap) g = a.ovf[o];
+    }
+    if (g == ~0ull) return;
+    const uint64_t p = g * 16;
+    const uint4 v = *reinterpret_cast<const uint4 *>(a.t + p);  // inside the n-byte (256-rounded) buffer
+    uint32_t bits = chunk_bits16(v, a.sh);
+    if (p + 16 > a.n) bits &= (1u << (uint32_t)(a.n - p)) - 1u;
+    a.bits16[g] = (uint16_t)bits;
+}
+
 // ------------------------------------------------ directory of a bitmap ---
 // Used for the last level when its bitmap comes out of the pass before it:
 // k_bitdir_blocks scans the popcounts of kBitDirBlocks 512-bit blocks per
@@ -1765,6 +1809,13 @@ __global__ __launch_bounds__(kThreads) void k_bitdir_small(BitDirArgs a) {
         off += c[q];
     }
     for (uint64_t k = a.nblk + threadIdx.x; k < a.rank_stride; k += kThreads) a.ranks[k] = (k == a.nblk) ? tot : 0ull;
+}
+
+hipError_t launch_fold_stitch(const StitchArgs &a, hipStream_t s) {
+    const uint64_t items = a.nown + a.ovf_cap;
+    if (items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fold_stitch, dim3((uint32_t)ceil_div(items, kThreads)), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_bitdir(const BitDirArgs &a, hipStream_t s) {

@@ -93,6 +93,9 @@ struct Layout {
     uint64_t ws_zo;                     // per level 2^i x (u64, u64)
     uint64_t ws_start;                  // per level 2^i + 1 node starts (u64)
     uint64_t ws_partials;               // scan partial sums
+    // folded last level (u8): the record count (inside the control area),
+    // two owner records per tile, and the direct path's records
+    uint64_t ws_fold_cnt, ws_fold_own, ws_fold_ovf, fold_ovf_cap;
     uint64_t work_bytes;
 };
 
@@ -136,11 +139,46 @@ struct LevelArgs {
     uint64_t dwords;
     uint32_t dsh;
     // last level folded into this pass (u8 trees, level l-2, single-node and
-    // direct split paths only): the bitmap of level i + 1, zeroed beforehand,
-    // receives bit sh - 1 of every symbol at its T_{i+1} position, and
-    // T_{i+1} itself is not written (tout is null); null otherwise
+    // direct split paths only): the bitmap of level i + 1 receives bit sh - 1
+    // of every symbol at its T_{i+1} position, as 16-bit granules (16
+    // positions, 16-aligned) with one writer each; null otherwise.  A
+    // granule wholly inside one run of a tile's split leaves the pass as one
+    // 16-bit store.  The others are shared between runs: the symbols of
+    // every edge chunk are stored at their positions in tout (T_{i+1}, not
+    // otherwise written), and the run holding a granule's first position
+    // records it (fold_own: two records per tile, one per run, ~0 for none;
+    // the direct path appends to fold_ovf), so that k_fold_stitch writes it
+    // once, after the pass.
     uint64_t *bits_next;
+    uint64_t *fold_own;
+    uint64_t *fold_ovf;
+    unsigned int *fold_ovf_n;
+    uint64_t fold_ovf_cap;
+    uint32_t *fold_status;            // bit 1 set if fold_ovf would overflow (never, by its sizing)
 };
+
+// The granules of a folded last level that the pass recorded: one thread
+// per record reads the granule's 16 symbols from T_{l-1} and writes its 16
+// bits (positions >= n as zero).
+struct StitchArgs {
+    const uint8_t *t;                 // T_{l-1} (edge symbols at their positions)
+    const uint64_t *own;              // nown records (~0: none)
+    const uint64_t *ovf;              // direct-path records, *ovf_n of them (at most ovf_cap)
+    const unsigned int *ovf_n;
+    uint16_t *bits16;                 // the last level's bitmap as 16-bit granules
+    uint64_t nown, ovf_cap, n;
+    uint32_t sh;                      // bit of the last level (0)
+};
+hipError_t launch_fold_stitch(const StitchArgs &a, hipStream_t s);
+// Records the direct path of a folded pass can append: tiles spanning
+// several nodes number fewer than the nodes of level l-2 (at most 2^(l-2)),
+// and such a tile's destinations hold at most TILE/16 + (its runs: two per
+// node) multiples of 16.
+static inline uint64_t fold_ovf_capacity(uint64_t ntiles, uint32_t levels, uint64_t tile) {
+    const uint64_t nodes = levels >= 2 ? (1ull << (levels - 2)) : 1ull;
+    const uint64_t tiles = ntiles < nodes ? ntiles : nodes;
+    return tiles * (tile / 16 + 2 * nodes + 1);
+}
 
 // Rank directory of one bitmap level from its words (entry k = ones before
 // position 512k for k < nblk, entry nblk = all ones, zero padding up to

@@ -105,6 +105,22 @@ def test_parity_last_level_from_previous_pass(sigma, lg):
         t.close()
 
 
+@pytest.mark.parametrize("n", [(1 << 21) + 4099, (1 << 22) - 13])
+def test_parity_folded_level_tiles_over_many_nodes(n):
+    # u8, sigma = 256: nine symbols in ten are 0, the rest spread over the
+    # alphabet, so the level-6 nodes other than node 0 are small and some
+    # tiles of the pass that also writes the last level span dozens of them
+    # (its direct path then leaves many shared 16-position granules)
+    rng = np.random.Generator(np.random.PCG64(n))
+    S = np.where(rng.random(n) < 0.9, 0, rng.integers(0, 256, n)).astype(np.uint8)
+    t, _ = build_and_compare(S, 256, tag="fold-many-nodes")
+    t.close()
+    # the same after a sort of the tail: runs of every symbol, nodes in order
+    S[n // 2:] = np.sort(S[n // 2:])
+    t, _ = build_and_compare(S, 256, tag="fold-sorted-tail")
+    t.close()
+
+
 def test_parity_gauss_mix_large_alphabet():
     S, sigma = wtgen.workload("c3@lg22")
     t, _ = build_and_compare(S, sigma, tag="c3@lg22")
