@@ -103,24 +103,26 @@ def test_status_strings():
 
 def test_tune_table_set_get_and_validation():
     wt = _wt()
-    rc, before = wt.wt_tune_get(0, 1, 8, 20)
+    # u16, sigma = 2^16 (16 levels, no folded last level, whose record area
+    # grows with the tile): the workspace follows the per-tile counters
+    rc, before = wt.wt_tune_get(0, 2, 16, 20)
     assert rc == wt.WT_OK and before in (32, 64, 128)
     try:
-        assert wt.wt_tune_set(0, 1, 8, 20, 64) == wt.WT_OK
-        _, _, wb64 = wt.wt_footprint(1 << 20, 256, 1)
-        assert wt.wt_tune_set(0, 1, 8, 20, 32) == wt.WT_OK
-        assert wt.wt_tune_get(0, 1, 8, 20) == (wt.WT_OK, 32)
-        rc, tb32, wb32 = wt.wt_footprint(1 << 20, 256, 1)
+        assert wt.wt_tune_set(0, 2, 16, 20, 64) == wt.WT_OK
+        _, _, wb64 = wt.wt_footprint(1 << 20, 1 << 16, 2)
+        assert wt.wt_tune_set(0, 2, 16, 20, 32) == wt.WT_OK
+        assert wt.wt_tune_get(0, 2, 16, 20) == (wt.WT_OK, 32)
+        rc, tb32, wb32 = wt.wt_footprint(1 << 20, 1 << 16, 2)
         assert rc == wt.WT_OK
         # half the tile -> twice the per-tile counters; the tree is unchanged
         assert wb32 > wb64
-        assert tb32 == wt.wt_footprint(1 << 20, 256, 1)[1]
+        assert tb32 == wt.wt_footprint(1 << 20, 1 << 16, 2)[1]
         # the batched mode keeps its own entry
-        assert wt.wt_tune_get(1, 1, 8, 20)[0] == wt.WT_OK
-        assert wt.wt_tune_set(0, 1, 8, 20, 0) == wt.WT_OK
-        assert wt.wt_tune_get(0, 1, 8, 20) == (wt.WT_OK, 64)
+        assert wt.wt_tune_get(1, 2, 16, 20)[0] == wt.WT_OK
+        assert wt.wt_tune_set(0, 2, 16, 20, 0) == wt.WT_OK
+        assert wt.wt_tune_get(0, 2, 16, 20) == (wt.WT_OK, 64)
     finally:
-        wt.wt_tune_set(0, 1, 8, 20, before)
+        wt.wt_tune_set(0, 2, 16, 20, before)
     for bad in [(2, 1, 8, 20, 64), (0, 3, 8, 20, 64), (0, 1, 0, 20, 64), (0, 1, 9, 20, 64),
                 (0, 4, 25, 20, 64), (0, 1, 8, 41, 64), (0, 1, 8, 20, 128), (0, 2, 8, 20, 48),
                 (0, 2, 8, 20, 3)]:
