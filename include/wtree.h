@@ -176,6 +176,27 @@ int wt_build_buffered(const void *S, const wt_desc *desc, uint64_t buffer_syms, 
 int wt_batch_footprint(uint32_t m, const wt_desc *descs, uint64_t *work_bytes);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): wt_build
+ * with the workspace taken from a fixed device array inside the library
+ * (WT_NOALLOC_WORK_BYTES on each device, held until the process ends)
+ * instead of d_work.  No device or host memory is allocated and no handle is
+ * returned: the tree lands in d_tree (tree_bytes >= wt_footprint's
+ * tree_bytes) with the layout above, and its status word (the first 32 bits
+ * of d_tree: 0 = success, bit 0 = some symbol >= sigma) is valid once the
+ * stream has passed the build.  WT_ENOMEM when wt_footprint's work_bytes
+ * for *desc exceed WT_NOALLOC_WORK_BYTES (for example u8 inputs above about
+ * 2^25 symbols), WT_EINVAL as for wt_build, WT_EDEVICE if the array's
+ * address cannot be read on the current device (done once per device, on
+ * the first call there).  The array is shared by every call on a device and
+ * keeps the last build's contents: builds that overlap on one device (other
+ * streams, other threads) race and must be serialised by the caller.
+ * Profiling (wt_prof_enable) must be off.
+ */
+#define WT_NOALLOC_WORK_BYTES (64ull << 20)
+int wt_build_noalloc(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t tree_bytes, void *stream);
+
+/*
  * Build m independent trees in one batched launch sequence on `stream`: the
  * construction of wt_build (Sections 3.1 and 3.2) for many sequences at
  * once, the segments of all of them sharing each launch the way Algorithm

@@ -719,11 +719,53 @@ static hipError_t enqueue_buffered(const uint8_t *S, const BufPlan &P, uint8_t *
     return err;
 }
 
+// ------------------------------------------------ no-allocation build ---
+// Workspace of wt_build_noalloc: a file-scope device array, one copy on
+// every device the library runs on, held until the process ends.  In host
+// code its name is not a device address: the address of the current
+// device's copy comes from hipGetSymbolAddress, taken once per device on the
+// first call there, and only that pointer reaches the kernels.
+static __device__ __align__(256) uint8_t scratch[WT_NOALLOC_WORK_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static uint8_t *g_scratch[kMaxDevices];
+
+static int scratch_on_current_device(uint8_t **p) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return WT_EDEVICE;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) return WT_EDEVICE;
+        g_scratch[dev] = reinterpret_cast<uint8_t *>(ptr);
+    }
+    *p = g_scratch[dev];
+    return WT_OK;
+}
+
 }  // namespace wt
 
 using namespace wt;
 
 extern "C" {
+
+int wt_build_noalloc(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t tree_bytes, void *stream) {
+    int rc = check_desc(desc);
+    if (rc != WT_OK) return rc;
+    if (!d_tree || (desc->n > 0 && !d_S)) return WT_EINVAL;
+    if (((uintptr_t)d_S & 15) || ((uintptr_t)d_tree & 255)) return WT_EINVAL;
+    Layout L;
+    make_layout(desc->n, desc->sigma, desc->width, false, &L);
+    if (tree_bytes < L.tree_bytes || L.work_bytes > WT_NOALLOC_WORK_BYTES) return WT_ENOMEM;
+    uint8_t *work = nullptr;
+    rc = scratch_on_current_device(&work);
+    if (rc != WT_OK) return rc;
+    return enqueue_build(d_S, L, reinterpret_cast<uint8_t *>(d_tree), work, reinterpret_cast<hipStream_t>(stream)) ==
+                   hipSuccess
+               ? WT_OK
+               : WT_EDEVICE;
+}
 
 int wt_footprint(const wt_desc *desc, uint64_t *tree_bytes, uint64_t *work_bytes) {
     int rc = check_desc(desc);

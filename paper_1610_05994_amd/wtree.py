@@ -27,8 +27,9 @@ EXPORTED = [
     "wt_access", "wt_rank", "wt_select", "wt_query_multi_footprint", "wt_query_multi", "wt_strerror",
     "wt_tune_set", "wt_tune_get", "wt_buffered_footprint", "wt_build_buffered",
     "wt_multiary_footprint", "wt_build_multiary", "wt_multiary_levels",
-    "wt_prof_enable", "wt_prof_read",
+    "wt_prof_enable", "wt_prof_read", "wt_build_noalloc",
 ]
+WT_NOALLOC_WORK_BYTES = 64 << 20
 
 
 class WtError(RuntimeError):
@@ -63,6 +64,7 @@ def lib():
         "wt_footprint": ([P(wt_desc), P(u64), P(u64)], i32),
         "wt_build": ([vp, P(wt_desc), vp, u64, vp, u64, vp, P(vp)], i32),
         "wt_build_matrix": ([vp, P(wt_desc), vp, u64, vp, u64, vp, P(vp)], i32),
+        "wt_build_noalloc": ([vp, P(wt_desc), vp, u64, vp], i32),
         "wt_matrix_zeros": ([vp, P(u64)], i32),
         "wt_buffered_footprint": ([P(wt_desc), u64, P(u64), P(u64)], i32),
         "wt_multiary_footprint": ([P(wt_desc), P(u64), P(u64)], i32),
@@ -132,6 +134,11 @@ def wt_build(d_S: int, n: int, sigma: int, width: int, d_tree: int, tree_bytes: 
     h = ctypes.c_void_p()
     rc = lib().wt_build(d_S, ctypes.byref(d), d_tree, tree_bytes, d_work, work_bytes, stream, ctypes.byref(h))
     return rc, h.value
+
+
+def wt_build_noalloc(d_S: int, n: int, sigma: int, width: int, d_tree: int, tree_bytes: int, stream: int) -> int:
+    d = wt_desc(n, sigma, width)
+    return lib().wt_build_noalloc(d_S, ctypes.byref(d), d_tree, tree_bytes, stream)
 
 
 def wt_build_matrix(d_S: int, n: int, sigma: int, width: int, d_tree: int, tree_bytes: int, d_work: int,
