@@ -82,6 +82,12 @@ def lib():
         L.wto_rank4.restype = ctypes.c_int
         L.wto_select4.argtypes = [vp, u64, u32, u32, u64, vp]
         L.wto_select4.restype = ctypes.c_int
+        L.wto_huffman_lengths.argtypes = [vp, u32, vp, vp]
+        L.wto_huffman_lengths.restype = ctypes.c_int
+        L.wto_huffman_codes.argtypes = [vp, u32, u32, vp]
+        L.wto_huffman_codes.restype = ctypes.c_int
+        L.wto_build_huffman.argtypes = [vp, u64, u32, u32, vp, vp, u32, vp, vp, vp, vp]
+        L.wto_build_huffman.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -288,3 +294,164 @@ def select4(t: OracleTree4, c: int, j: int):
     if rc != OK:
         raise ValueError("select4 status %d" % rc)
     return int(out.value)
+
+
+# ------------------------------------------------- Huffman-shaped tree ---
+
+def huffman_lengths(counts: np.ndarray):
+    """Code lengths (uint8 per symbol, 0 for absent symbols) and the longest."""
+    counts = np.ascontiguousarray(counts, dtype=np.uint64)
+    sigma = int(counts.shape[0])
+    ln = np.zeros(sigma, dtype=np.uint8)
+    mx = ctypes.c_uint32()
+    rc = lib().wto_huffman_lengths(_ptr(counts), sigma, _ptr(ln), ctypes.byref(mx))
+    if rc != OK:
+        raise ValueError("huffman lengths status %d" % rc)
+    return ln, int(mx.value)
+
+
+def huffman_codes(lengths: np.ndarray, maxlen: int) -> np.ndarray:
+    """Canonical codes (right-aligned in each symbol's length)."""
+    lengths = np.ascontiguousarray(lengths, dtype=np.uint8)
+    code = np.zeros(lengths.shape[0], dtype=np.uint32)
+    rc = lib().wto_huffman_codes(_ptr(lengths), lengths.shape[0], maxlen, _ptr(code))
+    if rc != OK:
+        raise ValueError("huffman codes status %d" % rc)
+    return code
+
+
+@dataclass
+class OracleHuffman:
+    n: int
+    sigma: int
+    levels: int                 # the longest code length
+    lengths: np.ndarray         # (sigma,) uint8
+    codes: np.ndarray           # (sigma,) uint32, right-aligned
+    sizes: list                 # n_d: symbols whose code is longer than d
+    bitmaps: list               # per depth: words_per_level(n_d) uint64
+    ranks: list                 # per depth: rank_stride(n_d) uint64, or None
+    only: int = -1              # with no levels and n > 0: the one symbol of S
+
+
+def build_huffman(S: np.ndarray, sigma: int, with_ranks: bool = True) -> OracleHuffman:
+    """Huffman-shaped wavelet tree of S from its definition (code lengths from
+    the symbol counts of S, canonical codes, one bitmap per depth)."""
+    S = np.ascontiguousarray(S)
+    width = S.dtype.itemsize
+    n = int(S.shape[0])
+    if n and int(S.max()) >= sigma:
+        raise ValueError("symbol out of range")
+    counts = np.bincount(S.astype(np.int64), minlength=sigma).astype(np.uint64) if n else np.zeros(sigma, np.uint64)
+    ln, L = huffman_lengths(counts)
+    code = huffman_codes(ln, L)
+    sizes = [int(counts[ln > d].sum()) for d in range(L)]
+    bofs = np.zeros(max(L, 1), dtype=np.uint64)
+    rofs = np.zeros(max(L, 1), dtype=np.uint64)
+    tb = tr = 0
+    for d in range(L):
+        bofs[d], rofs[d] = tb, tr
+        tb += words_per_level(sizes[d])
+        tr += rank_stride(sizes[d])
+    B = np.zeros(max(tb, 1), dtype=np.uint64)
+    R = np.zeros(max(tr, 1), dtype=np.uint64) if with_ranks else None
+    rc = lib().wto_build_huffman(_ptr(S), n, sigma, width, _ptr(ln), _ptr(code), L, _ptr(bofs), _ptr(rofs),
+                                 _ptr(B), _ptr(R) if R is not None else None)
+    if rc != OK:
+        raise ValueError("oracle wto_build_huffman status %d" % rc)
+    bm = [B[int(bofs[d]):int(bofs[d]) + words_per_level(sizes[d])].copy() for d in range(L)]
+    rk = [R[int(rofs[d]):int(rofs[d]) + rank_stride(sizes[d])].copy() for d in range(L)] if with_ranks else None
+    only = int(np.flatnonzero(counts)[0]) if (L == 0 and n > 0) else -1
+    return OracleHuffman(n, sigma, L, ln, code, sizes, bm, rk, only)
+
+
+def _bits(words: np.ndarray, size: int) -> np.ndarray:
+    """A depth's bitmap as size 0/1 values (position p = word p/64, bit p%64)."""
+    b = np.unpackbits(words.view(np.uint8), bitorder="little")
+    return b[:size].astype(np.int64)
+
+
+class HuffmanWalker:
+    """Queries on an OracleHuffman by walking its bitmaps (Section 2.2's
+    navigation by counting bits of a node's range), with the internal nodes
+    of every depth laid out from left to right: a node's 0-child and 1-child
+    take, in that order, the next places at the next depth when they are
+    internal, and a child whose prefix is a code is that symbol's leaf."""
+
+    def __init__(self, t: OracleHuffman):
+        self.t = t
+        self.bits = [_bits(t.bitmaps[d], t.sizes[d]) for d in range(t.levels)]
+        self.leaf = {}
+        for s in range(t.sigma):
+            if t.lengths[s]:
+                self.leaf[(int(t.lengths[s]), int(t.codes[s]))] = s
+        # node table: depth -> {prefix: (start, size)}
+        self.nodes = []
+        if t.levels:
+            self.nodes.append({0: (0, t.n)})
+        for d in range(t.levels):
+            nxt, pos = {}, 0
+            for pre in sorted(self.nodes[d]):
+                b, sz = self.nodes[d][pre]
+                ones = int(self.bits[d][b:b + sz].sum())
+                for bit, cnt in ((0, sz - ones), (1, ones)):
+                    child = 2 * pre + bit
+                    if (d + 1, child) not in self.leaf and cnt > 0:
+                        nxt[child] = (pos, cnt)
+                        pos += cnt
+            self.nodes.append(nxt)
+
+    def access(self, i: int) -> int:
+        if self.t.levels == 0:
+            return self.t.only
+        pre, p = 0, i
+        for d in range(self.t.levels):
+            b, sz = self.nodes[d][pre]
+            bit = int(self.bits[d][b + p])
+            p = int((self.bits[d][b:b + p] == bit).sum())
+            pre = 2 * pre + bit
+            if (d + 1, pre) in self.leaf:
+                return self.leaf[(d + 1, pre)]
+        raise AssertionError("walk did not end at a leaf")
+
+    def rank(self, c: int, i: int) -> int:
+        L = int(self.t.lengths[c]) if c < self.t.sigma else 0
+        if self.t.levels == 0:
+            return i if c == self.t.only else 0
+        if L == 0:
+            return 0
+        code = int(self.t.codes[c])
+        pre, cnt = 0, i
+        for d in range(L):
+            b, sz = self.nodes[d][pre]
+            bit = (code >> (L - 1 - d)) & 1
+            cnt = int((self.bits[d][b:b + cnt] == bit).sum())
+            pre = 2 * pre + bit
+        return cnt
+
+    def select(self, c: int, j: int):
+        """0-based position of the j-th (1-based) c, or None."""
+        if j < 1:
+            return None
+        if self.t.levels == 0:
+            return j - 1 if (c == self.t.only and j <= self.t.n) else None
+        L = int(self.t.lengths[c]) if c < self.t.sigma else 0
+        if L == 0:
+            return None
+        code = int(self.t.codes[c])
+        path, pre = [], 0
+        for d in range(L):
+            path.append(pre)
+            pre = 2 * pre + ((code >> (L - 1 - d)) & 1)
+        # leaf size: the count of its bit in the parent node
+        d = L - 1
+        b, sz = self.nodes[d][path[d]]
+        bit = code & 1
+        if j > int((self.bits[d][b:b + sz] == bit).sum()):
+            return None
+        k = j - 1                              # index among the leaf's symbols
+        for d in range(L - 1, -1, -1):
+            b, sz = self.nodes[d][path[d]]
+            bit = (code >> (L - 1 - d)) & 1
+            where = np.flatnonzero(self.bits[d][b:b + sz] == bit)
+            k = int(where[k])                   # index inside the node at depth d
+        return k

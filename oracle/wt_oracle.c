@@ -640,3 +640,187 @@ int wto_select4(const uint64_t *D, uint64_t n, uint32_t sigma, uint32_t c, uint6
     *out = p;
     return WTO_OK;
 }
+
+/* ---------------------------------------------- Huffman-shaped tree ---- */
+/*
+ * Huffman-shaped wavelet tree, one of the compressed wavelet trees that
+ * Section 5 names as future work (the paper gives no definition; this takes
+ * the standard one): the tree's shape is the code tree of a Huffman code for
+ * the symbol frequencies of S.  A symbol that occurs is a leaf at the depth
+ * of its code length, reached by following its code bits (0 = left); every
+ * internal node holds a bitmap listing, for the symbols of its subtree in
+ * their input order, the next bit of their codes.  The pointerless layout
+ * keeps one bitmap per depth d: the concatenation, from left to right, of
+ * the bitmaps of the internal nodes at depth d.
+ *
+ * A Huffman code is not unique, so the construction fixes every choice
+ * (readings listed in the design notes):
+ *  - lengths: Huffman's merging of the two lightest items, done with two
+ *    first-in first-out queues -- the symbols that occur, ordered by (count,
+ *    symbol), and the merged items in the order they are made; the lighter
+ *    front is taken, the symbol queue on equal weights; the code length of a
+ *    symbol is the depth of its leaf.  One symbol alone has length 0 (a tree
+ *    with no levels), as has every symbol when n = 0;
+ *  - codes: canonical, from the lengths: symbols ordered by (length,
+ *    symbol); the first gets 0, each next one the previous code plus one,
+ *    shifted left by the increase in length.
+ * Position p of depth d sits in word p/64 at bit p%64 of that depth's
+ * round_up(ceil(n_d/64), 8) words (n_d = symbols whose code is longer than d),
+ * every bit past n_d zero; its directory holds ceil(n_d/512) + 1 counts in a
+ * slot of round_up(that, 8) entries, as for the balanced tree.
+ */
+
+static int cmp_count_sym(const void *a, const void *b, const uint64_t *counts)
+{
+    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    if (counts[x] != counts[y]) return counts[x] < counts[y] ? -1 : 1;
+    return x < y ? -1 : (x > y);
+}
+
+/* merge sort of symbol indices by (count, symbol) */
+static void sort_by_count(uint32_t *v, uint32_t *tmp, uint64_t k, const uint64_t *counts)
+{
+    if (k < 2) return;
+    uint64_t h = k / 2;
+    sort_by_count(v, tmp, h, counts);
+    sort_by_count(v + h, tmp, k - h, counts);
+    uint64_t a = 0, b = h, o = 0;
+    while (a < h && b < k) tmp[o++] = (cmp_count_sym(&v[b], &v[a], counts) < 0) ? v[b++] : v[a++];
+    while (a < h) tmp[o++] = v[a++];
+    while (b < k) tmp[o++] = v[b++];
+    memcpy(v, tmp, k * sizeof(uint32_t));
+}
+
+/* Code lengths of the sigma symbols (0 for a symbol that does not occur). */
+int wto_huffman_lengths(const uint64_t *counts, uint32_t sigma, uint8_t *len, uint32_t *maxlen)
+{
+    if (sigma == 0) return WTO_EINVAL;
+    memset(len, 0, sigma);
+    *maxlen = 0;
+    uint64_t k = 0;
+    for (uint32_t c = 0; c < sigma; c++) k += counts[c] > 0;
+    if (k < 2) return WTO_OK;
+    uint32_t *leaf = (uint32_t *)malloc(k * sizeof(uint32_t));
+    uint32_t *tmp = (uint32_t *)malloc(k * sizeof(uint32_t));
+    uint64_t *iw = (uint64_t *)malloc(k * sizeof(uint64_t));      /* merged items' weights */
+    uint64_t *parent = (uint64_t *)malloc((2 * k) * sizeof(uint64_t)); /* leaves 0..k-1, merged k.. */
+    uint32_t *depth = (uint32_t *)malloc((2 * k) * sizeof(uint32_t));
+    if (!leaf || !tmp || !iw || !parent || !depth) {
+        free(leaf); free(tmp); free(iw); free(parent); free(depth);
+        return WTO_ENOMEM;
+    }
+    uint64_t q = 0;
+    for (uint32_t c = 0; c < sigma; c++)
+        if (counts[c] > 0) leaf[q++] = c;
+    sort_by_count(leaf, tmp, k, counts);
+    uint64_t lf = 0, mf = 0, made = 0;  /* fronts of the two queues, merged items made */
+    while (made < k - 1) {
+        uint64_t pick[2];
+        uint64_t w = 0;
+        for (int t = 0; t < 2; t++) {
+            int take_leaf = lf < k && (mf >= made || counts[leaf[lf]] <= iw[mf]);
+            if (take_leaf) { pick[t] = lf; w += counts[leaf[lf]]; lf++; }
+            else           { pick[t] = k + mf; w += iw[mf]; mf++; }
+        }
+        iw[made] = w;
+        parent[pick[0]] = k + made;
+        parent[pick[1]] = k + made;
+        made++;
+    }
+    /* the last merged item is the root; parents are made after children */
+    depth[k + made - 1] = 0;
+    for (uint64_t m = made - 1; m-- > 0;) depth[k + m] = depth[parent[k + m]] + 1;
+    for (uint64_t i = 0; i < k; i++) {
+        uint32_t d = depth[parent[i]] + 1;
+        if (d > 255) d = 255;
+        len[leaf[i]] = (uint8_t)d;
+        if (d > *maxlen) *maxlen = d;
+    }
+    free(leaf); free(tmp); free(iw); free(parent); free(depth);
+    return WTO_OK;
+}
+
+/* Canonical codes from the lengths (code[c] right-aligned in len[c] bits). */
+int wto_huffman_codes(const uint8_t *len, uint32_t sigma, uint32_t maxlen, uint32_t *code)
+{
+    if (maxlen > 32) return WTO_EINVAL;
+    memset(code, 0, (uint64_t)sigma * sizeof(uint32_t));
+    uint64_t c = 0;
+    uint32_t prev = 0;
+    int first = 1;
+    for (uint32_t L = 1; L <= maxlen; L++) {
+        for (uint32_t s = 0; s < sigma; s++) {
+            if (len[s] != L) continue;
+            if (first) { c = 0; first = 0; }
+            else c = (c + 1) << (L - prev);
+            prev = L;
+            code[s] = (uint32_t)c;
+        }
+    }
+    return WTO_OK;
+}
+
+/* bit d (from the top, d < len) of symbol s's code */
+static uint32_t code_bit(const uint8_t *len, const uint32_t *code, uint32_t s, uint32_t d)
+{
+    return (code[s] >> (len[s] - 1 - d)) & 1u;
+}
+
+/* the first d bits of s's code (d <= len) */
+static uint32_t code_prefix(const uint8_t *len, const uint32_t *code, uint32_t s, uint32_t d)
+{
+    return d == 0 ? 0u : (code[s] >> (len[s] - d));
+}
+
+/*
+ * Build the maxlen depth bitmaps (and, when R != NULL, their directories).
+ * Depth d's words start at B + bofs[d], its directory at R + rofs[d].
+ * A holds the symbols of the current depth's internal nodes, node after node
+ * from left to right, each node's symbols in input order; a node is a run
+ * of equal code prefixes.  Each node's bitmap is the next code bit of its
+ * symbols; the next depth splits every node into its 0-child and then its
+ * 1-child (each in order), leaving out the symbols whose code ends here
+ * (they are leaves).  Returns WTO_ERANGE if a symbol is >= sigma or has no
+ * code (length 0 while the tree has levels).
+ */
+int wto_build_huffman(const void *S, uint64_t n, uint32_t sigma, uint32_t width, const uint8_t *len,
+                      const uint32_t *code, uint32_t maxlen, const uint64_t *bofs, const uint64_t *rofs,
+                      uint64_t *B, uint64_t *R)
+{
+    if (sigma == 0 || (width != 1 && width != 2 && width != 4)) return WTO_EINVAL;
+    for (uint64_t j = 0; j < n; j++) {
+        uint64_t s = sym_at(S, width, j);
+        if (s >= sigma || (maxlen > 0 && len[s] == 0)) return WTO_ERANGE;
+    }
+    if (maxlen == 0) return WTO_OK;
+    uint32_t *A = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    uint32_t *Anext = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    if (!A || !Anext) { free(A); free(Anext); return WTO_ENOMEM; }
+    uint64_t cur = n;
+    for (uint64_t j = 0; j < n; j++) A[j] = (uint32_t)sym_at(S, width, j);
+    for (uint32_t d = 0; d < maxlen; d++) {
+        uint64_t *Bd = B + bofs[d];
+        uint64_t W = wto_words_per_level(cur);
+        memset(Bd, 0, W * sizeof(uint64_t));
+        uint64_t nxt = 0;
+        uint64_t p = 0;
+        while (p < cur) {
+            /* the node: the run of symbols sharing A[p]'s first d code bits */
+            uint32_t pre = code_prefix(len, code, A[p], d);
+            uint64_t e = p;
+            while (e < cur && code_prefix(len, code, A[e], d) == pre) e++;
+            for (uint64_t k = p; k < e; k++)
+                if (code_bit(len, code, A[k], d)) Bd[k >> 6] |= 1ull << (k & 63);
+            for (int b = 0; b < 2; b++)
+                for (uint64_t k = p; k < e; k++)
+                    if (code_bit(len, code, A[k], d) == (uint32_t)b && len[A[k]] > d + 1) Anext[nxt++] = A[k];
+            p = e;
+        }
+        if (R) rank_directory(Bd, cur, R + rofs[d]);
+        uint32_t *t = A; A = Anext; Anext = t;
+        cur = nxt;
+    }
+    free(A);
+    free(Anext);
+    return WTO_OK;
+}
