@@ -159,37 +159,66 @@ def whole_build_traffic(args, ms_per_step: float):
     return {"bytes": b, "gbps": gbps, "frac_of_peak": gbps / HBM_PEAK_GBPS}
 
 
+def host_facts() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cores_available": aff}
+
+
+def _workload_input(workload: str, lg: int):
+    return wtgen.workload(workload if not lg else "%s@lg%d" % (workload, lg))
+
+
 def cpu_baseline(workload: str, lg: int, runs: int, matrix: bool = False, arity: int = 2):
+    """The sequential oracle on the workload (its full size unless lg is
+    set), on one host core: the calling thread is pinned to one CPU of its
+    affinity set while it runs."""
     import oracle
-    S, sigma = wtgen.workload("%s@lg%d" % (workload, lg))
+    S, sigma = _workload_input(workload, lg)
     build = oracle.build_matrix if matrix else (oracle.build4 if arity == 4 else oracle.build)
     build(S[:4096], sigma)  # load + warm the library
-    times = []
-    for _ in range(runs):
-        t0 = time.perf_counter()
-        build(S, sigma)
-        times.append(time.perf_counter() - t0)
-    med = statistics.median(times)
-    # the paper times construction without the rank structures: the same
-    # oracle with the directories switched off
-    plain = []
-    for _ in range(runs):
+    pinned = None
+    if hasattr(os, "sched_setaffinity"):
+        saved = os.sched_getaffinity(0)
+        pinned = min(saved)
+        os.sched_setaffinity(0, {pinned})
+    try:
+        times = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            build(S, sigma)
+            times.append(time.perf_counter() - t0)
+        med = statistics.median(times)
+        # the paper times construction without the rank structures: the same
+        # oracle with the directories switched off (one run)
         t0 = time.perf_counter()
         if arity == 4:
             build(S, sigma, with_dir=False)
         else:
             build(S, sigma, with_ranks=False)
-        plain.append(time.perf_counter() - t0)
-    med_plain = statistics.median(plain)
+        plain = time.perf_counter() - t0
+    finally:
+        if pinned is not None:
+            os.sched_setaffinity(0, saved)
+    n = S.shape[0]
     return {
-        "value": S.shape[0] / med,
+        "value": n / med,
         "unit": "symbols/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": "first-principles sequential oracle (gcc -O2, one thread) on n=2^%d symbols of the same "
-                  "generator and distribution, median of %d runs of %.2f s each, bitmaps + rank directories"
-                  % (lg, runs, med),
-        "value_without_directories": S.shape[0] / med_plain,
+        "sample": "first-principles sequential oracle (gcc -O2, one thread pinned to CPU %s) on the whole "
+                  "workload input (n=%d), median of %d runs of %.2f s each, bitmaps + rank directories"
+                  % (pinned, n, runs, med),
+        "value_without_directories": n / plain,
+        "host": host_facts(),
     }
 
 
@@ -197,7 +226,7 @@ def cpu_multicore(workload: str, lg: int, runs: int):
     """The paper's parallel algorithms (pwt, dd) on every host core, on the
     same bounded sample as the oracle baseline."""
     from paper_1610_05994_amd import cpu_baseline as cb
-    S, sigma = wtgen.workload("%s@lg%d" % (workload, lg))
+    S, sigma = _workload_input(workload, lg)
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     threads = int(os.environ.get("OMP_NUM_THREADS", threads))
     out = {}
@@ -211,7 +240,7 @@ def cpu_multicore(workload: str, lg: int, runs: int):
             assert rc == 0
         med = statistics.median(times)
         out[algo] = {"value": S.shape[0] / med, "unit": "symbols/s", "cores": threads,
-                     "sample": "n=2^%d symbols of the same generator, median of %d runs of %.3f s" % (lg, runs, med)}
+                     "sample": "n=%d symbols of the workload, median of %d runs of %.3f s" % (S.shape[0], runs, med)}
     return out
 
 
@@ -231,8 +260,11 @@ def main() -> int:
                          "page-locked host memory (PCIe included in the step) or, with --buffered-source "
                          "device, from HBM")
     ap.add_argument("--buffered-source", default="host", choices=["host", "device"])
-    ap.add_argument("--cpu-sample-lg", type=int, default=26)
+    ap.add_argument("--cpu-sample-lg", type=int, default=0,
+                    help="time the CPU baselines on 2^LG symbols of the workload (0: its full size)")
     ap.add_argument("--cpu-runs", type=int, default=3)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="default line only: skip the c3 and c4 measurements added to it under 'extra'")
     ap.add_argument("--input-cache", default="",
                     help="directory to keep the generated input between runs (.npy)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -245,14 +277,60 @@ def main() -> int:
               "benchmark takes no multi-GPU configuration (--gpus 1).", file=sys.stderr)
         return 2
 
+    if args.workload == "c4":
+        print(json.dumps(bench_batch(args)), flush=True)
+        return 0
+    if args.workload == "c5":
+        return bench_serve(args)
+    default = args.workload == "c2" and not (args.matrix or args.buffered or args.arity == 4)
+    out = bench_single(args)
+    if out is None:
+        return 2
+    if not args.no_cpu_baseline:
+        lg = args.cpu_sample_lg
+        print("bench: CPU oracle baseline on n=2^%s" % (lg if lg else "full"), file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.workload, lg, args.cpu_runs, args.matrix, args.arity)
+        out["cpu_multicore"] = cpu_multicore(args.workload, lg, args.cpu_runs)
+    if default and not args.no_extra:
+        out["extra"] = extra_workloads(args)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def extra_workloads(args) -> dict:
+    """The large-alphabet single build (c3) and the batched build (c4),
+    measured in the same run as the headline line with fewer steps: time per
+    build, symbols/s, the level-pass roofline, the compulsory-byte fraction,
+    and for the batch its speedup over one build call per sequence."""
+    import torch
+    ex = {}
+    a3 = argparse.Namespace(**vars(args))
+    a3.workload, a3.steps, a3.warmup = "c3", max(5, args.steps // 4), 1
+    r3 = bench_single(a3)
+    ex["c3"] = {"workload": r3["config"]["workload"], "steps": a3.steps, "ms_per_step": r3["ms_per_step"],
+                "symbols_per_s": r3["value"], "build_latency_ms": r3["build_latency_ms"],
+                "roofline": {k: r3["roofline"][k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic",
+                                                             "kernel", "avg_launch_us", "frac_of_copy")},
+                "compulsory_bytes": r3["compulsory_bytes"], "whole_build_traffic": r3["whole_build_traffic"]}
+    del r3
+    torch.cuda.empty_cache()
+    a4 = argparse.Namespace(**vars(args))
+    a4.workload, a4.steps, a4.warmup = "c4", 2, 1
+    r4 = bench_batch(a4)
+    ex["c4"] = {"workload": r4["config"]["workload"], "steps": a4.steps, "ms_per_step": r4["ms_per_step"],
+                "symbols_per_s": r4["value"], "roofline": r4["roofline"], "compulsory_bytes": r4["compulsory_bytes"],
+                "one_call_per_sequence": r4["one_call_per_sequence"]}
+    torch.cuda.empty_cache()
+    return ex
+
+
+def bench_single(args):
+    """One single-build workload (c1-c3, or a variant): returns the JSON
+    object of its line, without the CPU baselines."""
     import torch
 
     from paper_1610_05994_amd import wtree
 
-    if args.workload == "c4":
-        return bench_batch(args)
-    if args.workload == "c5":
-        return bench_serve(args)
     dev = torch.device("cuda:0")
     print("bench: generating workload %s" % args.workload, file=sys.stderr, flush=True)
     S, sigma = None, None
@@ -269,7 +347,7 @@ def main() -> int:
     n, width = S.shape[0], S.dtype.itemsize
     if (args.buffered or args.arity == 4) and args.matrix or (args.buffered and args.arity == 4):
         print("bench.py: --matrix, --arity 4 and --buffered are separate variants", file=sys.stderr)
-        return 2
+        return None
     if args.buffered and args.buffered_source == "host":
         view = {1: np.uint8, 2: np.int16, 4: np.int32}[width]
         dS = torch.from_numpy(S.view(view)).pin_memory()
@@ -414,15 +492,10 @@ def main() -> int:
             "merge_gbps": (sum(r["bytes"] for r in mg) / (mg_ms / 1e3) / 1e9) if mg_ms > 0 else None,
             "workspace_bytes": wb,
         }
-    if not args.no_cpu_baseline:
-        print("bench: CPU oracle baseline on n=2^%d" % args.cpu_sample_lg, file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_lg, args.cpu_runs, args.matrix, args.arity)
-        out["cpu_multicore"] = cpu_multicore(args.workload, args.cpu_sample_lg, args.cpu_runs)
-    print(json.dumps(out), flush=True)
-    return 0
+    return out
 
 
-def bench_batch(args) -> int:
+def bench_batch(args) -> dict:
     """Batched build of many uneven sequences vs one build call per sequence."""
     import torch
 
@@ -510,6 +583,9 @@ def bench_batch(args) -> int:
     lvl_ms = sum(r["ms"] for r in lvl)
     lvl_bytes = sum(r["bytes"] for r in lvl)
     achieved = lvl_bytes / (lvl_ms / 1e3) / 1e9 if lvl_ms > 0 else 0.0
+    # compulsory bytes: read every sequence once, write every tree once
+    qmin = sum(d[0] * d[2] for d in descs) + sum(tb - 256 for tb in tbytes)
+    qmin_gbps = qmin / (ms_batch / 1e3) / 1e9
     out = {
         "metric": METRIC,
         "value": total / (ms_batch / 1e3),
@@ -529,11 +605,12 @@ def bench_batch(args) -> int:
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
                      "kernel": "batched build kernels: one-workgroup builds of the short sequences and the "
                                "level phases (supsum + prep + level pass) of the long ones"},
+        "compulsory_bytes": {"bytes": qmin, "gbps": qmin_gbps, "frac_of_peak": qmin_gbps / HBM_PEAK_GBPS},
         "one_call_per_sequence": {"ms": ms_single, "symbols_per_s": total / (ms_single / 1e3),
                                   "batched_speedup": ms_single / ms_batch},
     }
-    print(json.dumps(out), flush=True)
-    return 0
+    del dS, trees, work, work1
+    return out
 
 
 def bench_serve(args) -> int:
