@@ -176,6 +176,53 @@ int wt_build_buffered(const void *S, const wt_desc *desc, uint64_t buffer_syms, 
 int wt_batch_footprint(uint32_t m, const wt_desc *descs, uint64_t *work_bytes);
 
 /*
+ * Huffman-shaped wavelet tree (compressed wavelet trees are future work in
+ * Section 5; the paper gives no definition, so this is the standard one): the
+ * tree's shape is the code tree of a Huffman code for the symbol counts of S.
+ * A symbol that occurs is a leaf at the depth of its code length, reached by
+ * its code bits (0 = left); every internal node lists, for the symbols of its
+ * subtree in input order, their next code bit.  Depth d's bitmap is the
+ * concatenation, left to right, of the bitmaps of the internal nodes at depth
+ * d: n_d bits, n_d = the number of symbols whose code is longer than d.  The
+ * code is fixed as follows: lengths by Huffman's merging with two
+ * first-in first-out queues (the symbols that occur, by count then symbol;
+ * the merged items in the order they are made), the lighter front first and
+ * the symbol queue on equal weights; canonical codes from the lengths
+ * (symbols by length then symbol, each code the previous plus one, shifted
+ * left by the increase in length).  A single distinct symbol (or n = 0)
+ * gives a tree with no levels.  Codes longer than 24 bits are not supported
+ * (WT_EINVAL).
+ *
+ * wt_histogram writes the sigma symbol counts of d_S (u64, device memory of
+ * 8 * sigma bytes, 8-byte aligned) on `stream`; symbols >= sigma are not
+ * counted.  The caller copies them to the host and passes them to
+ * wt_huffman_footprint (tree and workspace bytes) and wt_build_huffman; the
+ * counts must add up to n (else WT_EINVAL) and be those of S (a symbol that
+ * occurs with a zero count, or >= sigma, is reported as WT_ERANGE by
+ * wt_tree_status).  The build enqueues a copy of its code tables (host memory
+ * owned by the handle: release the handle only after the stream has passed
+ * the build) and the kernels on `stream`.
+ *
+ * Layout of the tree memory: the 256-byte header (status word first), a
+ * 1280-byte table (sizes and byte offsets of every depth, canonical code
+ * bounds), a u32 per symbol (bits 0-4 its code length, bit 7 set if it
+ * occurs, bits 8-31 its code), the symbols in code order, then the depth
+ * bitmaps (depth d: round_up(ceil(n_d/64), 8) words, position p in word p/64
+ * at bit p%64, bits past n_d zero) and their directories (round_up(K_d, 8)
+ * entries, K_d = ceil(n_d/512) + 1, entry k = ones in [0, min(512k, n_d))).
+ * wt_huffman_levels gives, per depth, n_d and the byte offsets of its bitmap
+ * and directory in the tree memory, K_d, and (optionally, sigma entries) the
+ * code table.  The access / rank / select entry points accept the handle
+ * (walks over the depths; a leaf is recognised by its canonical code).
+ */
+int wt_histogram(const void *d_S, const wt_desc *desc, uint64_t *d_counts, void *stream);
+int wt_huffman_footprint(const uint64_t *counts, const wt_desc *desc, uint64_t *tree_bytes, uint64_t *work_bytes);
+int wt_build_huffman(const void *d_S, const wt_desc *desc, const uint64_t *counts, void *d_tree,
+                     uint64_t tree_bytes, void *d_work, uint64_t work_bytes, void *stream, wt_tree **out);
+int wt_huffman_levels(const wt_tree *tree, uint32_t *levels, uint64_t *sizes, uint64_t *bits_off,
+                      uint64_t *dir_off, uint64_t *dir_entries, uint32_t *code_table);
+
+/*
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): wt_build
  * with the workspace taken from a fixed device array inside the library

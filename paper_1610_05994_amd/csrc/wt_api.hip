@@ -20,6 +20,10 @@ struct wt_tree {
     hipStream_t stream;    // stream the build was enqueued on
     int device;
     uint64_t *d_query;     // lazily allocated scratch for the single queries
+    // Huffman-shaped tree: its table (host copy) and the host buffer of the
+    // tables copied into the tree memory by the build (kept until wt_free)
+    wt::HuffMeta *hm;
+    uint8_t *htab;
 };
 
 namespace wt {
@@ -312,6 +316,7 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         pa.slots = L.matrix ? kSlotSpan : level_slots(i);
         pa.n = L.n;
         pa.matrix = L.matrix;
+        pa.shift = 0;
         const bool big = pa.nodes > kScanChunk;  // one counter slot there
         if (big) {
             pr = prof_begin(st, "plan", i, L.width, L.n, pa.nodes * (8 + 16 + 8 + 16));
@@ -363,6 +368,7 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         a.matrix = L.matrix;
         a.zeros = L.matrix ? reinterpret_cast<unsigned long long *>(tree + kZerosOff) : nullptr;
         a.bits_next = fold_here ? bits_last : nullptr;
+        a.n_out = L.n;
         a.fold_own = fold_here ? reinterpret_cast<uint64_t *>(work + L.ws_fold_own) : nullptr;
         a.fold_ovf = fold_here ? reinterpret_cast<uint64_t *>(work + L.ws_fold_ovf) : nullptr;
         a.fold_ovf_n = fold_here ? reinterpret_cast<unsigned int *>(work + L.ws_fold_cnt) : nullptr;
@@ -455,6 +461,14 @@ static TreeView view_of(const wt_tree *t) {
     v.dwords = t->L.dwords;
     v.levels4 = t->L.levels4;
     if (four) v.bits = v.ranks = nullptr;
+    v.huff = nullptr;
+    v.hbase = nullptr;
+    if (t->hm) {
+        v.bits = v.ranks = nullptr;
+        v.huff = reinterpret_cast<const HuffMeta *>(t->tree + kHeaderBytes);
+        v.hbase = t->tree;
+        v.levels = t->hm->levels;
+    }
     return v;
 }
 
@@ -467,6 +481,8 @@ static wt_tree *new_handle(const Layout &L, void *tree, hipStream_t st) {
     h->device = 0;
     (void)hipGetDevice(&h->device);
     h->d_query = nullptr;
+    h->hm = nullptr;
+    h->htab = nullptr;
     return h;
 }
 
@@ -719,6 +735,267 @@ static hipError_t enqueue_buffered(const uint8_t *S, const BufPlan &P, uint8_t *
     return err;
 }
 
+// ------------------------------------------------ Huffman-shaped tree ---
+// The code: Huffman's merging of the two lightest items with two FIFO queues
+// (the symbols that occur, by count then symbol; the merged items in the
+// order they are made), the lighter front first and the symbol queue on
+// equal weights; a symbol's length is the depth of its leaf.  Canonical
+// codes follow from the lengths.  One symbol alone (or n = 0) gives a tree
+// with no levels.
+struct HuffPlan {
+    HuffMeta m;
+    std::vector<uint32_t> code_tab;  // per symbol: length | kHuffPresent | code << 8
+    std::vector<uint32_t> syms;      // symbols by (length, symbol)
+    uint32_t inner_width;            // bytes per left-aligned code
+    Layout inner;                    // level split over the codes (2^L symbols)
+    uint64_t tree_bytes, ws_k, ws_work, work_bytes;
+};
+
+static int huff_lengths(const uint64_t *counts, uint32_t sigma, std::vector<uint8_t> &len, uint32_t &maxlen) {
+    len.assign(sigma, 0);
+    maxlen = 0;
+    std::vector<uint32_t> leaf;
+    for (uint32_t c = 0; c < sigma; c++)
+        if (counts[c]) leaf.push_back(c);
+    const size_t k = leaf.size();
+    if (k < 2) return WT_OK;
+    std::stable_sort(leaf.begin(), leaf.end(), [&](uint32_t x, uint32_t y) { return counts[x] < counts[y]; });
+    // items: leaves 0..k-1 (in queue order), merged items k..2k-2
+    std::vector<uint64_t> w(2 * k - 1), up(2 * k - 1);
+    for (size_t i = 0; i < k; i++) w[i] = counts[leaf[i]];
+    size_t lf = 0, mf = k, made = k;
+    for (; made < 2 * k - 1; made++) {
+        size_t pick[2];
+        for (int t = 0; t < 2; t++) {
+            const bool from_leaf = lf < k && (mf >= made || w[lf] <= w[mf]);
+            pick[t] = from_leaf ? lf++ : mf++;
+        }
+        w[made] = w[pick[0]] + w[pick[1]];
+        up[pick[0]] = up[pick[1]] = made;
+    }
+    std::vector<uint32_t> depth(2 * k - 1, 0);
+    for (size_t i = 2 * k - 2; i-- > 0;) depth[i] = depth[up[i]] + 1;  // parents come later
+    for (size_t i = 0; i < k; i++) {
+        len[leaf[i]] = (uint8_t)std::min<uint32_t>(depth[i], 255u);
+        maxlen = std::max(maxlen, depth[i]);
+    }
+    return WT_OK;
+}
+
+static int plan_huffman(const uint64_t *counts, const wt_desc *desc, HuffPlan *P) {
+    int rc = check_desc(desc);
+    if (rc != WT_OK) return rc;
+    if (!counts) return WT_EINVAL;
+    const uint32_t sigma = desc->sigma;
+    const uint64_t n = desc->n;
+    uint64_t total = 0;
+    uint32_t distinct = 0, only = 0;
+    for (uint32_t c = 0; c < sigma; c++) {
+        total += counts[c];
+        if (counts[c]) { distinct++; only = c; }
+    }
+    if (total != n) return WT_EINVAL;  // not the histogram of S
+    std::vector<uint8_t> len;
+    uint32_t L;
+    huff_lengths(counts, sigma, len, L);
+    if (L > kHuffMaxLevels) return WT_EINVAL;
+    HuffMeta &m = P->m;
+    memset(&m, 0, sizeof(m));
+    m.n = n;
+    m.sigma = sigma;
+    m.levels = L;
+    m.distinct = distinct;
+    m.only = (L == 0 && n > 0) ? only : 0xFFFFFFFFu;
+    // canonical codes: by (length, symbol); counts and first codes per length
+    P->code_tab.assign(sigma, 0);
+    P->syms.clear();
+    for (uint32_t c = 0; c < sigma; c++)
+        if (counts[c]) P->code_tab[c] = kHuffPresent;  // (length 0 when the tree has no levels)
+    uint64_t next = 0;  // first code of the current length
+    for (uint32_t l = 1; l <= L; l++) {
+        m.first[l] = (uint32_t)next;
+        m.start[l] = (uint32_t)P->syms.size();
+        uint32_t cnt = 0;
+        for (uint32_t c = 0; c < sigma; c++) {
+            if (len[c] != l) continue;
+            P->code_tab[c] = l | kHuffPresent | ((uint32_t)(next + cnt) << 8);
+            P->syms.push_back(c);
+            cnt++;
+        }
+        m.count[l] = cnt;
+        next = (next + cnt) << 1;
+    }
+    // depth sizes: symbols whose code is longer than d
+    for (uint32_t d = 0; d < L; d++) {
+        uint64_t sz = 0;
+        for (uint32_t c = 0; c < sigma; c++)
+            if (len[c] > d) sz += counts[c];
+        m.size[d] = sz;
+    }
+    // tree layout
+    uint64_t off = kHeaderBytes + kHuffMetaBytes;
+    m.code_off = off;
+    off += round_up((uint64_t)sigma * 4, 256);
+    m.syms_off = off;
+    off += round_up((uint64_t)(P->syms.size() ? P->syms.size() : 1) * 4, 256);
+    uint64_t max_words = 0, max_wg = 1;
+    for (uint32_t d = 0; d < L; d++) {
+        m.bits_off[d] = off;
+        const uint64_t words = round_up(ceil_div(m.size[d], 64), 8);
+        max_words = std::max(max_words, words);
+        off += words * 8;
+    }
+    for (uint32_t d = 0; d < L; d++) {
+        m.dir_off[d] = off;
+        m.dir_entries[d] = ceil_div(m.size[d], 512) + 1;
+        max_wg = std::max(max_wg, ceil_div(m.dir_entries[d] - 1, kBitDirBlocks));
+        off += round_up(m.dir_entries[d], 8) * 8;
+    }
+    P->tree_bytes = off;
+    // workspace: the codes (T_0 of the level split) and the split's own
+    // workspace, tiled (the one-workgroup build lists every level in full)
+    P->inner_width = L <= 8 ? 1u : (L <= 16 ? 2u : 4u);
+    memset(&P->inner, 0, sizeof(P->inner));
+    uint64_t w = 0;
+    P->ws_k = w;
+    if (L > 0) {
+        uint32_t g = tuned_geometry(n, 1u << L, P->inner_width, false);
+        if (g == kGeomSmall || g == kGeomMid) g = 32;
+        make_layout_geom(n, 1u << L, P->inner_width, g, &P->inner);
+        w += round_up(n * P->inner_width, 256);
+        P->ws_work = w;
+        w += round_up(P->inner.work_bytes, 256);
+    }
+    P->work_bytes = w ? w : 256;
+    (void)max_words;
+    (void)max_wg;
+    return WT_OK;
+}
+
+static hipError_t enqueue_huffman(const void *S, const wt_desc *desc, const HuffPlan &P, const uint8_t *htab,
+                                  uint64_t htab_bytes, uint8_t *tree, uint8_t *work, hipStream_t st) {
+    const HuffMeta &m = P.m;
+    const uint32_t L = m.levels;
+    const Layout &I = P.inner;
+    uint32_t *status = reinterpret_cast<uint32_t *>(tree);
+    // status word (and, with levels, the split's counters) cleared, tables in
+    long pr = prof_begin(st, "zero", 0, desc->width, m.n, L ? I.ws_ctrl_bytes : 0);
+    hipError_t err = L ? launch_zero(work + P.ws_work + I.ws_ctrl, I.ws_ctrl_bytes, status, nullptr, 0, st)
+                       : launch_zero(tree, 0, status, nullptr, 0, st);
+    prof_end(pr, st);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(tree + kHeaderBytes, htab, htab_bytes, hipMemcpyHostToDevice, st);
+    if (err != hipSuccess) return err;
+    const uint32_t *code_tab = reinterpret_cast<const uint32_t *>(tree + m.code_off);
+    uint8_t *K = L ? work + P.ws_k : nullptr;
+    pr = prof_begin(st, "huff_map", 0, desc->width, m.n, m.n * (desc->width + (L ? P.inner_width : 0)));
+    err = launch_huff_map(S, m.n, desc->width, code_tab, m.sigma, L, K, P.inner_width, status, st);
+    prof_end(pr, st);
+    if (err != hipSuccess || L == 0) return err;
+    // The level split over the left-aligned codes, compacted: level d lists
+    // only the n_d symbols still inside the tree (its positions are depth d's
+    // bitmap positions).  The node tables of level d + 1 are shifted down by
+    // the number of symbols whose code ends at depth d + 1 (they come first
+    // in that level's order), so that the split drops them and places the
+    // others directly in the next depth's order.
+    const uint64_t TILE = tile_syms(I.width, I.lane_bytes);
+    uint32_t *tile_ones = reinterpret_cast<uint32_t *>(work + P.ws_work + I.ws_tile_ones);
+    unsigned long long *supsum = reinterpret_cast<unsigned long long *>(work + P.ws_work + I.ws_supsum);
+    unsigned long long *ones = reinterpret_cast<unsigned long long *>(work + P.ws_work + I.ws_ones);
+    unsigned long long *sup = reinterpret_cast<unsigned long long *>(work + P.ws_work + I.ws_sup);
+    ulonglong2 *zo = reinterpret_cast<ulonglong2 *>(work + P.ws_work + I.ws_zo);
+    uint64_t *start = reinterpret_cast<uint64_t *>(work + P.ws_work + I.ws_start);
+    uint64_t *partials = reinterpret_cast<uint64_t *>(work + P.ws_work + I.ws_partials);
+    uint8_t *tbuf[2] = {work + P.ws_work + I.ws_ta, work + P.ws_work + I.ws_tb};
+    IngestArgs ia;
+    ia.S = K;
+    ia.tile_ones0 = tile_ones;
+    ia.ones0 = ones;
+    ia.start0 = start;
+    ia.tree_status = status;
+    ia.n = m.n;
+    ia.ntiles = I.ntiles;
+    ia.slots0 = level_slots(0);
+    ia.sigma = 1u << L;
+    ia.check = 0;
+    ia.msb = L - 1;
+    ia.zero_p = nullptr;
+    ia.zero_words = 0;
+    {
+        uint64_t k = kWaves;
+        while (I.ntiles > 8192 * k) k <<= 1;
+        ia.tiles_per_block = k;
+    }
+    pr = prof_begin(st, "ingest", 0, I.width, m.n, m.n * I.width);
+    err = launch_ingest(ia, I.width, I.lane_bytes, st);
+    prof_end(pr, st);
+    if (err != hipSuccess) return err;
+    const uint64_t stride = tile_stride(I.ntiles);
+    for (uint32_t d = 0; d < L; d++) {
+        const uint64_t nd = m.size[d];
+        const uint64_t nnext = (d + 1 < L) ? m.size[d + 1] : 0;
+        const uint64_t ntiles = ceil_div(nd, TILE), nsup = ceil_div(ntiles, kSup);
+        PlanArgs pa;
+        pa.start = start + start_offset(d);
+        pa.ones = ones + ones_offset(d);
+        pa.zo = zo + zo_offset(d);
+        pa.start_next = (d + 1 < L) ? start + start_offset(d + 1) : nullptr;
+        pa.partials = partials;
+        pa.nodes = 1ull << d;
+        pa.slots = level_slots(d);
+        pa.n = nd;
+        pa.matrix = 0;
+        pa.shift = (d + 1 < L) ? nd - nnext : 0;  // the symbols whose code ends at depth d + 1
+        const bool big = pa.nodes > kScanChunk;
+        if (big) {
+            err = launch_plan(pa, st);
+            if (err != hipSuccess) return err;
+        }
+        PrepArgs pp;
+        pp.tile_ones = tile_ones + (uint64_t)d * stride;
+        pp.supsum = supsum;
+        pp.sup = sup + (uint64_t)d * I.nsup;
+        pp.ntiles = ntiles;
+        pp.nsup = nsup;
+        pp.plan = pa;
+        pp.plan_here = big ? 0u : 1u;
+        pp.sums_here = (nsup <= kPrepSups && !big && pa.nodes < kThreads) ? 1u : 0u;
+        pr = prof_begin(st, "prep", d, I.width, nd, ntiles * 4 + nsup * 16);
+        err = launch_prep(pp, st);
+        prof_end(pr, st);
+        if (err != hipSuccess) return err;
+        LevelArgs a;
+        memset(&a, 0, sizeof(a));
+        a.tin = (d == 0) ? (const void *)K : tbuf[(d - 1) & 1];
+        a.tout = (d + 1 < L) ? tbuf[d & 1] : nullptr;
+        a.bits = reinterpret_cast<uint64_t *>(tree + m.bits_off[d]);
+        a.ranks = reinterpret_cast<uint64_t *>(tree + m.dir_off[d]);
+        a.zo = zo + zo_offset(d);
+        a.tile_ones = tile_ones + (uint64_t)d * stride;
+        a.sup = sup + (uint64_t)d * I.nsup;
+        a.tile_ones_next = (d + 1 < L) ? tile_ones + (uint64_t)(d + 1) * stride : nullptr;
+        a.ones_next = (d + 1 < L) ? ones + ones_offset(d + 1) : nullptr;
+        a.nodes_next = 2ull << d;
+        a.slots_next = level_slots(d + 1);
+        a.n = nd;
+        a.n_out = nnext;
+        a.words = round_up(ceil_div(nd, 64), 8);
+        a.rank_entries = m.dir_entries[d];
+        a.rank_stride = round_up(m.dir_entries[d], 8);
+        a.ntiles = ntiles;
+        a.levels = L;
+        a.level = d;
+        a.symmask = (uint32_t)((1ull << L) - 1);
+        const uint64_t lbytes = nd * I.width + nnext * I.width + a.words * 8 + a.rank_stride * 8;
+        pr = prof_begin(st, "level", d, I.width, nd, lbytes);
+        // (the plain variant: every destination comes from the node tables)
+        err = launch_level(a, I.width, I.lane_bytes, false, st);
+        prof_end(pr, st);
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
 // ------------------------------------------------ no-allocation build ---
 // Workspace of wt_build_noalloc: a file-scope device array, one copy on
 // every device the library runs on, held until the process ends.  In host
@@ -749,6 +1026,84 @@ static int scratch_on_current_device(uint8_t **p) {
 using namespace wt;
 
 extern "C" {
+
+int wt_histogram(const void *d_S, const wt_desc *desc, uint64_t *d_counts, void *stream) {
+    int rc = check_desc(desc);
+    if (rc != WT_OK) return rc;
+    if (!d_counts || (desc->n > 0 && !d_S) || ((uintptr_t)d_counts & 7)) return WT_EINVAL;
+    return launch_histogram(d_S, desc->n, desc->width, desc->sigma, reinterpret_cast<unsigned long long *>(d_counts),
+                            reinterpret_cast<hipStream_t>(stream)) == hipSuccess
+               ? WT_OK
+               : WT_EDEVICE;
+}
+
+int wt_huffman_footprint(const uint64_t *counts, const wt_desc *desc, uint64_t *tree_bytes, uint64_t *work_bytes) {
+    HuffPlan P;
+    int rc = plan_huffman(counts, desc, &P);
+    if (rc != WT_OK) return rc;
+    if (tree_bytes) *tree_bytes = P.tree_bytes;
+    if (work_bytes) *work_bytes = P.work_bytes;
+    return WT_OK;
+}
+
+int wt_build_huffman(const void *d_S, const wt_desc *desc, const uint64_t *counts, void *d_tree, uint64_t tree_bytes,
+                     void *d_work, uint64_t work_bytes, void *stream, wt_tree **out) {
+    if (out) *out = nullptr;
+    if (!out) return WT_EINVAL;
+    HuffPlan P;
+    int rc = plan_huffman(counts, desc, &P);
+    if (rc != WT_OK) return rc;
+    if (!d_tree || !d_work || (desc->n > 0 && !d_S)) return WT_EINVAL;
+    if (((uintptr_t)d_S & 15) || ((uintptr_t)d_tree & 255) || ((uintptr_t)d_work & 255)) return WT_EINVAL;
+    if (tree_bytes < P.tree_bytes || work_bytes < P.work_bytes) return WT_ENOMEM;
+    // the tables as they sit in the tree memory from kHeaderBytes on
+    const uint64_t tab_bytes = P.m.syms_off + P.syms.size() * 4 - kHeaderBytes;
+    uint8_t *htab = new (std::nothrow) uint8_t[tab_bytes];
+    HuffMeta *hm = new (std::nothrow) HuffMeta(P.m);
+    Layout hl;
+    memset(&hl, 0, sizeof(hl));
+    hl.n = desc->n;
+    hl.sigma = desc->sigma;
+    hl.width = desc->width;
+    hl.levels = P.m.levels;
+    hl.tree_bytes = P.tree_bytes;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    wt_tree *h = (htab && hm) ? new_handle(hl, d_tree, st) : nullptr;
+    if (!h) {
+        delete[] htab;
+        delete hm;
+        return WT_ENOMEM;
+    }
+    memset(htab, 0, tab_bytes);
+    memcpy(htab, &P.m, sizeof(HuffMeta));
+    memcpy(htab + (P.m.code_off - kHeaderBytes), P.code_tab.data(), P.code_tab.size() * 4);
+    if (!P.syms.empty()) memcpy(htab + (P.m.syms_off - kHeaderBytes), P.syms.data(), P.syms.size() * 4);
+    h->hm = hm;
+    h->htab = htab;
+    if (enqueue_huffman(d_S, desc, P, htab, tab_bytes, reinterpret_cast<uint8_t *>(d_tree),
+                        reinterpret_cast<uint8_t *>(d_work), st) != hipSuccess) {
+        wt_free(h);
+        return WT_EDEVICE;
+    }
+    *out = h;
+    return WT_OK;
+}
+
+int wt_huffman_levels(const wt_tree *t, uint32_t *levels, uint64_t *sizes, uint64_t *bits_off, uint64_t *dir_off,
+                      uint64_t *dir_entries, uint32_t *code_table) {
+    if (!t || !t->hm) return WT_EINVAL;
+    const HuffMeta &m = *t->hm;
+    if (levels) *levels = m.levels;
+    for (uint32_t d = 0; d < m.levels; d++) {
+        if (sizes) sizes[d] = m.size[d];
+        if (bits_off) bits_off[d] = m.bits_off[d];
+        if (dir_off) dir_off[d] = m.dir_off[d];
+        if (dir_entries) dir_entries[d] = m.dir_entries[d];
+    }
+    if (code_table)
+        memcpy(code_table, t->htab + (m.code_off - kHeaderBytes), (uint64_t)m.sigma * 4);
+    return WT_OK;
+}
 
 int wt_build_noalloc(const void *d_S, const wt_desc *desc, void *d_tree, uint64_t tree_bytes, void *stream) {
     int rc = check_desc(desc);
@@ -1042,12 +1397,16 @@ int wt_tree_status(const wt_tree *t) {
 void wt_free(wt_tree *t) {
     if (!t) return;
     if (t->d_query) (void)hipFree(t->d_query);
+    delete t->hm;
+    delete[] t->htab;
     delete t;
 }
 
 int wt_levels(const wt_tree *t, uint32_t *levels, const uint64_t **d_bitmaps, uint64_t *words_per_level,
               const uint64_t **d_ranks, uint64_t *rank_stride, uint64_t *rank_entries) {
-    if (!t || t->L.arity == 4) return WT_EINVAL;  // a 4-ary tree has digit levels (wt_multiary_levels)
+    // a 4-ary tree has digit levels (wt_multiary_levels), a Huffman-shaped
+    // tree levels of different sizes (wt_huffman_levels)
+    if (!t || t->L.arity == 4 || t->hm) return WT_EINVAL;
     if (levels) *levels = t->L.levels;
     if (d_bitmaps) *d_bitmaps = reinterpret_cast<const uint64_t *>(t->tree + t->L.tree_bits_off);
     if (words_per_level) *words_per_level = t->L.words;

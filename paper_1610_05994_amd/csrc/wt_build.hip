@@ -474,17 +474,17 @@ __device__ __forceinline__ unsigned long long plan_chunk_with(const PlanArgs &a,
         if (v < a.nodes) {
             const unsigned long long ones = loc[q];
             const uint64_t s_next = cs.next[q];
-            a.zo[v] = make_ulonglong2(o1, s_next - ones - o1);
+            a.zo[v] = make_ulonglong2(o1 - a.shift, s_next - ones - o1 - a.shift);
             if (a.start_next && !a.matrix) {
-                a.start_next[2 * v] = (q == 0) ? cs.first : cs.next[q - 1];
-                a.start_next[2 * v + 1] = s_next - ones;
+                a.start_next[2 * v] = ((q == 0) ? cs.first : cs.next[q - 1]) - a.shift;
+                a.start_next[2 * v + 1] = s_next - ones - a.shift;
             }
             o1 += ones;
         }
     }
     if (a.start_next && b0 == 0 && threadIdx.x == 0) {
         if (a.matrix) a.start_next[0] = 0;
-        a.start_next[a.matrix ? 1 : 2 * a.nodes] = a.n;
+        a.start_next[a.matrix ? 1 : 2 * a.nodes] = a.n - a.shift;
     }
     return tot;
 }
@@ -870,7 +870,7 @@ __device__ __forceinline__ void stage_multi(const LevelArgs &a, const uint4 (&ra
         const unsigned long long g = tb->g[lo];
         const uint32_t s = blk * CH;
         if (s + CH > kStage) continue;  // (only with inconsistent tables)
-        if (!(s >= st && s + CH <= st + len && g + (s - st) + CH <= a.n)) continue;  // partial: below
+        if (!(s >= st && s + CH <= st + len && g + (s - st) + CH <= a.n_out)) continue;  // partial: below
         const uint4 v = *reinterpret_cast<const uint4 *>(&s_stage[s]);
         const unsigned long long gfirst = g + (s - st);
         *reinterpret_cast<uint4 *>(tout + gfirst) = v;
@@ -885,13 +885,13 @@ __device__ __forceinline__ void stage_multi(const LevelArgs &a, const uint4 (&ra
             const uint32_t blk = (lane & 1) ? bend - 1 : bfirst;
             const uint32_t s = blk * CH;
             const bool take = len > 0 && bend > bfirst && !((lane & 1) && bend - 1 == bfirst) && s + CH <= kStage;
-            if (take && !(s >= st && s + CH <= st + len && g + (s - st) + CH <= a.n)) {
+            if (take && !(s >= st && s + CH <= st + len && g + (s - st) + CH <= a.n_out)) {
                 const uint4 v = *reinterpret_cast<const uint4 *>(&s_stage[s]);
                 uint32_t ones = 0;
 #pragma unroll
                 for (int e = 0; e < (int)CH; e++) {
                     const uint32_t q = s + e;
-                    if (q >= st && q < st + len && g + (q - st) < a.n) {
+                    if (q >= st && q < st + len && g + (q - st) < a.n_out) {
                         const uint32_t x = chunk_elem<W>(v, e);
                         tout[g + (q - st)] = (T)x;
                         ones += (x >> sh2) & 1u;
@@ -1059,7 +1059,7 @@ __device__ __forceinline__ void split_dense(const LevelArgs &a, const uint4 (&ra
                 const ulonglong2 zo = (v == vf) ? zf : zl;
                 const unsigned long long R = prefix + r;
                 const uint64_t dst = b ? zo.y + R : base + p - R + zo.x;
-                if (dst < a.n) {
+                if (dst < a.n_out) {
                     tout[dst] = (T)x;
                     const uint32_t key = ((v == vf) ? 0u : 4u) + 2 * b + (uint32_t)((dst / TILE) & 1);
                     if (key < 4) ecl += (unsigned long long)nb << (16 * key);
@@ -1078,7 +1078,7 @@ __device__ __forceinline__ void split_dense(const LevelArgs &a, const uint4 (&ra
         const uint32_t ca = (ia_u + CH - 1) / CH, cb = ib_u / CH;  // whole chunks [ca, cb)
         for (uint32_t c = ca + lane; c < cb; c += 64) {
             const uint32_t s0 = c * CH;
-            if (base + s0 + CH <= a.n)
+            if (base + s0 + CH <= a.n_out)
                 *reinterpret_cast<uint4 *>(tout + (base + s0)) = *reinterpret_cast<const uint4 *>(&s_stage[s0]);
         }
         if (ia_u < ib_u) {
@@ -1087,7 +1087,7 @@ __device__ __forceinline__ void split_dense(const LevelArgs &a, const uint4 (&ra
             const uint32_t tb0 = (cb * CH > ca * CH) ? cb * CH : ((ca * CH < ib_u) ? ca * CH : ib_u);
             const uint32_t q = (lane < 32) ? ia_u + (uint32_t)lane : tb0 + (uint32_t)(lane - 32);
             const uint32_t qe = (lane < 32) ? he : ib_u;
-            if (q < qe && base + q < a.n) tout[base + q] = s_stage[q];
+            if (q < qe && base + q < a.n_out) tout[base + q] = s_stage[q];
         }
     }
     if (!counting) return;
@@ -1280,8 +1280,10 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
 #pragma unroll
         for (int r = 0; r < 2; r++) {
             const uint32_t lo = r ? a1 : a0;
-            const uint32_t len = (uint32_t)(r ? O : Z);
             const uint64_t gb = (r ? g1 : g0) - lo;  // destination = gb + slot
+            // a run whose destinations lie below 0 is dropped whole (a
+            // child that the next level does not list; runs never straddle 0)
+            const uint32_t len = ((int64_t)(gb + lo) < 0) ? 0u : (uint32_t)(r ? O : Z);
             const uint32_t cb = lo / CH, ce = len ? (lo + len + CH - 1) / CH : cb;
             const uint32_t fb = (lo + CH - 1) / CH, fe = (lo + len) / CH;  // chunks inside the run
             const uint64_t dt0 = (gb + (uint64_t)cb * CH) / TILE;
@@ -1299,11 +1301,11 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
             // (destinations beyond n only arise from inconsistent tables;
             // they are dropped rather than written; checked per chunk only
             // when the run's last whole chunk would pass n)
-            const bool inside = gb + (uint64_t)fe * CH <= a.n;
+            const bool inside = gb + (uint64_t)fe * CH <= a.n_out;
             for (uint32_t c = fb + lane; c < fe; c += 64) {  // whole chunks [fb, fe)
                 const uint32_t s = c * CH;
                 const uint4 v = *reinterpret_cast<const uint4 *>(&s_stage[s]);
-                if (inside || gb + s + CH <= a.n) {
+                if (inside || gb + s + CH <= a.n_out) {
                     if (fold)  // the granule's 16 bits (gb + s is a multiple of 16)
                         bnext[(gb + s) >> 4] = (uint16_t)chunk_bits16(v, sh2);
                     else
@@ -1330,7 +1332,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
             if (e < CH && c != 0xffffffffu) {
                 const uint32_t s = c * CH + (uint32_t)e;
                 const uint64_t d = gb + s;
-                if (s >= lo && s < lo + len && d < a.n) {
+                if (s >= lo && s < lo + len && d < a.n_out) {
                     const uint32_t x = (uint32_t)s_stage[s];
                     tout[d] = (T)x;  // (folded: read back by the stitch)
                     one = (x >> sh2) & 1u;
@@ -1413,7 +1415,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
             const uint32_t b = (uint32_t)(mb >> k) & 1u;
             const uint64_t dst = b ? zo.y + r1 : p - r1 + zo.x;
             r1 += b;
-            if (dst < a.n) {
+            if (dst < a.n_out) {
                 tout[dst] = (T)x;
                 nown += (fold && (dst & 15) == 0) ? 1u : 0u;
                 if (counting && ((x >> sh2) & 1u)) {
@@ -1453,7 +1455,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
                 const uint32_t b = (uint32_t)(mb >> k) & 1u;
                 const uint64_t dst = b ? zo.y + r1 : pos0 + k - r1 + zo.x;
                 r1 += b;
-                if (dst < a.n && (dst & 15) == 0) {
+                if (dst < a.n_out && (dst & 15) == 0) {
                     if (at < a.fold_ovf_cap) a.fold_ovf[at] = dst >> 4;
                     at++;
                     nown--;
@@ -1517,10 +1519,11 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
     __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W, B, M, kCopy>()];
     __shared__ SplitRec s_rec[kWaves];
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint64_t t = (uint64_t)blockIdx.x * kWaves + wv;
+    const uint64_t t0 = (uint64_t)blockIdx.x * kWaves;
+    const uint64_t t = t0 + wv;
     if ((threadIdx.x & 63) < 4) s_rec[wv].cnt[threadIdx.x & 63] = 0;
     if (t < a.ntiles) level_tile<W, B, M, kCopy>(a, t, s_all + wv * level_wave_bytes<W, B, M, kCopy>(), &s_rec[wv]);
-    flush_split_recs(a, s_rec, (uint64_t)blockIdx.x * kWaves);
+    flush_split_recs(a, s_rec, t0);
 }
 
 // ------------------------------------------------------------ batched ---
@@ -1558,6 +1561,7 @@ __device__ __forceinline__ LevelArgs job_level(const BatchJob &j, uint32_t i) {
     a.dwords = 0;
     a.dsh = 0;
     a.bits_next = nullptr;
+    a.n_out = j.n;
     a.fold_own = a.fold_ovf = nullptr;
     a.fold_ovf_n = nullptr;
     a.fold_ovf_cap = 0;
@@ -1583,6 +1587,7 @@ __device__ __forceinline__ PrepArgs job_prep(const BatchJob &j, uint32_t i) {
     p.plan.slots = level_slots(i);
     p.plan.n = j.n;
     p.plan.matrix = 0;
+    p.plan.shift = 0;
     p.plan_here = (p.plan.nodes > kScanChunk) ? 0u : 1u;  // larger levels: the k_batch_plan_* kernels
     p.sums_here = 0;                                       // (k_batch_supsum runs for every level)
     return p;

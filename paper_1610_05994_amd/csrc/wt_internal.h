@@ -129,6 +129,10 @@ struct LevelArgs {
     unsigned long long *ones_next;    // next-level ones per node, slot-spread (accumulated)
     uint64_t nodes_next, slots_next;
     uint64_t n, words, rank_entries, rank_stride, ntiles;
+    // positions of the next order (T_{i+1}): n, or fewer when the node
+    // tables map the symbols of some children below 0 (those children are
+    // dropped: a Huffman-shaped tree's leaves)
+    uint64_t n_out;
     uint32_t levels, level, symmask;
     // wavelet matrix: one node per level; zeros[level] receives z_i
     uint32_t matrix;
@@ -213,6 +217,10 @@ struct PlanArgs {
     uint64_t *partials;
     uint64_t nodes, slots, n;
     uint32_t matrix;                   // wavelet matrix: the next level is again one node [0, n)
+    // subtracted from every next-level position (zo and start_next): the
+    // next level then lists only the children at or after that position
+    // (Huffman-shaped tree: its leaves at the next depth come first); 0 else
+    uint64_t shift;
 };
 
 struct PrepArgs {
@@ -312,6 +320,40 @@ struct DigitDirArgs {
 constexpr uint64_t kDirBlocksPerWG = 256;  // 512-position blocks per directory workgroup
 hipError_t launch_digit_dir(const DigitDirArgs &a, hipStream_t s);
 
+// Huffman-shaped tree (wt_huffman.hip, wt_api.hip, wt_query.hip).  Its
+// tree memory starts with the 256-byte header (status word first), then this
+// table at kHeaderBytes, then the per-symbol code table, the symbols in code
+// order, the depth bitmaps and their directories.  Depth d holds size[d] =
+// n_d positions (the symbols whose code is longer than d); in the order of
+// the first d bits of the left-aligned codes over all of S, those positions
+// come after the n - n_d symbols whose code ends by depth d.
+constexpr uint32_t kHuffMaxLevels = 24;
+constexpr uint64_t kHuffMetaBytes = 1280;
+struct HuffMeta {
+    uint64_t n;
+    uint32_t sigma, levels, distinct, only;     // only: the one symbol of S when levels = 0 and n > 0
+    uint64_t size[kHuffMaxLevels];              // n_d
+    uint64_t bits_off[kHuffMaxLevels];          // byte offsets from the tree base
+    uint64_t dir_off[kHuffMaxLevels];
+    uint64_t dir_entries[kHuffMaxLevels];       // ceil(n_d / 512) + 1
+    uint32_t first[kHuffMaxLevels + 1];         // canonical: first code of each length (right-aligned)
+    uint32_t count[kHuffMaxLevels + 1];         // codes of each length
+    uint32_t start[kHuffMaxLevels + 1];         // their first index in the code-ordered symbol list
+    uint64_t code_off, syms_off;                // byte offsets of the two tables
+};
+static_assert(sizeof(HuffMeta) <= kHuffMetaBytes, "Huffman table size");
+// code table entry of a symbol: bits 0-4 its code length, bit 7 set when the
+// symbol occurs, bits 8-31 its code (right-aligned)
+constexpr uint32_t kHuffPresent = 0x80u;
+
+hipError_t launch_histogram(const void *S, uint64_t n, uint32_t width, uint32_t sigma, unsigned long long *counts,
+                            hipStream_t s);
+// K[j] = code of S[j] left-aligned to `levels` bits, stored at width wout;
+// status bit 0 for a symbol >= sigma or absent from the code table
+hipError_t launch_huff_map(const void *S, uint64_t n, uint32_t width, const uint32_t *code_tab, uint32_t sigma,
+                           uint32_t levels, void *K, uint32_t wout, uint32_t *status, hipStream_t s);
+
+
 // query launchers (wt_query.hip)
 struct TreeView {
     const uint64_t *bits;
@@ -325,6 +367,9 @@ struct TreeView {
     const uint64_t *dir;
     uint64_t dwords;
     uint32_t levels4;
+    // Huffman-shaped tree (non-null): its table and tree base (device)
+    const HuffMeta *huff;
+    const uint8_t *hbase;
 };
 hipError_t launch_access(const TreeView &t, const uint64_t *i, uint32_t *sym, uint64_t m,
                          hipStream_t s);

@@ -260,9 +260,99 @@ __device__ uint64_t select4(const TreeView &t, uint32_t c, uint64_t j) {
     return idx;
 }
 
+// Huffman-shaped tree: depth d holds the n_d symbols whose code is longer
+// than d.  The walk keeps the plain coordinates of the level split over the
+// left-aligned codes (a node's children occupy its range at the next
+// depth, zeros first), where depth d starts at m_d = n - n_d: position P of
+// an internal node is position P - m_d of depth d's bitmap.  A child whose
+// first d + 1 code bits form a code of that length is a leaf (canonical
+// codes of length l are first[l] .. first[l] + count[l] - 1).
+__device__ __forceinline__ Level hlevel(const TreeView &t, uint32_t d) {
+    return Level{reinterpret_cast<const uint64_t *>(t.hbase + t.huff->bits_off[d]),
+                 reinterpret_cast<const uint64_t *>(t.hbase + t.huff->dir_off[d])};
+}
+
+__device__ uint32_t huff_access(const TreeView &t, uint64_t i) {
+    const HuffMeta &m = *t.huff;
+    if (m.levels == 0) return m.only;
+    const uint32_t *syms = reinterpret_cast<const uint32_t *>(t.hbase + m.syms_off);
+    uint64_t b = 0, e = m.n, p = i;
+    uint32_t pre = 0;
+    for (uint32_t d = 0; d < m.levels; d++) {
+        const Level L = hlevel(t, d);
+        const uint64_t md = m.n - m.size[d];
+        const uint64_t rb = rank1(L, b - md), re = rank1(L, e - md), rp = rank1(L, p - md);
+        const uint64_t zeros = (e - b) - (re - rb);
+        const uint64_t q = p - md;
+        const uint32_t bit = (uint32_t)((L.B[q >> 6] >> (q & 63)) & 1ull);
+        uint64_t before;
+        if (bit) { before = rp - rb; b = b + zeros; }
+        else     { before = (p - b) - (rp - rb); e = b + zeros; }
+        p = b + before;
+        pre = 2 * pre + bit;
+        const uint32_t len = d + 1;
+        if (pre - m.first[len] < m.count[len]) return syms[m.start[len] + (pre - m.first[len])];
+        if (p >= e) return 0xFFFFFFFEu;  // corrupted tree only
+    }
+    return 0xFFFFFFFEu;
+}
+
+__device__ uint64_t huff_rank(const TreeView &t, uint32_t c, uint64_t i) {
+    const HuffMeta &m = *t.huff;
+    if (m.levels == 0) return (c == m.only) ? i : 0;
+    const uint32_t ent = reinterpret_cast<const uint32_t *>(t.hbase + m.code_off)[c];
+    const uint32_t len = ent & 31u, code = ent >> 8;
+    if (len == 0) return 0;
+    uint64_t b = 0, e = m.n, p = i;
+    for (uint32_t d = 0; d < len; d++) {
+        const Level L = hlevel(t, d);
+        const uint64_t md = m.n - m.size[d];
+        const uint64_t rb = rank1(L, b - md), re = rank1(L, e - md), rp = rank1(L, p - md);
+        const uint64_t zeros = (e - b) - (re - rb);
+        if ((code >> (len - 1 - d)) & 1u) { p = b + zeros + (rp - rb); b = b + zeros; }
+        else                              { p = p - (rp - rb); e = b + zeros; }
+        if (p > e) return ~1ull;  // corrupted tree only
+    }
+    return p - b;
+}
+
+__device__ uint64_t huff_select(const TreeView &t, uint32_t c, uint64_t j) {
+    const HuffMeta &m = *t.huff;
+    if (m.levels == 0) return (c == m.only && j >= 1 && j <= m.n) ? j - 1 : ~0ull;
+    const uint32_t ent = reinterpret_cast<const uint32_t *>(t.hbase + m.code_off)[c];
+    const uint32_t len = ent & 31u, code = ent >> 8;
+    if (len == 0) return ~0ull;
+    uint64_t bs[kHuffMaxLevels + 1];
+    uint64_t b = 0, e = m.n;
+    for (uint32_t d = 0; d < len; d++) {  // node ranges of c, top-down
+        const Level L = hlevel(t, d);
+        const uint64_t md = m.n - m.size[d];
+        bs[d] = b;
+        const uint64_t rb = rank1(L, b - md), re = rank1(L, e - md);
+        const uint64_t zeros = (e - b) - (re - rb);
+        if ((code >> (len - 1 - d)) & 1u) b = b + zeros; else e = b + zeros;
+        if (b > e) return ~1ull;  // corrupted tree only
+    }
+    if (j == 0 || j > e - b) return ~0ull;
+    uint64_t idx = j - 1;  // index among the leaf's symbols
+    for (uint32_t d = len; d-- > 0;) {  // bottom-up back to S
+        const Level L = hlevel(t, d);
+        const uint64_t md = m.n - m.size[d], nd = m.size[d];
+        const uint64_t bb = bs[d];
+        const uint64_t rb = rank1(L, bb - md);
+        uint64_t q;
+        if ((code >> (len - 1 - d)) & 1u) q = select1(L, m.dir_entries[d], (nd + 63) / 64, rb + idx + 1);
+        else q = select0(L, m.dir_entries[d], nd, (bb - md - rb) + idx + 1);
+        if (q >= nd) return ~0ull;
+        idx = q + md - bb;
+    }
+    return idx;
+}
+
 // access(i): the symbol at position i (0xFFFFFFFF if i >= n).
 __device__ uint32_t access_one(const TreeView &t, uint64_t i) {
     if (i >= t.n) return 0xFFFFFFFFu;
+    if (t.huff) return huff_access(t, i);
     if (t.zeros) return matrix_access(t, i);
     if (t.digits) return access4(t, i);
     uint64_t b = 0, e = t.n, p = i;
@@ -285,6 +375,7 @@ __device__ uint32_t access_one(const TreeView &t, uint64_t i) {
 // rank(c, i): occurrences of c in S[0, i) (UINT64_MAX if c >= sigma or i > n).
 __device__ uint64_t rank_one(const TreeView &t, uint32_t c, uint64_t i) {
     if (c >= t.sigma || i > t.n) return ~0ull;
+    if (t.huff) return huff_rank(t, c, i);
     if (t.zeros) {
         uint64_t b, e;
         matrix_range(t, c, i, b, e);
@@ -307,6 +398,7 @@ __device__ uint64_t rank_one(const TreeView &t, uint32_t c, uint64_t i) {
 // select(c, j): 0-based position of the j-th (1-based) c (UINT64_MAX if none).
 __device__ uint64_t select_one(const TreeView &t, uint32_t c, uint64_t j) {
     if (c >= t.sigma) return ~0ull;
+    if (t.huff) return huff_select(t, c, j);
     if (t.zeros) return matrix_select(t, c, j);
     if (t.digits) return select4(t, c, j);
     uint64_t bs[32];

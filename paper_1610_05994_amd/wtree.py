@@ -28,7 +28,9 @@ EXPORTED = [
     "wt_tune_set", "wt_tune_get", "wt_buffered_footprint", "wt_build_buffered",
     "wt_multiary_footprint", "wt_build_multiary", "wt_multiary_levels",
     "wt_prof_enable", "wt_prof_read", "wt_build_noalloc",
+    "wt_histogram", "wt_huffman_footprint", "wt_build_huffman", "wt_huffman_levels",
 ]
+HUFF_MAX_LEVELS = 24
 WT_NOALLOC_WORK_BYTES = 64 << 20
 
 
@@ -65,6 +67,10 @@ def lib():
         "wt_build": ([vp, P(wt_desc), vp, u64, vp, u64, vp, P(vp)], i32),
         "wt_build_matrix": ([vp, P(wt_desc), vp, u64, vp, u64, vp, P(vp)], i32),
         "wt_build_noalloc": ([vp, P(wt_desc), vp, u64, vp], i32),
+        "wt_histogram": ([vp, P(wt_desc), vp, vp], i32),
+        "wt_huffman_footprint": ([vp, P(wt_desc), P(u64), P(u64)], i32),
+        "wt_build_huffman": ([vp, P(wt_desc), vp, vp, u64, vp, u64, vp, P(vp)], i32),
+        "wt_huffman_levels": ([vp, P(u32), vp, vp, vp, vp, vp], i32),
         "wt_matrix_zeros": ([vp, P(u64)], i32),
         "wt_buffered_footprint": ([P(wt_desc), u64, P(u64), P(u64)], i32),
         "wt_multiary_footprint": ([P(wt_desc), P(u64), P(u64)], i32),
@@ -139,6 +145,43 @@ def wt_build(d_S: int, n: int, sigma: int, width: int, d_tree: int, tree_bytes: 
 def wt_build_noalloc(d_S: int, n: int, sigma: int, width: int, d_tree: int, tree_bytes: int, stream: int) -> int:
     d = wt_desc(n, sigma, width)
     return lib().wt_build_noalloc(d_S, ctypes.byref(d), d_tree, tree_bytes, stream)
+
+
+def wt_histogram(d_S: int, n: int, sigma: int, width: int, d_counts: int, stream: int) -> int:
+    d = wt_desc(n, sigma, width)
+    return lib().wt_histogram(d_S, ctypes.byref(d), d_counts, stream)
+
+
+def wt_huffman_footprint(counts: np.ndarray, n: int, sigma: int, width: int):
+    counts = np.ascontiguousarray(counts, dtype=np.uint64)
+    d = wt_desc(n, sigma, width)
+    tb, wb = ctypes.c_uint64(), ctypes.c_uint64()
+    rc = lib().wt_huffman_footprint(counts.ctypes.data_as(ctypes.c_void_p), ctypes.byref(d), ctypes.byref(tb),
+                                    ctypes.byref(wb))
+    return rc, tb.value, wb.value
+
+
+def wt_build_huffman(d_S: int, n: int, sigma: int, width: int, counts: np.ndarray, d_tree: int, tree_bytes: int,
+                     d_work: int, work_bytes: int, stream: int):
+    counts = np.ascontiguousarray(counts, dtype=np.uint64)
+    d = wt_desc(n, sigma, width)
+    h = ctypes.c_void_p()
+    rc = lib().wt_build_huffman(d_S, ctypes.byref(d), counts.ctypes.data_as(ctypes.c_void_p), d_tree, tree_bytes,
+                                d_work, work_bytes, stream, ctypes.byref(h))
+    return rc, h.value
+
+
+def wt_huffman_levels(h: int, sigma: int):
+    lv = ctypes.c_uint32()
+    arrs = [np.zeros(HUFF_MAX_LEVELS, dtype=np.uint64) for _ in range(4)]
+    code = np.zeros(max(1, sigma), dtype=np.uint32)
+    vp = ctypes.c_void_p
+    rc = lib().wt_huffman_levels(h, ctypes.byref(lv), *[a.ctypes.data_as(vp) for a in arrs],
+                                 code.ctypes.data_as(vp))
+    L = lv.value
+    return rc, dict(levels=L, sizes=[int(x) for x in arrs[0][:L]], bits_off=[int(x) for x in arrs[1][:L]],
+                    dir_off=[int(x) for x in arrs[2][:L]], dir_entries=[int(x) for x in arrs[3][:L]],
+                    code_table=code[:sigma])
 
 
 def wt_build_matrix(d_S: int, n: int, sigma: int, width: int, d_tree: int, tree_bytes: int, d_work: int,
@@ -515,3 +558,88 @@ def build_batch(Ss, sigmas, widths=None, stream=None):
     if rc != WT_OK:
         raise WtError(rc, "wt_build_batch")
     return [Tree(h, tm, work, S, d[0], d[1], d[2], st) for h, tm, S, d in zip(hs, trees_mem, Ss, descs)]
+
+
+class HuffTree(Tree):
+    """A Huffman-shaped tree: depth d holds n_d positions (its own size)."""
+
+    def __init__(self, handle: int, tree_mem, work_mem, S, n: int, sigma: int, width: int, stream):
+        self.handle = handle
+        self.matrix = False
+        self.arity = 2
+        self.tree_mem = tree_mem
+        self.work_mem = work_mem
+        self.S = S
+        self.n, self.sigma, self.width = n, sigma, width
+        self.stream = stream
+        rc, info = wt_huffman_levels(handle, sigma)
+        if rc != WT_OK:
+            raise WtError(rc, "wt_huffman_levels")
+        self.info = info
+
+    @property
+    def sizes(self):
+        return self.info["sizes"]
+
+    def lengths(self) -> np.ndarray:
+        return (self.info["code_table"] & 31).astype(np.uint8)
+
+    def codes(self) -> np.ndarray:
+        return (self.info["code_table"] >> 8).astype(np.uint32)
+
+    def bitmaps(self):
+        """Per depth: round_up(ceil(n_d/64), 8) uint64 words."""
+        self.check()
+        host = self.tree_mem.cpu().numpy()
+        out = []
+        for d in range(self.levels):
+            words = ((self.sizes[d] + 63) // 64 + 7) // 8 * 8
+            o = self.info["bits_off"][d]
+            out.append(host[o:o + 8 * words].view(np.uint64).copy())
+        return out
+
+    def ranks(self):
+        """Per depth: round_up(ceil(n_d/512) + 1, 8) uint64 directory entries."""
+        self.check()
+        host = self.tree_mem.cpu().numpy()
+        out = []
+        for d in range(self.levels):
+            ent = (self.info["dir_entries"][d] + 7) // 8 * 8
+            o = self.info["dir_off"][d]
+            out.append(host[o:o + 8 * ent].view(np.uint64).copy())
+        return out
+
+
+def histogram(S, sigma: int, width: int | None = None, stream=None) -> np.ndarray:
+    """Symbol counts of a device tensor S (wt_histogram), on the host."""
+    torch = _torch()
+    width = width or S.element_size()
+    n = S.numel()
+    counts = torch.empty(max(1, sigma), dtype=torch.int64, device=S.device)
+    st = stream if stream is not None else torch.cuda.current_stream(S.device)
+    rc = wt_histogram(S.data_ptr() if n else 0, n, sigma, width, counts.data_ptr(), int(st.cuda_stream))
+    if rc != WT_OK:
+        raise WtError(rc, "wt_histogram")
+    st.synchronize()
+    return counts[:sigma].cpu().numpy().view(np.uint64).copy()
+
+
+def build_huffman(S, sigma: int, width: int | None = None, stream=None, counts=None) -> HuffTree:
+    """Huffman-shaped tree of a device tensor S: its histogram on the GPU,
+    then the build from those counts."""
+    torch = _torch()
+    width = width or S.element_size()
+    n = S.numel()
+    st = stream if stream is not None else torch.cuda.current_stream(S.device)
+    if counts is None:
+        counts = histogram(S, sigma, width, st)
+    rc, tb, wb = wt_huffman_footprint(counts, n, sigma, width)
+    if rc != WT_OK:
+        raise WtError(rc, "wt_huffman_footprint")
+    tree_mem = _alloc(tb, S.device)
+    work_mem = _alloc(wb, S.device)
+    rc, h = wt_build_huffman(S.data_ptr() if n else 0, n, sigma, width, counts, tree_mem.data_ptr(),
+                             tree_mem.numel(), work_mem.data_ptr(), work_mem.numel(), int(st.cuda_stream))
+    if rc != WT_OK:
+        raise WtError(rc, "wt_build_huffman")
+    return HuffTree(h, tree_mem, work_mem, S, n, sigma, width, st)
