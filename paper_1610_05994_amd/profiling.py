@@ -56,8 +56,11 @@ def overlap(dispatches):
         last = t
     streams = sorted({d[2] for d in dispatches})
     queues = sorted({d[3] for d in dispatches})
+    window = (max(d[1] for d in dispatches) - min(d[0] for d in dispatches)) if dispatches else 0
     return {"dispatches": len(dispatches), "streams": streams, "queues": queues,
-            "busy_ms": busy / 1e6, "two_or_more_streams_ms": multi_stream / 1e6,
+            "window_ms": window / 1e6, "busy_ms": busy / 1e6,
+            "busy_frac_of_window": (busy / window) if window else 0.0,
+            "two_or_more_streams_ms": multi_stream / 1e6,
             "two_or_more_queues_ms": multi_queue / 1e6,
             "overlap_frac_of_busy": (multi_stream / busy) if busy else 0.0}
 
