@@ -149,7 +149,7 @@ def whole_build_traffic(args, ms_per_step: float):
     """HBM bytes that every kernel of one build moves (rocprofv3 FETCH_SIZE and
     WRITE_SIZE, scaled by a plain copy's readings) over the measured time per
     build, or None for variants and when the counters are stale."""
-    if args.matrix or args.buffered or args.arity == 4:
+    if args.matrix or args.buffered or args.arity == 4 or args.huffman:
         return None
     ent = load_traffic_entry(args.workload)
     if not ent or "bytes_per_build" not in ent:
@@ -255,6 +255,9 @@ def main() -> int:
                     help="build the wavelet matrix of the workload instead of the wavelet tree (c1-c3)")
     ap.add_argument("--arity", type=int, default=2, choices=[2, 4],
                     help="4: build the 4-ary wavelet tree of the workload (c1-c3)")
+    ap.add_argument("--huffman", action="store_true",
+                    help="build the Huffman-shaped wavelet tree of the workload (c1-c3): each step counts the "
+                         "symbols on the GPU, reads the counts back, derives the code on the host and builds")
     ap.add_argument("--buffered", type=int, default=0, metavar="LG",
                     help="buffered build of the workload (c1-c3) in buffers of 2^LG symbols, read from "
                          "page-locked host memory (PCIe included in the step) or, with --buffered-source "
@@ -282,7 +285,7 @@ def main() -> int:
         return 0
     if args.workload == "c5":
         return bench_serve(args)
-    default = args.workload == "c2" and not (args.matrix or args.buffered or args.arity == 4)
+    default = args.workload == "c2" and not (args.matrix or args.buffered or args.arity == 4 or args.huffman)
     out = bench_single(args)
     if out is None:
         return 2
@@ -345,15 +348,20 @@ def bench_single(args):
             os.makedirs(args.input_cache, exist_ok=True)
             np.save(os.path.join(args.input_cache, "%s.npy" % args.workload), S)
     n, width = S.shape[0], S.dtype.itemsize
-    if (args.buffered or args.arity == 4) and args.matrix or (args.buffered and args.arity == 4):
-        print("bench.py: --matrix, --arity 4 and --buffered are separate variants", file=sys.stderr)
+    if sum(bool(x) for x in (args.buffered, args.arity == 4, args.matrix, args.huffman)) > 1:
+        print("bench.py: --matrix, --arity 4, --huffman and --buffered are separate variants", file=sys.stderr)
         return None
     if args.buffered and args.buffered_source == "host":
         view = {1: np.uint8, 2: np.int16, 4: np.int32}[width]
         dS = torch.from_numpy(S.view(view)).pin_memory()
     else:
         dS = wtree.to_device(S, dev)
-    if args.buffered:
+    if args.huffman:
+        counts_dev = torch.empty(sigma, dtype=torch.int64, device=dev)
+        counts_host = torch.empty(sigma, dtype=torch.int64).pin_memory()
+        counts0 = np.bincount(S.astype(np.int64), minlength=sigma).astype(np.uint64)
+        rc, tb, wb = wtree.wt_huffman_footprint(counts0, n, sigma, width)
+    elif args.buffered:
         rc, tb, wb = wtree.wt_buffered_footprint(n, sigma, width, 1 << args.buffered)
     elif args.arity == 4:
         rc, tb, wb = wtree.wt_multiary_footprint(n, sigma, width)
@@ -377,6 +385,18 @@ def bench_single(args):
         def build_fn(S_ptr, n, sigma, width, t_ptr, tb, w_ptr, wb, sh):
             return wtree.wt_build_buffered(S_ptr, n, sigma, width, 1 << args.buffered, t_ptr, tb, w_ptr, wb, sh)
     fn_name = "wt_build_buffered" if args.buffered else build_fn.__name__
+    if args.huffman:
+        def build_fn(S_ptr, n, sigma, width, t_ptr, tb, w_ptr, wb, sh):
+            # the whole method: counts on the GPU, read back, code on the host, build
+            rc = wtree.wt_histogram(S_ptr, n, sigma, width, counts_dev.data_ptr(), sh)
+            if rc != wtree.WT_OK:
+                return rc, 0
+            with torch.cuda.stream(stream):
+                counts_host.copy_(counts_dev, non_blocking=True)
+            stream.synchronize()
+            return wtree.wt_build_huffman(S_ptr, n, sigma, width, counts_host.numpy().view(np.uint64), t_ptr, tb,
+                                          w_ptr, wb, sh)
+        fn_name = "wt_build_huffman"
 
     def one_build():
         rc, h = build_fn(dS.data_ptr(), n, sigma, width, tree_mem.data_ptr(), tb, work_mem.data_ptr(), wb, sh)
@@ -399,6 +419,12 @@ def bench_single(args):
     torch.cuda.synchronize()
     want = torch.from_numpy(S[pos.cpu().numpy()].astype(np.int64))
     assert torch.equal(sym.cpu().to(torch.int64) & 0xFFFFFFFF, want), "sampled access mismatch"
+    huff_info = None
+    if args.huffman:
+        rc, info = wtree.wt_huffman_levels(h, sigma)
+        assert rc == wtree.WT_OK
+        huff_info = {"levels": info["levels"], "bits_per_symbol": sum(info["sizes"]) / max(1, n),
+                     "balanced_levels": max(0, (sigma - 1).bit_length()), "tree_bytes": tb}
     wtree.wt_free(h)
 
     print("bench: timing %d steps" % args.steps, file=sys.stderr, flush=True)
@@ -420,7 +446,8 @@ def bench_single(args):
     p99 = float(np.percentile(step_ms, 99))
     value = n / (ms_per_step / 1e3)
 
-    lvl = [r for r in recs if r["kernel"] == "level"]
+    lvl_kernel = "quad" if args.arity == 4 else "level"  # the pass that moves the symbols
+    lvl = [r for r in recs if r["kernel"] == lvl_kernel]
     lvl_ms = sum(r["ms"] for r in lvl)
     lvl_bytes = sum(r["bytes"] for r in lvl)
     launches = len(lvl)
@@ -434,7 +461,7 @@ def bench_single(args):
         f["avg_us"] = round(f["ms"] * 1e3 / f["launches"], 2)
         f["ms_per_step"] = round(f["ms"] / args.steps, 4)
         del f["ms"]
-    traffic = None if (args.matrix or args.buffered or args.arity == 4) else load_traffic(args.workload)
+    traffic = None if (args.matrix or args.buffered or args.arity == 4 or args.huffman) else load_traffic(args.workload)
     levels = max(0, (sigma - 1).bit_length())
     qmin = n * width + (tb - 256)  # read S once + write every bitmap word and rank entry once
     qmin_gbps = qmin / (p50 / 1e3) / 1e9
@@ -454,7 +481,9 @@ def bench_single(args):
         "data": "synthetic",
         "config": {"workload": "%s: %s%s%s" % (args.workload, WORKLOADS[args.workload],
                                                ("; wavelet matrix" if args.matrix else "") +
-                                               ("; 4-ary wavelet tree" if args.arity == 4 else ""),
+                                               ("; 4-ary wavelet tree" if args.arity == 4 else "") +
+                                               ("; Huffman-shaped wavelet tree (histogram, code and build "
+                                                "in every step)" if args.huffman else ""),
                                                ("; buffered build, 2^%d-symbol buffers from %s" % (
                                                    args.buffered, "page-locked host memory (PCIe included)"
                                                    if args.buffered_source == "host" else "HBM"))
@@ -467,7 +496,8 @@ def bench_single(args):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": traffic,
-            "kernel": "k_level (one launch per tree level)",
+            "kernel": ("k_quad (one four-way split per digit level)" if args.arity == 4
+                       else "k_level (one launch per tree level)"),
             "avg_launch_us": lvl_ms * 1e3 / max(launches, 1),
             "algorithmic_bytes_per_launch": lvl_bytes / max(launches, 1),
             "per_level": per_level_rows(lvl),
@@ -480,6 +510,8 @@ def bench_single(args):
         "whole_build_traffic": whole_build_traffic(args, ms_per_step),
         "kernels": fams,
     }
+    if huff_info:
+        out["huffman"] = huff_info
     if args.buffered:
         mg = [r for r in recs if r["kernel"] == "merge"]
         mg_ms = sum(r["ms"] for r in mg)
@@ -629,7 +661,8 @@ def bench_serve(args) -> int:
         p["host"] = None          # only the device copies and counts are needed
     mean_n = float(np.mean([p["n"] for p in pool]))
     budget = int(float(os.environ.get("WT_SERVE_BUDGET_GIB", "64")) * (1 << 30))
-    srv = serve.Server(budget_bytes=budget, streams=4, max_inflight=8)
+    nstreams = int(os.environ.get("WT_SERVE_STREAMS", "4"))
+    srv = serve.Server(budget_bytes=budget, streams=nstreams, max_inflight=8)
     torch.cuda.synchronize()
 
     def run(count, qps, seed, rid0):
@@ -687,7 +720,7 @@ def bench_serve(args) -> int:
         "dtype": "u8/u16/u32",
         "data": "synthetic",
         "config": {"workload": "c5: " + WORKLOADS["c5"], "pool_sequences": P, "mean_n": mean_n,
-                   "budget_bytes": budget, "streams": 4},
+                   "budget_bytes": budget, "streams": nstreams},
         "latency_ms": {"p50": mid["p50_ms"], "p99": mid["p99_ms"], "at_load": 0.8},
         "serving": {"saturation": sat, "loads": loads, "arena_high_water": srv.arena.high_water},
         "one_call_per_request": {"symbols_per_s": one, "served_speedup": sustain / one},

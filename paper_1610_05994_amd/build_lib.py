@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libwtree.so")
-SOURCES = ["wt_build.hip", "wt_small.hip", "wt_query.hip", "wt_buffered.hip", "wt_multiary.hip", "wt_huffman.hip",
+SOURCES = ["wt_build.hip", "wt_small.hip", "wt_query.hip", "wt_buffered.hip", "wt_multiary.hip", "wt_huffman.hip", "wt_quad.hip",
            "wt_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -200,9 +200,13 @@ static uint64_t dir_wgs(uint64_t n) { return ceil_div(ceil_div(n, 512), kDirBloc
 static void make_layout4(uint64_t n, uint32_t sigma, uint32_t width, Layout *L) {
     uint32_t g = tuned_geometry(n, sigma, width, false);
     if (g == kGeomSmall || g == kGeomMid) g = 32;
-    make_layout_geom(n, sigma, width, g, L);
+    // the tables of a binary split over the code padded to an even number of
+    // bits (2 L4), read two levels at a time by the four-way passes
+    const uint32_t l4 = (levels_for(sigma) + 1) / 2;
+    make_layout_geom(n, (uint32_t)(1ull << (2 * l4)), width, g, L);
+    L->sigma = sigma;
     L->arity = 4;
-    L->levels4 = (L->levels + 1) / 2;
+    L->levels4 = l4;
     L->dwords = round_up(ceil_div(n, 32), 8);
     L->tree_bits_off = L->tree_ranks_off = 0;  // no binary levels
     L->tree_digits_off = kHeaderBytes;
@@ -210,23 +214,27 @@ static void make_layout4(uint64_t n, uint32_t sigma, uint32_t width, Layout *L) 
     L->tree_bytes = L->tree_dir_off + (uint64_t)L->levels4 * L->rank_stride * 32;
     L->ws_dsum = L->work_bytes;
     L->work_bytes += round_up((uint64_t)(L->levels4 ? L->levels4 : 1) * (dir_wgs(n) ? dir_wgs(n) : 1) * 32, 256);
-}
-
-// Binary passes a 4-ary build runs: up to the one whose T_i is the order of
-// the last digit level.  Digit level k (k >= 1) lists the symbols in the
-// order of their top 2k bits of the code padded to 2 L4 bits, i.e. the top
-// 2k - pad bits of the symbol: that order is T_{2k - pad}.
-static uint32_t multiary_passes(const Layout &L) {
-    if (L.levels4 <= 1) return L.levels4;
-    const uint32_t pad = 2 * L.levels4 - L.levels;
-    return 2 * (L.levels4 - 1) - pad + 1;
-}
-
-static int digit_level(const Layout &L, uint32_t i) {  // -1: pass i emits no digit level
-    const uint32_t pad = 2 * L.levels4 - L.levels;
-    if (i == 0) return 0;
-    if ((i + pad) % 2) return -1;
-    return (int)((i + pad) / 2);
+    // four-way passes: their two extra tile counts are cleared with the
+    // control area, so they go right after it and the area grows over them
+    // (everything that followed the control area moves up)
+    const uint64_t stride = tile_stride(L->ntiles);
+    const uint64_t qcnt_bytes = round_up(2ull * (L->levels4 ? L->levels4 : 1) * stride * 4, 256);
+    const uint64_t ctrl_end = L->ws_ctrl + L->ws_ctrl_bytes;
+    uint64_t *after[] = {&L->ws_sup, &L->ws_supsum, &L->ws_zo, &L->ws_start, &L->ws_partials,
+                         &L->ws_fold_own, &L->ws_fold_ovf, &L->ws_dsum};
+    for (uint64_t *o : after)
+        if (*o >= ctrl_end) *o += qcnt_bytes;
+    L->ws_qcnt = ctrl_end;
+    L->ws_ctrl_bytes += qcnt_bytes;
+    L->work_bytes += qcnt_bytes;
+    const uint64_t nsup = L->nsup ? L->nsup : 1;
+    L->ws_qsup = L->work_bytes;
+    L->work_bytes += round_up(2ull * (L->levels4 ? L->levels4 : 1) * nsup * 8, 256);
+    L->ws_qsupsum = L->work_bytes;
+    L->work_bytes += round_up(3ull * nsup * 8, 256);
+    L->ws_qpartials = L->work_bytes;
+    const uint64_t top = L->levels >= 2 ? (1ull << (L->levels - 2)) : 1;  // nodes of the last four-way level
+    L->work_bytes += round_up(3ull * ceil_div(top, 1024) * 8, 256);
 }
 
 // Whether the last level of a build is folded into the pass before it:
@@ -262,14 +270,13 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
     uint64_t *start = reinterpret_cast<uint64_t *>(work + L.ws_start);
     uint64_t *partials = reinterpret_cast<uint64_t *>(work + L.ws_partials);
 
-    const bool four = L.arity == 4;
     const bool fold = fold_last_level(L, partial);
     // folded: granules below n get one writer each (the pass or the stitch);
     // the words from the one holding position n on are cleared by ingest
     uint64_t *bits_last = fold ? bits + (uint64_t)(l - 1) * L.words : nullptr;
     long pr = prof_begin(st, "zero", 0, L.width, L.n, L.ws_ctrl_bytes);
     hipError_t err = launch_zero(work + L.ws_ctrl, L.ws_ctrl_bytes, tree_status,
-                                 (L.n == 0 && !four) ? ranks : nullptr, (uint64_t)l * L.rank_stride, st);
+                                 L.n == 0 ? ranks : nullptr, (uint64_t)l * L.rank_stride, st);
     prof_end(pr, st);
     if (err == hipSuccess && L.n == 0 && L.matrix && l)  // the zeros of an empty matrix
         err = launch_zero(tree + kZerosOff, (uint64_t)l * 8, tree_status, nullptr, 0, st);
@@ -302,7 +309,7 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
     if (l == 0) return hipSuccess;
 
     uint8_t *tbuf[2] = {work + L.ws_ta, work + L.ws_tb};
-    const uint32_t lrun = four ? multiary_passes(L) : (fold ? l - 1 : l);  // binary passes to run
+    const uint32_t lrun = fold ? l - 1 : l;  // passes to run
     for (uint32_t i = 0; i < lrun; i++) {
         PlanArgs pa;
         pa.start = start + start_offset(i);
@@ -343,13 +350,11 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         a.tin = (i == 0) ? S : tbuf[(i - 1) & 1];  // T_i for i >= 1 alternates ta, tb
         // (folded: T_{l-1} receives the edge symbols of the split only)
         a.tout = (i + 1 < lrun || fold_here) ? tbuf[i & 1] : nullptr;
-        a.bits = four ? nullptr : bits + (uint64_t)i * L.words;
-        a.ranks = four ? nullptr : ranks + (uint64_t)i * L.rank_stride;
-        const int dl = four ? digit_level(L, i) : -1;
-        a.digits = (dl >= 0) ? reinterpret_cast<uint64_t *>(tree + L.tree_digits_off) + (uint64_t)dl * L.dwords
-                             : nullptr;
-        a.dwords = L.dwords;
-        a.dsh = (dl >= 0) ? 2 * (L.levels4 - 1 - (uint32_t)dl) : 0u;
+        a.bits = bits + (uint64_t)i * L.words;
+        a.ranks = ranks + (uint64_t)i * L.rank_stride;
+        a.digits = nullptr;
+        a.dwords = 0;
+        a.dsh = 0;
         a.zo = zo + zo_offset(i);
         a.tile_ones = tile_ones + (uint64_t)i * tile_stride(L.ntiles);
         a.sup = sup + (uint64_t)i * L.nsup;
@@ -414,10 +419,103 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
     return err;
 }
 
-// A 4-ary build: the binary passes with digit emission, then the digit
+// A 4-ary build: one four-way pass per digit level over the code padded to
+// 2 L4 bits (digit level k is binary level 2k of that code), then the digit
 // directories (also for n = 0: the level totals and padding).
 static hipError_t enqueue_multiary(const void *S, const Layout &L, uint8_t *tree, uint8_t *work, hipStream_t st) {
-    hipError_t err = enqueue_build(S, L, tree, work, st);
+    const uint32_t L4 = L.levels4, lp = L.levels;  // lp = 2 L4
+    uint32_t *tree_status = reinterpret_cast<uint32_t *>(tree);
+    uint32_t *tile_ones = reinterpret_cast<uint32_t *>(work + L.ws_tile_ones);
+    uint32_t *qcnt = reinterpret_cast<uint32_t *>(work + L.ws_qcnt);
+    unsigned long long *ones = reinterpret_cast<unsigned long long *>(work + L.ws_ones);
+    unsigned long long *sup = reinterpret_cast<unsigned long long *>(work + L.ws_sup);
+    unsigned long long *qsup = reinterpret_cast<unsigned long long *>(work + L.ws_qsup);
+    unsigned long long *qsupsum = reinterpret_cast<unsigned long long *>(work + L.ws_qsupsum);
+    unsigned long long *qpart = reinterpret_cast<unsigned long long *>(work + L.ws_qpartials);
+    ulonglong2 *zo = reinterpret_cast<ulonglong2 *>(work + L.ws_zo);
+    uint64_t *start = reinterpret_cast<uint64_t *>(work + L.ws_start);
+    const uint64_t stride = tile_stride(L.ntiles), nsup = L.nsup;
+    long pr = prof_begin(st, "zero", 0, L.width, L.n, L.ws_ctrl_bytes);
+    hipError_t err = launch_zero(work + L.ws_ctrl, L.ws_ctrl_bytes, tree_status, nullptr, 0, st);
+    prof_end(pr, st);
+    if (err == hipSuccess && L.n > 0 && L4 > 0) {
+        QuadIngestArgs ia;
+        ia.S = S;
+        ia.cnt[0] = tile_ones;
+        ia.cnt[1] = qcnt;
+        ia.cnt[2] = qcnt + stride;
+        ia.ones_a0 = ones + ones_offset(0);
+        ia.ones_b1 = ones + ones_offset(1);
+        ia.slots_a0 = level_slots(0);
+        ia.slots_b1 = level_slots(1);
+        ia.start0 = start + start_offset(0);
+        ia.tree_status = tree_status;
+        ia.n = L.n;
+        ia.ntiles = L.ntiles;
+        ia.sigma = L.sigma;
+        ia.check = (L.width < 4 && (uint64_t)L.sigma == (1ull << (8 * L.width))) ? 0u : 1u;
+        ia.levels = lp;
+        pr = prof_begin(st, "ingest", 0, L.width, L.n, L.n * L.width);
+        err = launch_quad_ingest(ia, L.width, L.lane_bytes, st);
+        prof_end(pr, st);
+        uint8_t *tbuf[2] = {work + L.ws_ta, work + L.ws_tb};
+        for (uint32_t k = 0; k < L4 && err == hipSuccess; k++) {
+            const uint32_t i = 2 * k;
+            const bool more = k + 1 < L4;
+            QuadPrepArgs pp;
+            pp.cnt[0] = tile_ones + (uint64_t)i * stride;
+            pp.cnt[1] = qcnt + (uint64_t)(2 * k) * stride;
+            pp.cnt[2] = qcnt + (uint64_t)(2 * k + 1) * stride;
+            for (int j = 0; j < 3; j++) pp.supsum[j] = qsupsum + (uint64_t)j * nsup;
+            pp.sup[0] = sup + (uint64_t)i * nsup;
+            pp.sup[1] = qsup + (uint64_t)(2 * k) * nsup;
+            pp.sup[2] = qsup + (uint64_t)(2 * k + 1) * nsup;
+            pp.ntiles = L.ntiles;
+            pp.nsup = nsup;
+            pp.start = start + start_offset(i);
+            pp.ones_a = ones + ones_offset(i);
+            pp.ones_b = ones + ones_offset(i + 1);
+            pp.slots_a = level_slots(i);
+            pp.slots_b = level_slots(i + 1);
+            pp.K = zo + zo_offset(i);  // (2 entries per node: the zo space of levels i and i + 1)
+            pp.start_next = more ? start + start_offset(i + 2) : nullptr;
+            pp.partials = qpart;
+            pp.nodes = 1ull << i;
+            pp.n = L.n;
+            pr = prof_begin(st, "prep", k, L.width, L.n, L.ntiles * 12 + nsup * 48);
+            err = launch_quad_prep(pp, st);
+            prof_end(pr, st);
+            if (err != hipSuccess) break;
+            QuadArgs a;
+            a.tin = (k == 0) ? S : tbuf[(k - 1) & 1];
+            a.tout = more ? tbuf[k & 1] : nullptr;
+            a.K = zo + zo_offset(i);
+            for (int j = 0; j < 3; j++) {
+                a.cnt[j] = pp.cnt[j];
+                a.sup[j] = pp.sup[j];
+            }
+            a.cnt_next[0] = more ? tile_ones + (uint64_t)(i + 2) * stride : nullptr;
+            a.cnt_next[1] = more ? qcnt + (uint64_t)(2 * k + 2) * stride : nullptr;
+            a.cnt_next[2] = more ? qcnt + (uint64_t)(2 * k + 3) * stride : nullptr;
+            a.ones_a_next = more ? ones + ones_offset(i + 2) : nullptr;
+            a.ones_b_next = more ? ones + ones_offset(i + 3) : nullptr;
+            a.nodes_a_next = 1ull << (i + 2);
+            a.slots_a_next = level_slots(i + 2);
+            a.nodes_b_next = 1ull << (i + 3);
+            a.slots_b_next = level_slots(i + 3);
+            a.n = L.n;
+            a.ntiles = L.ntiles;
+            a.levels = lp;
+            a.level = i;
+            a.symmask = (uint32_t)((1ull << lp) - 1);
+            a.digits = reinterpret_cast<uint64_t *>(tree + L.tree_digits_off) + (uint64_t)k * L.dwords;
+            a.dwords = L.dwords;
+            const uint64_t qbytes = L.n * L.width * (more ? 2 : 1) + L.dwords * 8;
+            pr = prof_begin(st, "quad", k, L.width, L.n, qbytes);
+            err = launch_quad(a, L.width, L.lane_bytes, st);
+            prof_end(pr, st);
+        }
+    }
     if (err != hipSuccess) return err;
     DigitDirArgs d;
     d.digits = reinterpret_cast<const uint64_t *>(tree + L.tree_digits_off);
@@ -428,8 +526,8 @@ static hipError_t enqueue_multiary(const void *S, const Layout &L, uint8_t *tree
     d.dir_stride = L.rank_stride;
     d.nblk = ceil_div(L.n, 512);
     d.wg_per_level = dir_wgs(L.n);
-    d.levels = L.levels4;
-    long pr = prof_begin(st, "digit_dir", 0, L.width, L.n, (uint64_t)L.levels4 * (L.dwords * 8 + L.rank_stride * 32));
+    d.levels = L4;
+    pr = prof_begin(st, "digit_dir", 0, L.width, L.n, (uint64_t)L4 * (L.dwords * 8 + L.rank_stride * 32));
     err = launch_digit_dir(d, st);
     prof_end(pr, st);
     return err;
@@ -754,12 +852,33 @@ struct HuffPlan {
 static int huff_lengths(const uint64_t *counts, uint32_t sigma, std::vector<uint8_t> &len, uint32_t &maxlen) {
     len.assign(sigma, 0);
     maxlen = 0;
-    std::vector<uint32_t> leaf;
+    // the symbols that occur, by (count, symbol): a counting sort by count
+    // (stable, symbols taken in increasing order) when the counts are small
+    // next to the number of symbols, else a sort of the distinct packed keys
+    // count << 24 | symbol (count < 2^40, symbol < 2^24)
+    uint64_t k = 0, maxc = 0;
     for (uint32_t c = 0; c < sigma; c++)
-        if (counts[c]) leaf.push_back(c);
-    const size_t k = leaf.size();
+        if (counts[c]) {
+            k++;
+            maxc = std::max<uint64_t>(maxc, counts[c]);
+        }
     if (k < 2) return WT_OK;
-    std::stable_sort(leaf.begin(), leaf.end(), [&](uint32_t x, uint32_t y) { return counts[x] < counts[y]; });
+    std::vector<uint32_t> leaf(k);
+    if (maxc <= 4 * k + 1024) {
+        std::vector<uint32_t> pos(maxc + 2, 0);
+        for (uint32_t c = 0; c < sigma; c++)
+            if (counts[c]) pos[counts[c] + 1]++;
+        for (uint64_t x = 1; x < pos.size(); x++) pos[x] += pos[x - 1];
+        for (uint32_t c = 0; c < sigma; c++)
+            if (counts[c]) leaf[pos[counts[c]]++] = c;
+    } else {
+        std::vector<uint64_t> key;
+        key.reserve(k);
+        for (uint32_t c = 0; c < sigma; c++)
+            if (counts[c]) key.push_back((counts[c] << 24) | c);
+        std::sort(key.begin(), key.end());
+        for (size_t i = 0; i < k; i++) leaf[i] = (uint32_t)(key[i] & 0xFFFFFFu);
+    }
     // items: leaves 0..k-1 (in queue order), merged items k..2k-2
     std::vector<uint64_t> w(2 * k - 1), up(2 * k - 1);
     for (size_t i = 0; i < k; i++) w[i] = counts[leaf[i]];
@@ -811,26 +930,37 @@ static int plan_huffman(const uint64_t *counts, const wt_desc *desc, HuffPlan *P
     P->syms.clear();
     for (uint32_t c = 0; c < sigma; c++)
         if (counts[c]) P->code_tab[c] = kHuffPresent;  // (length 0 when the tree has no levels)
+    // codes per length, then each length's symbols in symbol order (one
+    // counting pass), and the occurrences per length for the depth sizes
+    uint64_t occ[kHuffMaxLevels + 1] = {0};
+    for (uint32_t c = 0; c < sigma; c++)
+        if (len[c]) {
+            m.count[len[c]]++;
+            occ[len[c]] += counts[c];
+        }
     uint64_t next = 0;  // first code of the current length
+    uint32_t at = 0;
     for (uint32_t l = 1; l <= L; l++) {
         m.first[l] = (uint32_t)next;
-        m.start[l] = (uint32_t)P->syms.size();
-        uint32_t cnt = 0;
-        for (uint32_t c = 0; c < sigma; c++) {
-            if (len[c] != l) continue;
-            P->code_tab[c] = l | kHuffPresent | ((uint32_t)(next + cnt) << 8);
-            P->syms.push_back(c);
-            cnt++;
-        }
-        m.count[l] = cnt;
-        next = (next + cnt) << 1;
+        m.start[l] = at;
+        at += m.count[l];
+        next = (next + m.count[l]) << 1;
+    }
+    P->syms.assign(at, 0);
+    uint32_t fill[kHuffMaxLevels + 1];
+    for (uint32_t l = 1; l <= L; l++) fill[l] = 0;
+    for (uint32_t c = 0; c < sigma; c++) {
+        const uint32_t l = len[c];
+        if (!l) continue;
+        P->code_tab[c] = l | kHuffPresent | ((m.first[l] + fill[l]) << 8);
+        P->syms[m.start[l] + fill[l]] = c;
+        fill[l]++;
     }
     // depth sizes: symbols whose code is longer than d
-    for (uint32_t d = 0; d < L; d++) {
-        uint64_t sz = 0;
-        for (uint32_t c = 0; c < sigma; c++)
-            if (len[c] > d) sz += counts[c];
-        m.size[d] = sz;
+    uint64_t longer = 0;
+    for (uint32_t d = L; d-- > 0;) {
+        longer += occ[d + 1];
+        m.size[d] = longer;
     }
     // tree layout
     uint64_t off = kHeaderBytes + kHuffMetaBytes;

@@ -22,6 +22,8 @@ namespace wt {
 
 namespace {
 
+#include "wt_wave.h"
+
 constexpr int kHThreads = 256;
 constexpr uint32_t kHistLds = 8192;  // alphabets up to this size count in LDS first
 
@@ -61,27 +63,71 @@ __global__ __launch_bounds__(kHThreads) void k_hist(const void *S, uint64_t n, u
     }
 }
 
+// One 16-byte chunk of S per thread (16 / W symbols), its codes stored as
+// one run of 16 / W values of WO bytes; a chunk reaching past n goes symbol
+// by symbol.
 template <int W, int WO>
 __global__ __launch_bounds__(kHThreads) void k_huff_map(const void *S, uint64_t n, const uint32_t *code_tab,
                                                         uint32_t sigma, uint32_t levels, void *K,
                                                         uint32_t *status) {
+    constexpr int CH = 16 / W;
+    const uint64_t chunks = (n + CH - 1) / CH;
     const uint64_t stride = (uint64_t)gridDim.x * kHThreads;
     bool bad = false;
-    for (uint64_t j = (uint64_t)blockIdx.x * kHThreads + threadIdx.x; j < n; j += stride) {
-        const uint32_t s = sym_load<W>(S, j);
-        uint32_t k = 0;
-        if (s >= sigma) {
-            bad = true;
+    for (uint64_t c = (uint64_t)blockIdx.x * kHThreads + threadIdx.x; c < chunks; c += stride) {
+        const uint64_t j0 = c * CH;
+        const int cnt = (j0 + CH <= n) ? CH : (int)(n - j0);
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (cnt == CH) {
+            v = reinterpret_cast<const uint4 *>(S)[c];
         } else {
-            const uint32_t e = code_tab[s];
-            const uint32_t len = e & 31u;
-            if (!(e & kHuffPresent)) bad = true;
-            else if (len) k = (e >> 8) << (levels - len);
+            uint32_t d[4] = {0, 0, 0, 0};
+            for (int e = 0; e < cnt; e++) {
+                const uint32_t x = sym_load<W>(S, j0 + e);
+                d[(e * W) >> 2] |= (W == 4) ? x : (x << (8 * ((e * W) & 3)));
+            }
+            v = make_uint4(d[0], d[1], d[2], d[3]);
+        }
+        constexpr int NW = (CH * WO) / 4;  // 32-bit words of the chunk's codes (CH * WO >= 4)
+        uint32_t wd[NW];
+#pragma unroll
+        for (int q = 0; q < NW; q++) wd[q] = 0;
+#pragma unroll
+        for (int e = 0; e < CH; e++) {
+            const uint32_t s = chunk_elem<W>(v, e);
+            uint32_t k = 0;
+            if (e < cnt) {
+                if (s >= sigma) {
+                    bad = true;
+                } else {
+                    const uint32_t ent = code_tab[s];
+                    const uint32_t len = ent & 31u;
+                    if (!(ent & kHuffPresent)) bad = true;
+                    else if (len) k = (ent >> 8) << (levels - len);
+                }
+            }
+            wd[(e * WO) >> 2] |= (WO == 4) ? k : (k << (8 * ((e * WO) & 3)));
         }
         if (K == nullptr) continue;  // (no levels: the symbols are only checked)
-        if (WO == 1) reinterpret_cast<uint8_t *>(K)[j] = (uint8_t)k;
-        else if (WO == 2) reinterpret_cast<uint16_t *>(K)[j] = (uint16_t)k;
-        else reinterpret_cast<uint32_t *>(K)[j] = k;
+        uint8_t *dst = reinterpret_cast<uint8_t *>(K) + j0 * WO;  // CH * WO-byte aligned
+        if (cnt == CH) {
+            if (NW >= 4) {
+#pragma unroll
+                for (int q = 0; q < NW / 4; q++)
+                    reinterpret_cast<uint4 *>(dst)[q] = make_uint4(wd[4 * q], wd[4 * q + 1], wd[4 * q + 2], wd[4 * q + 3]);
+            } else if (NW == 2) {
+                *reinterpret_cast<uint2 *>(dst) = make_uint2(wd[0], wd[NW - 1]);
+            } else {
+                *reinterpret_cast<uint32_t *>(dst) = wd[0];
+            }
+        } else {
+            for (int e = 0; e < cnt; e++) {
+                const uint32_t k = (WO == 4) ? wd[e] : ((wd[(e * WO) >> 2] >> (8 * ((e * WO) & 3))) & ((1u << (8 * WO)) - 1u));
+                if (WO == 1) dst[e] = (uint8_t)k;
+                else if (WO == 2) reinterpret_cast<uint16_t *>(dst)[e] = (uint16_t)k;
+                else reinterpret_cast<uint32_t *>(dst)[e] = k;
+            }
+        }
     }
     if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(status, 1u);
 }
@@ -110,8 +156,8 @@ hipError_t launch_histogram(const void *S, uint64_t n, uint32_t width, uint32_t 
 hipError_t launch_huff_map(const void *S, uint64_t n, uint32_t width, const uint32_t *code_tab, uint32_t sigma,
                            uint32_t levels, void *K, uint32_t wout, uint32_t *status, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    const uint64_t want = ceil_div(n, (uint64_t)kHThreads * 8);
-    const dim3 g((uint32_t)(want < 8192 ? want : 8192));
+    const uint64_t want = ceil_div(ceil_div(n, 16 / width), (uint64_t)kHThreads);
+    const dim3 g((uint32_t)(want < 16384 ? (want ? want : 1) : 16384));
     switch (width * 10 + wout) {
         case 11: hipLaunchKernelGGL((k_huff_map<1, 1>), g, dim3(kHThreads), 0, s, S, n, code_tab, sigma, levels, K, status); break;
         case 12: hipLaunchKernelGGL((k_huff_map<1, 2>), g, dim3(kHThreads), 0, s, S, n, code_tab, sigma, levels, K, status); break;

@@ -76,6 +76,10 @@ struct Layout {
     uint64_t dwords;        // 4-ary: 64-bit words per digit level (32 digits each, padded to 8)
     uint64_t tree_digits_off, tree_dir_off;  // 4-ary: digit levels, then directories (4 u64 per entry)
     uint64_t ws_dsum;       // 4-ary: per level and directory workgroup, four digit counts (u64)
+    // four-way split passes: per digit level the tile counts of b and a & b
+    // (inside the control area), their superchunk prefixes, the superchunk
+    // sums of the three counts, the scan partials of large levels
+    uint64_t ws_qcnt, ws_qsup, ws_qsupsum, ws_qpartials;
     uint64_t words;         // W: bitmap words per level
     uint64_t rank_entries;  // K
     uint64_t rank_stride;   // round_up(K, 8)
@@ -353,6 +357,69 @@ hipError_t launch_histogram(const void *S, uint64_t n, uint32_t width, uint32_t 
 hipError_t launch_huff_map(const void *S, uint64_t n, uint32_t width, const uint32_t *code_tab, uint32_t sigma,
                            uint32_t levels, void *K, uint32_t wout, uint32_t *status, hipStream_t s);
 
+
+// Four-way split (wt_quad.hip): one pass over T_i writes T_{i+2}, the
+// symbols of every level-i node stably split into its four grandchildren by
+// the two bits below the node prefix, the digit d = 2a + b (a = bit l-1-i, b =
+// bit l-2-i).  Per tile of T_i the pass needs the counts of a, of b and of
+// a & b (prefix-summed over tiles: A(p), B(p), AB(p) = the counts before
+// position p); per node v the table K(v) = (K0, K1, K2, K3) with
+//   destination of digit 0 at p: K0 + p - A(p) - B(p) + AB(p)
+//   digit 1: K1 + B(p) - AB(p),  digit 2: K2 + A(p) - AB(p),  digit 3: K3 + AB(p).
+// Node counts come in the binary counters of levels i (a-ones per level-i
+// node) and i + 1 (b-ones per level-(i+1) node 2v + a).
+struct QuadArgs {
+    const void *tin;
+    void *tout;                        // T_{i+2} (null: no next order)
+    const ulonglong2 *K;               // per node: (K0, K1), (K2, K3)
+    const uint32_t *cnt[3];            // per tile of T_i: counts of a, b, a & b
+    const unsigned long long *sup[3];  // their superchunk prefixes
+    uint32_t *cnt_next[3];             // the same for T_{i+2} (accumulated), or null
+    unsigned long long *ones_a_next;   // level i+2: a'-ones per node (slot-spread), or null
+    unsigned long long *ones_b_next;   // level i+3: b'-ones per node 2g + a' (slot-spread), or null
+    uint64_t nodes_a_next, slots_a_next, nodes_b_next, slots_b_next;
+    uint64_t n, ntiles;
+    uint32_t levels, level, symmask;   // level = i (even for a 4-ary tree's digit level i / 2)
+    // 4-ary tree: digit level i / 2 (32 digits per word), or null
+    uint64_t *digits;
+    uint64_t dwords;
+};
+hipError_t launch_quad(const QuadArgs &a, uint32_t width, uint32_t lane_bytes, hipStream_t s);
+
+// Node tables of a four-way level: superchunk prefixes of the three tile
+// counts, K(v) for the 2^i nodes of level i, and the node starts of level
+// i + 2 (four per node).
+struct QuadPrepArgs {
+    const uint32_t *cnt[3];
+    unsigned long long *supsum[3];     // scratch: per-superchunk sums
+    unsigned long long *sup[3];        // output: their exclusive prefixes
+    uint64_t ntiles, nsup;
+    const uint64_t *start;             // level i node starts (nodes + 1)
+    const unsigned long long *ones_a;  // level i a-ones, slots_a copies
+    const unsigned long long *ones_b;  // level i+1 b-ones (2 nodes per level-i node), slots_b copies
+    uint64_t slots_a, slots_b;
+    ulonglong2 *K;                     // output: 2 per node
+    uint64_t *start_next;              // output: level i+2 starts (4 nodes + 1), or null
+    unsigned long long *partials;      // scratch: 3 per chunk of kScanChunk nodes
+    uint64_t nodes, n;
+};
+hipError_t launch_quad_prep(const QuadPrepArgs &a, hipStream_t s);
+
+// Counts of the first four-way level straight from S: per tile of S the
+// counts of a, b, a & b (the two top bits of l), the root's a-ones and the
+// b-ones of the two level-1 nodes; symbols >= sigma flagged.
+struct QuadIngestArgs {
+    const void *S;
+    uint32_t *cnt[3];
+    unsigned long long *ones_a0;       // slots_a0 copies of 1 node
+    unsigned long long *ones_b1;       // slots_b1 copies of 2 nodes
+    uint64_t slots_a0, slots_b1;
+    uint64_t *start0;                  // {0, n}
+    uint32_t *tree_status;
+    uint64_t n, ntiles;
+    uint32_t sigma, check, levels;
+};
+hipError_t launch_quad_ingest(const QuadIngestArgs &a, uint32_t width, uint32_t lane_bytes, hipStream_t s);
 
 // query launchers (wt_query.hip)
 struct TreeView {
