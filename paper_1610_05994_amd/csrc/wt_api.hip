@@ -117,12 +117,57 @@ uint32_t tuned_geometry(uint64_t n, uint32_t sigma, uint32_t width, bool batched
     return resolve_geometry(g_tune[batched ? 1 : 0][wclass(width)][l < 25 ? l : 24][floor_lg(n)], n, width);
 }
 
+// Bytes per symbol that hold `bits` bits.
+static uint32_t bytes_for(uint32_t bits) { return bits <= 8 ? 1u : (bits <= 16 ? 2u : 4u); }
+
+// Builds of at least this many symbols narrow their symbol orders (smaller
+// ones are bound by launches, not bytes, and the anchor tables cost one).
+constexpr uint64_t kNarrowMinN = 1ull << 18;
+
+// Narrowed orders of a single binary-tree build (2- and 4-byte symbols):
+// T_{i+1} halves the width of T_i as soon as the levels after i fit in half
+// of it, where a narrowing pass exists for the width and the lane's symbol
+// count E (which stays the same: the tiles, and every per-tile table, are
+// those of the input), and where the anchor nodes the half width needs are
+// few beside the tiles (a tile over two anchors takes the slower direct
+// split: at most one tile in kAnchorTiles may); a width whose 8w bits hold
+// fewer bits than the levels gets the per-tile anchor table of level
+// levels - 8w.
+constexpr uint64_t kAnchorTiles = 8;
+static void plan_narrowing(Layout *L) {
+    const uint32_t l = L->levels;
+    L->narrow = 0;
+    for (uint32_t i = 0; i <= kMaxTreeLevels; i++) L->tw[i] = (uint8_t)L->width;
+    if (L->small || L->width < 2 || l < 2 || L->n < kNarrowMinN) return;
+    const uint32_t E = L->lane_bytes / L->width;
+    for (uint32_t i = 0; i + 1 < l; i++) {
+        const uint32_t w = L->tw[i];
+        const uint32_t half_bits = 8 * (w / 2);
+        const bool few_anchors = half_bits >= l || (kAnchorTiles << (l - half_bits)) <= L->ntiles;
+        const bool halve = w >= 2 && bytes_for(l - (i + 1)) <= w / 2 && narrowing_pass(w, E * w) && few_anchors;
+        L->tw[i + 1] = (uint8_t)(halve ? w / 2 : w);
+        if (halve) L->narrow = 1;
+    }
+    for (uint32_t i = l; i <= kMaxTreeLevels; i++) L->tw[i] = L->tw[l - 1];
+    if (!L->narrow) return;
+    for (uint32_t w = 1; w <= 2; w++) {
+        bool used = false;
+        for (uint32_t i = 0; i < l; i++) used |= L->tw[i] == w;
+        if (!used || 8 * w >= l) continue;
+        L->anc_level[w - 1] = l - 8 * w;
+        L->ws_tanc[w - 1] = L->work_bytes;
+        L->work_bytes += round_up(L->ntiles * 8, 256);
+    }
+}
+
 void make_layout(uint64_t n, uint32_t sigma, uint32_t width, bool batched, Layout *L) {
     make_layout_geom(n, sigma, width, tuned_geometry(n, sigma, width, batched), L);
+    if (!batched) plan_narrowing(L);
 }
 
 void make_layout_geom(uint64_t n, uint32_t sigma, uint32_t width, uint32_t geom, Layout *L) {
     memset(L, 0, sizeof(*L));
+    for (uint32_t i = 0; i <= kMaxTreeLevels; i++) L->tw[i] = (uint8_t)width;  // (no narrowing)
     const uint32_t l = levels_for(sigma);
     L->n = n;
     L->sigma = sigma;
@@ -310,6 +355,11 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
 
     uint8_t *tbuf[2] = {work + L.ws_ta, work + L.ws_tb};
     const uint32_t lrun = fold ? l - 1 : l;  // passes to run
+    // narrowed orders: T_i has tw[i] bytes per symbol, the same E symbols
+    // per lane (so the same tiles) at every width
+    const bool narrow = L.narrow && !partial && !L.matrix && L.arity != 4;
+    const uint32_t E = L.lane_bytes / L.width;
+    bool anc_ready[2] = {false, false};
     for (uint32_t i = 0; i < lrun; i++) {
         PlanArgs pa;
         pa.start = start + start_offset(i);
@@ -345,7 +395,27 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         prof_end(pr, st);
         if (err != hipSuccess) return err;
 
+        const uint32_t w = narrow ? L.tw[i] : L.width;
+        const uint32_t wo = (narrow && i + 1 < l) ? L.tw[i + 1] : w;
+        const bool anchored = narrow && w < L.width && 8 * w < l;
+        if (anchored && !anc_ready[w - 1]) {
+            // the anchor level's node starts exist since that level's prep
+            AnchorArgs an;
+            an.start = start + start_offset(L.anc_level[w - 1]);
+            an.nodes = 1ull << L.anc_level[w - 1];
+            an.n = L.n;
+            an.tile = tile_syms(L.width, L.lane_bytes);
+            an.ntiles = L.ntiles;
+            an.out = reinterpret_cast<uint2 *>(work + L.ws_tanc[w - 1]);
+            pr = prof_begin(st, "anchor", i, w, L.n, L.ntiles * 8);
+            err = launch_tile_anchor(an, st);
+            prof_end(pr, st);
+            if (err != hipSuccess) return err;
+            anc_ready[w - 1] = true;
+        }
+
         LevelArgs a;
+        memset(&a, 0, sizeof(a));
         const bool fold_here = fold && i + 1 == lrun;
         a.tin = (i == 0) ? S : tbuf[(i - 1) & 1];  // T_i for i >= 1 alternates ta, tb
         // (folded: T_{l-1} receives the edge symbols of the split only)
@@ -369,7 +439,10 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         a.ntiles = L.ntiles;
         a.levels = l;
         a.level = i;
-        a.symmask = (uint32_t)((1ull << l) - 1);
+        // (a narrowed symbol keeps its low 8w bits only)
+        a.symmask = (uint32_t)((1ull << (anchored ? 8 * w : l)) - 1);
+        a.anc_start = anchored ? start + start_offset(L.anc_level[w - 1]) : nullptr;
+        a.tile_anc = anchored ? reinterpret_cast<const uint2 *>(work + L.ws_tanc[w - 1]) : nullptr;
         a.matrix = L.matrix;
         a.zeros = L.matrix ? reinterpret_cast<unsigned long long *>(tree + kZerosOff) : nullptr;
         a.bits_next = fold_here ? bits_last : nullptr;
@@ -379,11 +452,12 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         a.fold_ovf_n = fold_here ? reinterpret_cast<unsigned int *>(work + L.ws_fold_cnt) : nullptr;
         a.fold_ovf_cap = fold_here ? L.fold_ovf_cap : 0;
         a.fold_status = tree_status;
-        const uint64_t lbytes = L.n * L.width * ((a.tout && !fold_here) ? 2 : 1) +
+        const uint64_t lbytes = L.n * w + ((a.tout && !fold_here) ? L.n * wo : 0) +
                                 (a.bits ? L.words * 8 + L.rank_stride * 8 : 0) + (a.digits ? L.dwords * 8 : 0) +
                                 (a.bits_next ? L.words * 8 : 0);
-        pr = prof_begin(st, "level", i, L.width, L.n, lbytes);
-        err = launch_level(a, L.width, L.lane_bytes, !L.matrix && level_multi(L.n, i, L.width, L.lane_bytes), st);
+        const uint32_t lb = E * w;  // lane bytes at this width
+        pr = prof_begin(st, "level", i, w, L.n, lbytes);
+        err = launch_level(a, w, lb, !L.matrix && wo == w && level_multi(L.n, i, w, lb), wo, st);
         prof_end(pr, st);
         if (err != hipSuccess) return err;
     }
@@ -1119,7 +1193,7 @@ static hipError_t enqueue_huffman(const void *S, const wt_desc *desc, const Huff
         const uint64_t lbytes = nd * I.width + nnext * I.width + a.words * 8 + a.rank_stride * 8;
         pr = prof_begin(st, "level", d, I.width, nd, lbytes);
         // (the plain variant: every destination comes from the node tables)
-        err = launch_level(a, I.width, I.lane_bytes, false, st);
+        err = launch_level(a, I.width, I.lane_bytes, false, I.width, st);
         prof_end(pr, st);
         if (err != hipSuccess) return err;
     }

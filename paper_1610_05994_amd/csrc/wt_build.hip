@@ -158,11 +158,12 @@ __device__ __forceinline__ uint32_t chunk_bits16(const uint4 &v, uint32_t sh) {
 
 // Stable split of one lane's symbols into LDS: zeros to zc, zc+1, ...,
 // ones to oc, oc+1, ...  kFull: all E symbols are valid (no guards).  The
-// level bits come in the order of level_bit_pos.
-template <int W, int B, bool kFull>
-__device__ __forceinline__ void stage_split(typename ElemT<W>::T *s_stage, const uint4 (&raw)[B / 16],
+// level bits come in the order of level_bit_pos.  The staged symbols are
+// WO-byte (their low bytes: WO < W narrows them).
+template <int W, int B, int WO, bool kFull>
+__device__ __forceinline__ void stage_split(typename ElemT<WO>::T *s_stage, const uint4 (&raw)[B / 16],
                                             typename MaskT<B / W>::T mb, uint32_t zc, uint32_t oc, int nval) {
-    typedef typename ElemT<W>::T T;
+    typedef typename ElemT<WO>::T T;
     constexpr int E = B / W;
     // With zp the next zero slot and D = (next one slot - zp) + k, symbol k
     // goes to zp + b * (D - k); zp advances on a zero, D by 2 on a one (one
@@ -178,7 +179,7 @@ __device__ __forceinline__ void stage_split(typename ElemT<W>::T *s_stage, const
             const int q = (k * W) >> 2;
             const uint4 &c = raw[q / 4];
             const uint32_t d = (q % 4 == 0) ? c.x : (q % 4 == 1) ? c.y : (q % 4 == 2) ? c.z : c.w;
-            // the store keeps the low W bytes of x (or, for the third byte of
+            // the store keeps the low WO bytes of x (or, for the third byte of
             // a dword, the d16_hi form picks it), so no masking is needed
             uint32_t x;
             if (W == 4) x = d;
@@ -530,10 +531,11 @@ struct MultiTables {
 };
 constexpr uint32_t kMultiTablesBytes = (uint32_t)((sizeof(MultiTables) + 15) / 16 * 16);
 
-template <int W, int B>
+template <int W, int B, int WO = W>
 __host__ __device__ constexpr uint32_t multi_stage_elems() {
-    // every run wastes fewer than CH slots at each end
-    return (uint32_t)tile_syms(W, B) + 2 * kRunNodes * 2 * (16 / W);
+    // every run wastes fewer than CH slots at each end (CH: WO-byte symbols
+    // per chunk; WO <= W stages in no more bytes than W)
+    return (uint32_t)tile_syms(W, B) + 2 * kRunNodes * 2 * (16 / WO);
 }
 
 // LDS bytes of one wave of a level pass: staging of the split (zeros at
@@ -567,7 +569,8 @@ __host__ __device__ constexpr uint32_t level_wave_bytes() {
     constexpr uint32_t dense = (kCopy ? 2u : 1u) * (uint32_t)tile_syms(W, B) * W;
     constexpr uint32_t plain = split > counters ? split : counters;
     constexpr uint32_t m1 = split > multi ? split : multi;
-    return M ? (m1 > dense ? m1 : dense) : plain;
+    constexpr uint32_t m2 = m1 > dense ? m1 : dense;
+    return M ? (m2 > counters ? m2 : counters) : plain;  // (M: the direct path takes tiles over two anchors)
 }
 
 // Split of a tile whose symbols span nodes vf..vl (fewer than kRunNodes):
@@ -580,18 +583,18 @@ __host__ __device__ constexpr uint32_t level_wave_bytes() {
 // single-node case.  Runs are staged in LDS at their destination's 16-byte
 // phase and written out in aligned chunks; next-level ones are counted per
 // chunk.
-template <int W, int B>
+template <int W, int B, int WO>
 __device__ __forceinline__ void stage_multi(const LevelArgs &a, const uint4 (&raw)[B / 16],
                                             typename MaskT<B / W>::T mb, int nval, uint32_t lr1, uint32_t agg,
                                             unsigned long long prefix, uint64_t base, uint64_t nvalid, uint32_t vf,
-                                            uint32_t vl, uint32_t nsh, uint8_t *s_wave,
-                                            typename ElemT<W>::T *tout, bool counting, uint32_t sh2,
+                                            uint32_t vl, uint32_t nsh, uint32_t nbase, uint8_t *s_wave,
+                                            typename ElemT<WO>::T *tout, bool counting, uint32_t sh2,
                                             unsigned long long *ones_next) {
-    typedef typename ElemT<W>::T T;
+    typedef typename ElemT<WO>::T T;  // staged and written symbols
     constexpr int E = B / W;
-    constexpr uint32_t CH = 16 / W;
+    constexpr uint32_t CH = 16 / WO;
     constexpr uint64_t TILE = tile_syms(W, B);
-    constexpr uint32_t kStage = multi_stage_elems<W, B>();
+    constexpr uint32_t kStage = multi_stage_elems<W, B, WO>();
     const int lane = threadIdx.x & 63;
     MultiTables *tb = reinterpret_cast<MultiTables *>(s_wave);
     T *s_stage = reinterpret_cast<T *>(s_wave + kMultiTablesBytes);
@@ -604,12 +607,12 @@ __device__ __forceinline__ void stage_multi(const LevelArgs &a, const uint4 (&ra
     wave_sync();
     // first symbol of every node present in the tile
     {
-        uint32_t vprev = wave_prev_lane((raw_elem<W, B>(raw, E - 1) & a.symmask) >> nsh, 0xFFFFFFFFu);
+        uint32_t vprev = wave_prev_lane(nbase + ((raw_elem<W, B>(raw, E - 1) & a.symmask) >> nsh), 0xFFFFFFFFu);
         uint32_t r = lr1;
 #pragma unroll
         for (int k = 0; k < E; k++) {
             if (k < nval) {
-                const uint32_t v = (raw_elem<W, B>(raw, k) & a.symmask) >> nsh;
+                const uint32_t v = nbase + ((raw_elem<W, B>(raw, k) & a.symmask) >> nsh);
                 if (v != vprev && v - vf < span) tb->key[v - vf] = (((uint32_t)lane * E + k) << 16) | r;
                 vprev = v;
                 r += (uint32_t)(mb >> k) & 1u;
@@ -663,7 +666,7 @@ __device__ __forceinline__ void stage_multi(const LevelArgs &a, const uint4 (&ra
         for (int k = 0; k < E; k++) {
             if (k < nval) {
                 const uint32_t x = raw_elem<W, B>(raw, k) & a.symmask;
-                const uint32_t j = (x >> nsh) - vf;
+                const uint32_t j = nbase + (x >> nsh) - vf;
                 const uint32_t b = (uint32_t)(mb >> k) & 1u;
                 if (j != jc && j < span) {
                     jc = j;
@@ -711,7 +714,7 @@ __device__ __forceinline__ void stage_multi(const LevelArgs &a, const uint4 (&ra
         const uint4 v = *reinterpret_cast<const uint4 *>(&s_stage[s]);
         const unsigned long long gfirst = g + (s - st);
         *reinterpret_cast<uint4 *>(tout + gfirst) = v;
-        add_ones(lo, gfirst, counting ? chunk_bit_count<W>(v, sh2) : 0u);
+        add_ones(lo, gfirst, counting ? chunk_bit_count<WO>(v, sh2) : 0u);
     }
     {
         const uint32_t run = (uint32_t)lane >> 1;
@@ -729,7 +732,7 @@ __device__ __forceinline__ void stage_multi(const LevelArgs &a, const uint4 (&ra
                 for (int e = 0; e < (int)CH; e++) {
                     const uint32_t q = s + e;
                     if (q >= st && q < st + len && g + (q - st) < a.n_out) {
-                        const uint32_t x = chunk_elem<W>(v, e);
+                        const uint32_t x = chunk_elem<WO>(v, e);
                         tout[g + (q - st)] = (T)x;
                         ones += (x >> sh2) & 1u;
                     }
@@ -764,20 +767,21 @@ __device__ __forceinline__ void stage_multi(const LevelArgs &a, const uint4 (&ra
 // (node, bit, destination-tile parity).  Node starts and their tile ranks
 // travel between lanes as (position << 16 | rank) in a prefix maximum and a
 // suffix minimum.
-template <int W, int B, bool kCopy>
+template <int W, int B, int WO, bool kCopy>
 __device__ __forceinline__ void split_dense(const LevelArgs &a, const uint4 (&raw)[B / 16],
                                             typename MaskT<B / W>::T mb, int nval, uint32_t lr1, uint32_t agg,
                                             unsigned long long prefix, uint64_t base, uint64_t nvalid, uint64_t t,
-                                            uint32_t vf, uint32_t vl, uint32_t nsh, uint8_t *s_wave,
-                                            typename ElemT<W>::T *tout, bool counting, uint32_t sh2,
+                                            uint32_t vf, uint32_t vl, uint32_t nsh, uint32_t nbase, uint8_t *s_wave,
+                                            typename ElemT<WO>::T *tout, bool counting, uint32_t sh2,
                                             unsigned long long *ones_next) {
-    typedef typename ElemT<W>::T T;
+    typedef typename ElemT<W>::T T;    // symbols read
+    typedef typename ElemT<WO>::T TO;  // symbols staged and written
     typedef typename MaskT<B / W>::T Mk;
     constexpr int E = B / W;
-    constexpr uint32_t CH = 16 / W;
+    constexpr uint32_t CH = 16 / WO;
     constexpr uint64_t TILE = tile_syms(W, B);
     const int lane = threadIdx.x & 63;
-    T *s_stage = reinterpret_cast<T *>(s_wave);
+    TO *s_stage = reinterpret_cast<TO *>(s_wave);
     const uint32_t p0 = (uint32_t)lane * E;
     const uint32_t nv = (uint32_t)nvalid;
     // The per-symbol loops run rolled (unrolled, they held too many
@@ -797,11 +801,11 @@ __device__ __forceinline__ void split_dense(const LevelArgs &a, const uint4 (&ra
     // node starts of this lane
     Mk fm = 0;
     {
-        uint32_t vprev = wave_prev_lane((raw_elem<W, B>(raw, E - 1) & a.symmask) >> nsh, 0xFFFFFFFFu);
+        uint32_t vprev = wave_prev_lane(nbase + ((raw_elem<W, B>(raw, E - 1) & a.symmask) >> nsh), 0xFFFFFFFFu);
 #pragma unroll 2
         for (int k = 0; k < E; k++) {
             if (k < nval) {
-                const uint32_t v = ((uint32_t)s_sym[k] & a.symmask) >> nsh;
+                const uint32_t v = nbase + (((uint32_t)s_sym[k] & a.symmask) >> nsh);
                 if (v != vprev) fm |= (Mk)1 << k;
                 vprev = v;
             }
@@ -862,7 +866,7 @@ __device__ __forceinline__ void split_dense(const LevelArgs &a, const uint4 (&ra
     for (int k = 0; k < E; k++) {
         if (k < nval) {
             const uint32_t x = (uint32_t)s_sym[k] & a.symmask;
-            const uint32_t v = x >> nsh;
+            const uint32_t v = nbase + (x >> nsh);
             const uint32_t b = (uint32_t)(mb >> k) & 1u;
             const uint32_t p = p0 + k;
             const bool fl = ((uint64_t)fm >> k) & 1u;
@@ -888,7 +892,7 @@ __device__ __forceinline__ void split_dense(const LevelArgs &a, const uint4 (&ra
             const uint32_t nb = counting ? (x >> sh2) & 1u : 0u;
             if (interior) {
                 const uint32_t dl = b ? pe - (re - r) : p - r + rs;
-                if (dl < TILE) s_stage[dl] = (T)x;
+                if (dl < TILE) s_stage[dl] = (TO)x;
                 c0 += nb & (b ^ 1u);
                 c1 += nb & b;
                 icount += nb;
@@ -897,7 +901,7 @@ __device__ __forceinline__ void split_dense(const LevelArgs &a, const uint4 (&ra
                 const unsigned long long R = prefix + r;
                 const uint64_t dst = b ? zo.y + R : base + p - R + zo.x;
                 if (dst < a.n_out) {
-                    tout[dst] = (T)x;
+                    tout[dst] = (TO)x;
                     const uint32_t key = ((v == vf) ? 0u : 4u) + 2 * b + (uint32_t)((dst / TILE) & 1);
                     if (key < 4) ecl += (unsigned long long)nb << (16 * key);
                     else ech += (unsigned long long)nb << (16 * (key - 4));
@@ -964,16 +968,19 @@ struct SplitRec {
 // One level pass over tile t, run by one wave (each lane B bytes = E = B/W
 // symbols of T_i); s_wave is the wave's own LDS slice.  Single-node tiles
 // leave their next-level counts in *rec; other tiles add theirs directly.
-template <int W, int B, bool kMulti, bool kCopy>
+// T_{i+1} is written with WO-byte symbols (WO = W, or W / 2 where the
+// order narrows).
+template <int W, int B, int WO, bool kMulti, bool kCopy>
 __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8_t *s_wave, SplitRec *rec) {
-    typedef typename ElemT<W>::T T;
+    typedef typename ElemT<WO>::T TO;           // symbols of T_{i+1}
     constexpr int E = B / W;                    // symbols per lane
-    constexpr int CH = 16 / W;                  // symbols per 16-byte chunk
+    constexpr int CH = 16 / WO;                 // output symbols per 16-byte chunk
     constexpr uint64_t TILE = tile_syms(W, B);  // 64 * E
     static_assert(TILE < 65536, "per-tile counts travel in 16-bit fields");
+    static_assert(WO == W || (2 * WO == W && !kMulti), "a narrowing pass halves the width, without the staged paths");
     typedef typename MaskT<E>::T M;
     const int lane = threadIdx.x & 63;
-    T *s_stage = reinterpret_cast<T *>(s_wave);
+    TO *s_stage = reinterpret_cast<TO *>(s_wave);
     uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_wave);
     uint32_t *s_tix = s_cnt + 4 * kNodeCap;
 
@@ -1063,11 +1070,30 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
     const bool fold = (W == 1) && !kMulti && bnext != nullptr;
     if (a.tout == nullptr && !fold) return;  // last level: no next order, no counts
 
+    TO *tout = reinterpret_cast<TO *>(a.tout);
+    const bool counting = a.tile_ones_next != nullptr;
+    const uint32_t sh2 = sh - 1;  // bit of the next level (when counting)
+    // (slot counts are powers of two)
+    unsigned long long *ones_next = counting ? a.ones_next + (t & (a.slots_next - 1)) * a.nodes_next : nullptr;
+
+    // narrowed T_i: a node's high bits come from the anchor holding the
+    // position (every symbol of the tile has the first one unless the tile
+    // holds two or more anchors: then it takes the direct split, which
+    // follows the anchors symbol by symbol)
+    uint2 anc = make_uint2(0u, 0u);
+    uint32_t asw = 0;  // node bits below the anchor, carried by the symbol
+    if (a.tile_anc) {
+        anc = a.tile_anc[t];
+        asw = 8u * W - nsh;
+    }
+    const bool straddle = anc.x != anc.y;
+    const uint32_t nbase = anc.x << asw;
+
     // node span of the tile (T_i is sorted by node)
     const bool full = (nvalid == TILE);  // every tile but a ragged last one
     // (a wavelet matrix has one node per level: every tile is single-node)
     const uint32_t vf = a.matrix ? 0u :
-        (uint32_t)__builtin_amdgcn_readlane((int)((raw_elem<W, B>(raw, 0) & a.symmask) >> nsh), 0);
+        nbase + (uint32_t)__builtin_amdgcn_readlane((int)((raw_elem<W, B>(raw, 0) & a.symmask) >> nsh), 0);
     uint32_t vl;
     if (full) {
         vl = (uint32_t)__builtin_amdgcn_readlane((int)((raw_elem<W, B>(raw, E - 1) & a.symmask) >> nsh), 63);
@@ -1079,14 +1105,8 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         for (int k = 0; k < E; k++) xv = (k == kl) ? raw_elem<W, B>(raw, k) : xv;
         vl = (uint32_t)__builtin_amdgcn_readlane((int)((xv & a.symmask) >> nsh), (int)(last / E));
     }
-    vl = a.matrix ? 0u : __builtin_amdgcn_readfirstlane(vl);
-
-    T *tout = reinterpret_cast<T *>(a.tout);
-    const bool counting = a.tile_ones_next != nullptr;
-    const uint32_t sh2 = sh - 1;  // bit of the next level (when counting)
-    // (slot counts are powers of two)
-    unsigned long long *ones_next = counting ? a.ones_next + (t & (a.slots_next - 1)) * a.nodes_next : nullptr;
-    if (vf == vl) {
+    vl = a.matrix ? 0u : (anc.y << asw) + __builtin_amdgcn_readfirstlane(vl);
+    if (vf == vl) {  // (never for a tile over two anchors)
         // Single node: zeros keep their order at g0.., ones at g1...
         const ulonglong2 zo = a.zo[vf];
         const uint64_t Z = nvalid - agg, O = agg;
@@ -1097,8 +1117,8 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         const uint32_t a1 = r1 + (uint32_t)(g1 % CH);
         const uint32_t zc = a0 + (uint32_t)lane * E - lr1;  // first zero slot of this lane
         const uint32_t oc = a1 + lr1;                       // first one slot of this lane
-        if (full) stage_split<W, B, true>(s_stage, raw, ms, zc, oc, nval);
-        else stage_split<W, B, false>(s_stage, raw, ms, zc, oc, nval);
+        if (full) stage_split<W, B, WO, true>(s_stage, raw, ms, zc, oc, nval);
+        else stage_split<W, B, WO, false>(s_stage, raw, ms, zc, oc, nval);
         wave_sync();
         // Write the two runs out (zeros at slots [a0, a0+Z) -> g0.., ones at
         // [a1, a1+O) -> g1..); the slot and destination phases agree, so
@@ -1109,7 +1129,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         // per-symbol loop while the others wait.  A run holds at most TILE
         // symbols, so it touches at most two consecutive destination tiles:
         // next-level ones are counted per (run, tile).
-        const uint32_t lowbits = (W == 1) ? 0x01010101u : (W == 2) ? 0x00010001u : 1u;
+        const uint32_t lowbits = (WO == 1) ? 0x01010101u : (WO == 2) ? 0x00010001u : 1u;
         const uint32_t mk = counting ? lowbits << sh2 : 0u;  // next-level bit of every symbol
         uint32_t cnt[4] = {0u, 0u, 0u, 0u};                   // (run, destination-tile parity)
         uint32_t lo_r[2], len_r[2], edge_r[2][2];
@@ -1171,7 +1191,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
                 const uint64_t d = gb + s;
                 if (s >= lo && s < lo + len && d < a.n_out) {
                     const uint32_t x = (uint32_t)s_stage[s];
-                    tout[d] = (T)x;  // (folded: read back by the stitch)
+                    tout[d] = (TO)x;  // (folded: read back by the stitch)
                     one = (x >> sh2) & 1u;
                     second = c >= cs;
                     if (fold && e == 0) own = d >> 4;
@@ -1208,16 +1228,16 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         return;
     }
 
-    if (kMulti && vl - vf < kRunNodes) {
-        stage_multi<W, B>(a, raw, mb, nval, lr1, agg, prefix, base, nvalid, vf, vl, nsh, s_wave, tout, counting, sh2,
-                          ones_next);
-        return;
-    }
-
-    if (kMulti) {
-        split_dense<W, B, kCopy>(a, raw, mb, nval, lr1, agg, prefix, base, nvalid, t, vf, vl, nsh, s_wave, tout, counting,
-                          sh2, ones_next);
-        return;
+    if constexpr (kMulti) {
+        if (straddle) {
+            // (the direct split below)
+        } else if (vl - vf < kRunNodes)
+            stage_multi<W, B, WO>(a, raw, mb, nval, lr1, agg, prefix, base, nvalid, vf, vl, nsh, nbase, s_wave, tout,
+                                  counting, sh2, ones_next);
+        else
+            split_dense<W, B, WO, kCopy>(a, raw, mb, nval, lr1, agg, prefix, base, nvalid, t, vf, vl, nsh, nbase,
+                                         s_wave, tout, counting, sh2, ones_next);
+        if (!straddle) return;
     }
 
     // Many nodes: every symbol goes straight to its destination.
@@ -1235,25 +1255,46 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         a.fold_own[2 * t] = ~0ull;
         a.fold_own[2 * t + 1] = ~0ull;
     }
+    // narrowed, over two anchors: the anchor of the lane's first symbol (the
+    // last one in [anc.x, anc.y] whose node starts at or before it), then
+    // the next anchor's start; a symbol at or past it searches again
+    auto find_anchor = [&](uint32_t lo, uint32_t hi, uint64_t p) {
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo + 1) / 2;
+            if (a.anc_start[mid] <= p) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    };
+    uint32_t cur = anc.x;
+    uint64_t next = ~0ull;
+    if (straddle) {
+        cur = find_anchor(anc.x, anc.y, pos0);
+        next = (cur < anc.y) ? a.anc_start[cur + 1] : ~0ull;
+    }
     // a lane's nodes never decrease (T_i is sorted by node): its node table
     // entry is loaded again only where the node changes, not per symbol
-    uint32_t cv = (raw_elem<W, B>(raw, 0) & a.symmask) >> nsh;
+    uint32_t cv = (cur << asw) + ((raw_elem<W, B>(raw, 0) & a.symmask) >> nsh);
     ulonglong2 zo = a.zo[nval > 0 ? cv : vf];
 #pragma unroll
     for (int k = 0; k < E; k++) {
         if (k < nval) {
+            const uint64_t p = pos0 + k;
+            if (p >= next) {
+                cur = find_anchor(cur + 1, anc.y, p);
+                next = (cur < anc.y) ? a.anc_start[cur + 1] : ~0ull;
+            }
             const uint32_t x = raw_elem<W, B>(raw, k) & a.symmask;
-            const uint32_t v = x >> nsh;
+            const uint32_t v = (cur << asw) + (x >> nsh);
             if (v != cv) {
                 cv = v;
                 zo = a.zo[v];
             }
-            const uint64_t p = pos0 + k;
             const uint32_t b = (uint32_t)(mb >> k) & 1u;
             const uint64_t dst = b ? zo.y + r1 : p - r1 + zo.x;
             r1 += b;
             if (dst < a.n_out) {
-                tout[dst] = (T)x;
+                tout[dst] = (TO)x;
                 nown += (fold && (dst & 15) == 0) ? 1u : 0u;
                 if (counting && ((x >> sh2) & 1u)) {
                     const uint64_t dt = dst / TILE;
@@ -1279,12 +1320,14 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         at = (uint32_t)__builtin_amdgcn_readlane((int)at, 0) + incl - nown;
         if (lane == 0 && (uint64_t)at + tot > a.fold_ovf_cap && tot) atomicOr(a.fold_status, 2u);
         r1 = r_lane;
-        cv = (raw_elem<W, B>(raw, 0) & a.symmask) >> nsh;
+        // (a folded pass reads 1-byte input symbols, never a narrowed order:
+        // nbase is 0 and no tile holds two anchors)
+        cv = nbase + ((raw_elem<W, B>(raw, 0) & a.symmask) >> nsh);
         zo = a.zo[nval > 0 ? cv : vf];
 #pragma unroll
         for (int k = 0; k < E; k++) {
             if (k < nval && nown) {
-                const uint32_t v = (raw_elem<W, B>(raw, k) & a.symmask) >> nsh;
+                const uint32_t v = nbase + ((raw_elem<W, B>(raw, k) & a.symmask) >> nsh);
                 if (v != cv) {
                     cv = v;
                     zo = a.zo[v];
@@ -1350,8 +1393,8 @@ __device__ __forceinline__ void flush_split_recs(const LevelArgs &a, const Split
     }
 }
 
-template <int W, int B, bool M>
-__global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
+template <int W, int B, int WO, bool M>
+__device__ __forceinline__ void level_kernel_body(const LevelArgs &a) {
     constexpr bool kCopy = dense_lds_copy<W, B>();
     __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W, B, M, kCopy>()];
     __shared__ SplitRec s_rec[kWaves];
@@ -1359,8 +1402,40 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
     const uint64_t t0 = (uint64_t)blockIdx.x * kWaves;
     const uint64_t t = t0 + wv;
     if ((threadIdx.x & 63) < 4) s_rec[wv].cnt[threadIdx.x & 63] = 0;
-    if (t < a.ntiles) level_tile<W, B, M, kCopy>(a, t, s_all + wv * level_wave_bytes<W, B, M, kCopy>(), &s_rec[wv]);
+    if (t < a.ntiles)
+        level_tile<W, B, WO, M, kCopy>(a, t, s_all + wv * level_wave_bytes<W, B, M, kCopy>(), &s_rec[wv]);
     flush_split_recs(a, s_rec, t0);
+}
+
+template <int W, int B, bool M>
+__global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
+    level_kernel_body<W, B, W, M>(a);
+}
+
+// A narrowing level pass: T_{i+1} keeps the low W / 2 bytes of each symbol.
+template <int W, int B>
+__global__ __launch_bounds__(kThreads) void k_level_narrow(LevelArgs a) {
+    level_kernel_body<W, B, W / 2, false>(a);
+}
+
+// Anchors of every tile: one thread per tile, binary search over the anchor
+// level's node starts (the node holding p is the last one starting at or
+// before p: empty nodes start where the next one does).
+__global__ __launch_bounds__(kThreads) void k_tile_anchor(AnchorArgs a) {
+    const uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (t >= a.ntiles) return;
+    auto find = [&](uint64_t p) {
+        uint64_t lo = 0, hi = a.nodes - 1;
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo + 1) / 2;
+            if (a.start[mid] <= p) lo = mid;
+            else hi = mid - 1;
+        }
+        return (uint32_t)lo;
+    };
+    const uint64_t p0 = t * a.tile;
+    const uint64_t p1 = (p0 + a.tile < a.n ? p0 + a.tile : a.n) - 1;
+    a.out[t] = make_uint2(find(p0), find(p1));
 }
 
 // ------------------------------------------------------------ batched ---
@@ -1403,6 +1478,8 @@ __device__ __forceinline__ LevelArgs job_level(const BatchJob &j, uint32_t i) {
     a.fold_ovf_n = nullptr;
     a.fold_ovf_cap = 0;
     a.fold_status = nullptr;
+    a.anc_start = nullptr;
+    a.tile_anc = nullptr;
     return a;
 }
 
@@ -1529,7 +1606,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_level(BatchClass c, uint32_t
     const LevelArgs a = job_level(j, level);
     if ((threadIdx.x & 63) < 4) s_rec[wv].cnt[threadIdx.x & 63] = 0;
     if (t0 + wv < j.ntiles)
-        level_tile<W, B, M, true>(a, t0 + wv, s_all + wv * level_wave_bytes<W, B, M, true>(), &s_rec[wv]);
+        level_tile<W, B, W, M, true>(a, t0 + wv, s_all + wv * level_wave_bytes<W, B, M, true>(), &s_rec[wv]);
     flush_split_recs(a, s_rec, t0);
 }
 
@@ -1740,9 +1817,27 @@ hipError_t launch_plan(const PlanArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_level(const LevelArgs &a, uint32_t width, uint32_t lane_bytes, bool multi, hipStream_t s) {
+hipError_t launch_level(const LevelArgs &a, uint32_t width, uint32_t lane_bytes, bool multi, uint32_t out_width,
+                        hipStream_t s) {
     const dim3 g((uint32_t)ceil_div(a.ntiles, kWaves));
-    WT_LAUNCH_WBM(k_level, width, lane_bytes, multi, g, s, a);
+    if (out_width == width) {
+        WT_LAUNCH_WBM(k_level, width, lane_bytes, multi, g, s, a);
+        return hipGetLastError();
+    }
+    if (multi || 2 * out_width != width) return hipErrorInvalidValue;
+    switch (width * 1000 + lane_bytes) {
+        case 4064: hipLaunchKernelGGL((k_level_narrow<4, 64>), g, dim3(kThreads), 0, s, a); break;
+        case 4128: hipLaunchKernelGGL((k_level_narrow<4, 128>), g, dim3(kThreads), 0, s, a); break;
+        case 2064: hipLaunchKernelGGL((k_level_narrow<2, 64>), g, dim3(kThreads), 0, s, a); break;
+        case 2128: hipLaunchKernelGGL((k_level_narrow<2, 128>), g, dim3(kThreads), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_anchor(const AnchorArgs &a, hipStream_t s) {
+    if (a.ntiles == 0 || a.nodes == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_anchor, dim3((uint32_t)ceil_div(a.ntiles, kThreads)), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 

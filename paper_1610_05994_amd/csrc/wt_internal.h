@@ -66,6 +66,8 @@ static inline uint32_t levels_for(uint32_t sigma) {
 }
 
 // Byte layout of one tree (in caller memory) and of one build's workspace.
+constexpr uint32_t kMaxTreeLevels = 24;  // lg WT_MAX_SIGMA
+
 struct Layout {
     uint64_t n;
     uint32_t sigma, width, levels, lane_bytes;
@@ -100,6 +102,17 @@ struct Layout {
     // folded last level (u8): the record count (inside the control area),
     // two owner records per tile, and the direct path's records
     uint64_t ws_fold_cnt, ws_fold_own, ws_fold_ovf, fold_ovf_cap;
+    // Narrowed symbol orders (single binary-tree builds of 2- and 4-byte
+    // symbols): T_i keeps only the low 8 tw[i] bits of every symbol, which
+    // hold the bits of the levels still to come.  The node of a symbol then
+    // takes its high bits from the position: the anchor level of a width w
+    // is levels - 8w, and the node of the anchor level holding a position
+    // (its start table is that level's) gives them; ws_tanc[w - 1] holds, per
+    // tile, the anchor nodes of its first and last position.
+    uint32_t narrow;                    // some T_i is narrower than the input
+    uint8_t tw[kMaxTreeLevels + 1];     // bytes per symbol of T_i
+    uint32_t anc_level[2];              // anchor level of widths 1 and 2 (0: none)
+    uint64_t ws_tanc[2];
     uint64_t work_bytes;
 };
 
@@ -163,7 +176,23 @@ struct LevelArgs {
     unsigned int *fold_ovf_n;
     uint64_t fold_ovf_cap;
     uint32_t *fold_status;            // bit 1 set if fold_ovf would overflow (never, by its sizing)
+    // narrowed T_i (its symbols' low 8W bits, W the pass's width, fewer bits
+    // than the levels; symmask keeps those bits): the node of a symbol x at
+    // position p is (anchor(p) << (8W - nsh)) | (x >> nsh), anchor(p) the
+    // node of level levels - 8W holding p (node starts anc_start); tile_anc
+    // gives every tile's first and last anchor.  Null otherwise.
+    const uint64_t *anc_start;
+    const uint2 *tile_anc;
 };
+
+// Anchor nodes of every tile (narrowed orders): out[t] = the nodes of the
+// anchor level holding tile t's first and last position.
+struct AnchorArgs {
+    const uint64_t *start;            // the anchor level's node starts (nodes + 1)
+    uint64_t nodes, n, tile, ntiles;
+    uint2 *out;
+};
+hipError_t launch_tile_anchor(const AnchorArgs &a, hipStream_t s);
 
 // The granules of a folded last level that the pass recorded: one thread
 // per record reads the granule's 16 symbols from T_{l-1} and writes its 16
@@ -280,7 +309,14 @@ hipError_t launch_zero(void *p, uint64_t bytes, uint32_t *tree_status, uint64_t 
 hipError_t launch_ingest(const IngestArgs &a, uint32_t width, uint32_t lane_bytes, hipStream_t s);
 hipError_t launch_prep(const PrepArgs &a, hipStream_t s);  // k_supsum, then k_prep
 hipError_t launch_plan(const PlanArgs &a, hipStream_t s);
-hipError_t launch_level(const LevelArgs &a, uint32_t width, uint32_t lane_bytes, bool multi, hipStream_t s);
+// out_width: bytes per symbol of T_{i+1}: width, or width / 2 (a narrowing
+// pass; lane_bytes 64 or 128, never multi)
+hipError_t launch_level(const LevelArgs &a, uint32_t width, uint32_t lane_bytes, bool multi, uint32_t out_width,
+                        hipStream_t s);
+// Whether a narrowing pass exists for this width and lane size.
+__host__ __device__ constexpr bool narrowing_pass(uint32_t width, uint32_t lane_bytes) {
+    return (width == 4 || width == 2) && (lane_bytes == 64 || lane_bytes == 128);
+}
 // Level passes take the staged split of tiles spanning a few nodes where the
 // average node is shorter than this many tiles.
 constexpr uint64_t kMultiAvgTiles = 8;

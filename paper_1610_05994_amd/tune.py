@@ -20,6 +20,10 @@ applies ``tune_table.json`` next to this file when it loads the library
 (``WT_TUNE_TABLE`` names another file; an empty value disables it).
 
     python -m paper_1610_05994_amd.tune [--quick] [--out PATH]
+    python -m paper_1610_05994_amd.tune --modes 0 --widths 2 4 --merge
+
+(``--merge`` measures only the given modes and widths and keeps the other
+points of the existing table.)
 """
 from __future__ import annotations
 
@@ -35,7 +39,7 @@ TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_tabl
 # representative depths per width (u8 text / byte alphabets, u16 mid-size
 # alphabets, u32 large alphabets) and lengths from short to long
 GRID_LEVELS = {1: (2, 5, 8), 2: (6, 12, 16), 4: (12, 20, 24)}
-GRID_LG_N = (10, 12, 14, 16, 18, 20, 22, 24, 26)
+GRID_LG_N = (10, 12, 14, 16, 18, 20, 22, 24, 26, 28)
 BATCH_SYMBOLS = 1 << 24   # symbols per timed batch in mode 1
 BATCH_MAX = 2048
 BATCH_WORK_CAP = 8 << 30  # workspace bytes of one timed batch
@@ -153,16 +157,19 @@ def _batch_count(n: int, sigma: int, width: int, levels: int, lg_n: int) -> int:
     return max(1, min(cnt, BATCH_WORK_CAP // ws1))
 
 
-def tune(quick: bool = False, reps: int = 5, seed: int = 1, log=print):
-    """Measure every geometry over the grid; returns the table dict."""
+def tune(quick: bool = False, reps: int = 5, seed: int = 1, log=print, modes=(0, 1), widths=(1, 2, 4)):
+    """Measure every geometry over the grid (of the given modes and widths);
+    returns the table dict."""
     import torch
 
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed)
     lg_ns = GRID_LG_N[::2] if quick else GRID_LG_N
     entries = []
-    for mode in (0, 1):
+    for mode in modes:
         for width, levels_list in GRID_LEVELS.items():
+            if width not in widths:
+                continue
             for levels in levels_list:
                 sigma = 1 << levels
                 for lg_n in lg_ns:
@@ -254,9 +261,19 @@ def main():
     ap.add_argument("--quick", action="store_true", help="every other length of the grid")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=TABLE_PATH)
+    ap.add_argument("--modes", type=int, nargs="+", default=[0, 1], choices=[0, 1])
+    ap.add_argument("--widths", type=int, nargs="+", default=[1, 2, 4], choices=[1, 2, 4])
+    ap.add_argument("--merge", action="store_true",
+                    help="replace only the measured (mode, width) points of the table at --out")
     args = ap.parse_args()
     os.environ["WT_TUNE_TABLE"] = ""      # measure from the defaults
-    table = tune(quick=args.quick, reps=args.reps)
+    table = tune(quick=args.quick, reps=args.reps, modes=tuple(args.modes), widths=tuple(args.widths))
+    if args.merge and os.path.exists(args.out):
+        with open(args.out) as f:
+            old = json.load(f)
+        done = {(e["mode"], e["width"]) for e in table["entries"]}
+        table["entries"] = [e for e in old.get("entries", []) if (e["mode"], e["width"]) not in done] + \
+            table["entries"]
     with open(args.out, "w") as f:
         json.dump(table, f, indent=1)
     print("wrote %s (%d points)" % (args.out, len(table["entries"])))
