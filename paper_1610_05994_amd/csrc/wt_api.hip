@@ -133,8 +133,10 @@ constexpr uint64_t kNarrowMinN = 1ull << 18;
 // split: at most one tile in kAnchorTiles may); a width whose 8w bits hold
 // fewer bits than the levels gets the per-tile anchor table of level
 // levels - 8w.
+// A wavelet matrix (one node per level) needs no anchors: its orders narrow
+// wherever the widths allow.
 constexpr uint64_t kAnchorTiles = 8;
-static void plan_narrowing(Layout *L) {
+static void narrow_widths(Layout *L, bool matrix) {
     const uint32_t l = L->levels;
     L->narrow = 0;
     for (uint32_t i = 0; i <= kMaxTreeLevels; i++) L->tw[i] = (uint8_t)L->width;
@@ -143,12 +145,17 @@ static void plan_narrowing(Layout *L) {
     for (uint32_t i = 0; i + 1 < l; i++) {
         const uint32_t w = L->tw[i];
         const uint32_t half_bits = 8 * (w / 2);
-        const bool few_anchors = half_bits >= l || (kAnchorTiles << (l - half_bits)) <= L->ntiles;
+        const bool few_anchors = matrix || half_bits >= l || (kAnchorTiles << (l - half_bits)) <= L->ntiles;
         const bool halve = w >= 2 && bytes_for(l - (i + 1)) <= w / 2 && narrowing_pass(w, E * w) && few_anchors;
         L->tw[i + 1] = (uint8_t)(halve ? w / 2 : w);
         if (halve) L->narrow = 1;
     }
     for (uint32_t i = l; i <= kMaxTreeLevels; i++) L->tw[i] = L->tw[l - 1];
+}
+
+static void plan_narrowing(Layout *L) {
+    const uint32_t l = L->levels;
+    narrow_widths(L, false);
     if (!L->narrow) return;
     for (uint32_t w = 1; w <= 2; w++) {
         bool used = false;
@@ -357,7 +364,7 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
     const uint32_t lrun = fold ? l - 1 : l;  // passes to run
     // narrowed orders: T_i has tw[i] bytes per symbol, the same E symbols
     // per lane (so the same tiles) at every width
-    const bool narrow = L.narrow && !partial && !L.matrix && L.arity != 4;
+    const bool narrow = L.narrow && !partial && L.arity != 4;
     const uint32_t E = L.lane_bytes / L.width;
     bool anc_ready[2] = {false, false};
     for (uint32_t i = 0; i < lrun; i++) {
@@ -397,7 +404,7 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
 
         const uint32_t w = narrow ? L.tw[i] : L.width;
         const uint32_t wo = (narrow && i + 1 < l) ? L.tw[i + 1] : w;
-        const bool anchored = narrow && w < L.width && 8 * w < l;
+        const bool anchored = narrow && !L.matrix && w < L.width && 8 * w < l;
         if (anchored && !anc_ready[w - 1]) {
             // the anchor level's node starts exist since that level's prep
             AnchorArgs an;
@@ -440,7 +447,7 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         a.levels = l;
         a.level = i;
         // (a narrowed symbol keeps its low 8w bits only)
-        a.symmask = (uint32_t)((1ull << (anchored ? 8 * w : l)) - 1);
+        a.symmask = (uint32_t)((1ull << (8 * w < l ? 8 * w : l)) - 1);
         a.anc_start = anchored ? start + start_offset(L.anc_level[w - 1]) : nullptr;
         a.tile_anc = anchored ? reinterpret_cast<const uint2 *>(work + L.ws_tanc[w - 1]) : nullptr;
         a.matrix = L.matrix;
@@ -1346,6 +1353,7 @@ static int build_one(const void *d_S, const wt_desc *desc, void *d_tree, uint64_
     Layout L;
     make_layout(desc->n, desc->sigma, desc->width, false, &L);
     L.matrix = matrix;
+    if (matrix) narrow_widths(&L, true);  // (the footprint's workspace still holds it)
     if (tree_bytes < L.tree_bytes || work_bytes < L.work_bytes) return WT_ENOMEM;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     wt_tree *h = new_handle(L, d_tree, st);

@@ -124,3 +124,24 @@ def test_narrowed_large_clustered(restore_table):
     _force(128)
     S = wtgen.gauss_mix((1 << 26) + 4099, 1 << 20, 74)
     _check(S, 1 << 20, "u32-gauss-2^26@128")
+
+
+@pytest.mark.parametrize("lane_bytes", [64, 128])
+def test_narrowed_wavelet_matrix(lane_bytes, restore_table):
+    # a wavelet matrix has one node per level: its orders narrow with no
+    # anchors, at any length above the threshold
+    import torch
+    _, wt = _mods()
+    _force(lane_bytes)
+    for tag, S, sigma in [("u32-gauss-2^20", wtgen.gauss_mix(N0, 1 << 20, 75), 1 << 20),
+                          ("u32-uniform-2^24", wtgen.uniform(N0, 1 << 24, 76, width=4), 1 << 24),
+                          ("u32-uniform-300", wtgen.uniform(N0, 300, 77, width=4), 300),
+                          ("u16-zipf-2^16", wtgen.zipf(N1, 1 << 16, 1.0, 78, width=2), 1 << 16)]:
+        print("narrow matrix %s@%d: n=%d" % (tag, lane_bytes, S.shape[0]), flush=True)
+        t = wt.build(wt.to_device(S, torch.device("cuda:0")), sigma, matrix=True)
+        assert t.status() == wt.WT_OK
+        ref = oracle.build_matrix(S, sigma)
+        assert tc.compare_levels(t.bitmaps(), ref.bitmaps) is None, tag
+        assert tc.compare_levels(t.ranks(), ref.ranks, "rank") is None, tag
+        assert np.array_equal(t.zeros(), ref.zeros), tag
+        t.close()

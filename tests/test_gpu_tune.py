@@ -65,13 +65,18 @@ def test_every_geometry_builds_the_oracle_tree(lane_bytes, restore_table):
 def test_every_geometry_clustered_large_alphabet(lane_bytes, restore_table):
     # Gaussian clusters over 2^20 symbols: deep levels hold tiles of many
     # small nodes next to a few large ones (the few-node and dense split
-    # paths of the staged variant), with a ragged last tile
+    # paths of the staged variant), with a ragged last tile; and the same
+    # for bytes (clusters a few symbols wide over 256, and a steep Zipf),
+    # where 128 lane bytes is no u8 geometry and the default one runs
     _, wt = _mods()
     import torch
     _force(lane_bytes)
-    for k, (n, width) in enumerate([(300_001, 4), (200_003, 2)]):
-        sigma = (1 << 20) if width == 4 else (1 << 16)
-        S = wtgen.gauss_mix(n, sigma, 950 + k, 16, max(1.0, sigma / 512), width)
+    for k, (n, width) in enumerate([(300_001, 4), (200_003, 2), (400_003, 1), (600_011, 1)]):
+        sigma = (1 << 20) if width == 4 else ((1 << 16) if width == 2 else 256)
+        if width == 1 and k == 3:
+            S = wtgen.zipf(n, sigma, 1.6, 950 + k)
+        else:
+            S = wtgen.gauss_mix(n, sigma, 950 + k, 16, max(1.0, sigma / 512), width)
         print("geometry %d clustered: n=%d sigma=%d width=%d" % (lane_bytes, n, sigma, width), flush=True)
         t = wt.build(wt.to_device(S, torch.device("cuda:0")), sigma)
         ref = oracle.build(S, sigma)
