@@ -16,7 +16,6 @@ timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import statistics
@@ -45,19 +44,10 @@ WORKLOADS = {
 
 
 def kernel_source_hash() -> str:
-    """Hash of everything that decides what the build's kernels move: every
-    source under csrc/ (kernels, launch sequences, layouts, the fold decision)
-    and the tuning table (tile geometry)."""
-    h = hashlib.sha256()
-    pkg = os.path.join(ROOT, "paper_1610_05994_amd")
-    csrc = os.path.join(pkg, "csrc")
-    paths = [os.path.join(csrc, f) for f in sorted(os.listdir(csrc))] + [os.path.join(pkg, "tune_table.json")]
-    for path in paths:
-        if os.path.isfile(path):
-            h.update(os.path.basename(path).encode())
-            with open(path, "rb") as f:
-                h.update(f.read())
-    return h.hexdigest()[:16]
+    """Hash of the kernel sources and the tuning table (the counter figures in
+    profiles/traffic.json are keyed by it)."""
+    from paper_1610_05994_amd.profiling import kernel_source_hash as h
+    return h()
 
 
 def instrumented_pass(steps, step):
@@ -78,6 +68,18 @@ def instrumented_pass(steps, step):
     recs = wtree.wt_prof_read()
     wtree.wt_prof_enable(False)
     return (t1 - t0) * 1e3 / steps, recs
+
+
+def calib_copy(args, dev):
+    """One plain device copy of --calib-copy-mib MiB: in a counter run, what
+    FETCH_SIZE and WRITE_SIZE read for it scales the kernels' readings."""
+    import torch
+    if args.calib_copy_mib:
+        src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
 
 def copy_reference(dev, stream, mib: int = 256, copies: int = 10, reps: int = 3):
@@ -137,6 +139,12 @@ def load_traffic_entry(workload: str):
     if not ent or ent.get("kernel_hash") != kernel_source_hash():
         return None
     return ent
+
+
+def load_batch_traffic():
+    """HBM bytes per batched build of the batched kernels (counters), or None."""
+    ent = load_traffic_entry("c4")
+    return ent.get("bytes_per_batched_build") if ent else None
 
 
 def load_traffic(workload: str):
@@ -272,6 +280,8 @@ def main() -> int:
                     help="directory to keep the generated input between runs (.npy)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="c4: skip the one-build-call-per-sequence comparison (counter runs)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -373,12 +383,7 @@ def bench_single(args):
     stream = torch.cuda.Stream(device=dev)
     sh = int(stream.cuda_stream)
 
-    if args.calib_copy_mib:
-        src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    calib_copy(args, dev)
 
     build_fn = wtree.wt_build_matrix if args.matrix else (wtree.wt_build_multiary if args.arity == 4 else wtree.wt_build)
     if args.buffered:
@@ -534,6 +539,7 @@ def bench_batch(args) -> dict:
     from paper_1610_05994_amd import wtree
 
     dev = torch.device("cuda:0")
+    calib_copy(args, dev)
     m = int(os.environ.get("WT_BENCH_BATCH", "4096"))
     print("bench: generating %d sequences" % m, file=sys.stderr, flush=True)
     specs = wtgen.batch_specs(m, wtgen.SEED_BASE + 3)
@@ -608,8 +614,10 @@ def bench_batch(args) -> dict:
         assert torch.equal(sym.cpu().to(torch.int64) & 0xFFFFFFFF, want), "batched access mismatch"
     for h in hs:
         wtree.wt_free(h)
-    print("bench: one build call per sequence", file=sys.stderr, flush=True)
-    ms_single = timed(one_by_one, max(1, args.steps // 4), 1)
+    ms_single = None
+    if not getattr(args, "batched_only", False):
+        print("bench: one build call per sequence", file=sys.stderr, flush=True)
+        ms_single = timed(one_by_one, max(1, args.steps // 4), 1)
 
     lvl = [r for r in recs if r["kernel"] in ("batch_level", "batch_small", "batch_mid")]
     lvl_ms = sum(r["ms"] for r in lvl)
@@ -634,12 +642,12 @@ def bench_batch(args) -> dict:
         "data": "synthetic",
         "config": {"workload": "c4: " + WORKLOADS["c4"], "sequences": m, "total_symbols": total},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": load_batch_traffic(),
                      "kernel": "batched build kernels: one-workgroup builds of the short sequences and the "
                                "level phases (supsum + prep + level pass) of the long ones"},
         "compulsory_bytes": {"bytes": qmin, "gbps": qmin_gbps, "frac_of_peak": qmin_gbps / HBM_PEAK_GBPS},
-        "one_call_per_sequence": {"ms": ms_single, "symbols_per_s": total / (ms_single / 1e3),
-                                  "batched_speedup": ms_single / ms_batch},
+        "one_call_per_sequence": None if ms_single is None else {
+            "ms": ms_single, "symbols_per_s": total / (ms_single / 1e3), "batched_speedup": ms_single / ms_batch},
     }
     del dS, trees, work, work1
     return out
