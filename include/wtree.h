@@ -267,6 +267,22 @@ int wt_tree_status(const wt_tree *tree);
 void wt_free(wt_tree *tree);
 
 /*
+ * Write counting, for verification (callers: tests and debugging only).
+ * The library promises that every word of a level bitmap (or 4-ary digit
+ * level) is stored by exactly one writer, with no atomics on the bitmaps.
+ * In the write-counting build of the library (libwtree_check.so, compiled
+ * with WT_WRITE_CHECK), every later store of bitmap or digit words that
+ * falls in [d_base, d_base + bytes) adds one to the 32-bit counter of each
+ * 16-bit granule it covers: d_counts holds bytes / 2 counters, in device
+ * memory the caller owns and clears.  A build kept the promise when every
+ * granule of its bitmaps counts exactly 1, padding words included.  d_counts
+ * null stops the counting.  Call it with no build in flight (it writes a
+ * device variable synchronously).  Returns WT_OK, WT_EINVAL (d_base or
+ * bytes odd, or the product build, which counts nothing) or WT_EDEVICE.
+ */
+int wt_debug_write_counters(void *d_counts, const void *d_base, uint64_t bytes);
+
+/*
  * The one-pointer-per-level representation of Section 2.2 (one n-bit bitmap
  * per level, addressed from a single pointer).  Layout of a built tree:
  * number of levels, device pointer to level 0's

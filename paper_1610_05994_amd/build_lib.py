@@ -9,6 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libwtree.so")
+CHECK_LIB = os.path.join(PKG, "libwtree_check.so")  # the write-counting build (WT_WRITE_CHECK)
 SOURCES = ["wt_build.hip", "wt_small.hip", "wt_query.hip", "wt_buffered.hip", "wt_multiary.hip", "wt_huffman.hip", "wt_quad.hip",
            "wt_api.hip"]
 
@@ -42,15 +43,17 @@ def build_cpu(verbose: bool = False) -> str:
     return CPU_LIB
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, check: bool = False) -> str:
     """Compile every source to an object in parallel (one hipcc per file; each
     file launches only its own kernels, so no relocatable device code is
-    needed), then link the shared library."""
+    needed), then link the shared library.  check: the write-counting build
+    (WT_WRITE_CHECK, libwtree_check.so) instead of the product one."""
     import tempfile
     from concurrent.futures import ThreadPoolExecutor
 
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
-    cflags = [f for f in FLAGS if f != "-shared"]
+    cflags = [f for f in FLAGS if f != "-shared"] + (["-DWT_WRITE_CHECK"] if check else [])
+    out = CHECK_LIB if check else LIB
     with tempfile.TemporaryDirectory(prefix="wtree_build_") as tmpdir:
         objs, cmds = [], []
         for s in SOURCES:
@@ -67,15 +70,16 @@ def build(verbose: bool = False) -> str:
         with ThreadPoolExecutor(max_workers=workers) as ex:
             for f in [ex.submit(run, c) for c in cmds]:
                 f.result()
-        tmp = LIB + ".tmp%d" % os.getpid()
+        tmp = out + ".tmp%d" % os.getpid()
         link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
         run(link)
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, check=True)
     build_cpu(verbose="-v" in sys.argv)
     print(LIB)
     print(CPU_LIB)

@@ -346,8 +346,9 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
     ia.sigma = L.sigma;
     ia.check = (L.width < 4 && (uint64_t)L.sigma == (1ull << (8 * L.width))) ? 0u : 1u;
     ia.msb = l ? l - 1 : 0;
-    ia.zero_p = fold ? bits_last + L.n / 64 : nullptr;
-    ia.zero_words = fold ? L.words - L.n / 64 : 0;
+    // (folded: the granules wholly past n; the pass and the stitch write the others)
+    ia.zero_g = fold ? reinterpret_cast<uint16_t *>(bits_last) + ceil_div(L.n, 16) : nullptr;
+    ia.zero_granules = fold ? 4 * L.words - ceil_div(L.n, 16) : 0;
     {
         // contiguous tiles per ingest workgroup: ~8192 workgroups
         uint64_t k = kWaves;
@@ -1130,8 +1131,8 @@ static hipError_t enqueue_huffman(const void *S, const wt_desc *desc, const Huff
     ia.sigma = 1u << L;
     ia.check = 0;
     ia.msb = L - 1;
-    ia.zero_p = nullptr;
-    ia.zero_words = 0;
+    ia.zero_g = nullptr;
+    ia.zero_granules = 0;
     {
         uint64_t k = kWaves;
         while (I.ntiles > 8192 * k) k <<= 1;
@@ -1596,6 +1597,22 @@ int wt_build_batch(uint32_t m, const void *const *d_S, const wt_desc *descs, voi
         out[q] = h;
     }
     return WT_OK;
+}
+
+int wt_debug_write_counters(void *d_counts, const void *d_base, uint64_t bytes) {
+    if (((uintptr_t)d_base & 1) || (bytes & 1)) return WT_EINVAL;
+#ifdef WT_WRITE_CHECK
+    uint32_t *c = static_cast<uint32_t *>(d_counts);
+    const uint64_t base = (uint64_t)(uintptr_t)d_base, span = c ? bytes : 0;
+    hipError_t e = write_check_build(c, base, span);
+    if (e == hipSuccess) e = write_check_small(c, base, span);
+    if (e == hipSuccess) e = write_check_buffered(c, base, span);
+    if (e == hipSuccess) e = write_check_quad(c, base, span);
+    return e == hipSuccess ? WT_OK : WT_EDEVICE;
+#else
+    (void)d_counts;
+    return WT_EINVAL;
+#endif
 }
 
 int wt_tree_status(const wt_tree *t) {

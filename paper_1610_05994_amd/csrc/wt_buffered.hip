@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "wt_check.h"
 #include "wt_internal.h"
 
 namespace wt {
@@ -322,7 +323,10 @@ __global__ __launch_bounds__(kMT) void k_merge(MergeArgs a) {
             }
         }
         // words from nw up to the level's padded end are zero
-        if (wi < a.words) a.bits[(uint64_t)i * a.words + wi] = word;
+        if (wi < a.words) {
+            a.bits[(uint64_t)i * a.words + wi] = word;
+            note_write(&a.bits[(uint64_t)i * a.words + wi], 8);
+        }
         words[u] = word;
     }
     // rank directory: block blk = wi / 8 holds words of one u (kMT is a
@@ -408,5 +412,11 @@ hipError_t launch_merge(const MergeArgs &a, hipStream_t s) {
     }
     return err;
 }
+
+#ifdef WT_WRITE_CHECK
+hipError_t write_check_buffered(uint32_t *cnt, uint64_t base, uint64_t bytes) {
+    return set_write_check_here(cnt, base, bytes);
+}
+#endif
 
 }  // namespace wt

@@ -37,6 +37,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "wt_check.h"
 #include "wt_internal.h"
 
 namespace wt {
@@ -258,7 +259,12 @@ __global__ __launch_bounds__(kThreads) void k_ingest(IngestArgs a) {
         if (u < t1) ones_acc += ingest_tile<W, B>(a, u, rb, nb, bad);
     }
     ingest_finish(a, bad, ones_acc, (uint64_t)blockIdx.x * kWaves + wv);
-    if (a.zero_p) zero_words(a.zero_p, a.zero_words);  // (a pass that only reads has write bandwidth to spare)
+    // (a pass that only reads has write bandwidth to spare)
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.zero_granules;
+         k += (uint64_t)gridDim.x * blockDim.x) {
+        a.zero_g[k] = 0;
+        note_write(&a.zero_g[k], 2);
+    }
 }
 
 // ----------------------------------------------------------- node tables --
@@ -1023,7 +1029,10 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         for (int d = 1; d < 64 / E; d++) wd |= (uint64_t)__shfl_down((uint32_t)mb, d, 64) << (d * E);
         if ((lane % (64 / E)) == 0) {
             const uint64_t widx = pos0 / 64;
-            if (widx < a.words) a.bits[widx] = wd;
+            if (widx < a.words) {
+                a.bits[widx] = wd;
+                note_write(&a.bits[widx], 8);
+            }
         }
         // rank directory: entry k = ones before position 512k
         if ((pos0 & 511) == 0) {
@@ -1048,7 +1057,10 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
                 for (int k = 0; k < DPW; k++)
                     wd |= (uint64_t)((raw_elem<W, B>(raw, w * DPW + k) >> a.dsh) & 3u) << (2 * k);
                 const uint64_t widx = pos0 / DPW + w;
-                if (widx < a.dwords) a.digits[widx] = wd;
+                if (widx < a.dwords) {
+                    a.digits[widx] = wd;
+                    note_write(&a.digits[widx], 8);
+                }
             }
         } else {
             uint32_t part = 0;  // 2E <= 32 bits
@@ -1059,7 +1071,10 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
             for (int d = 1; d < DPW / E; d++) wd |= (uint64_t)__shfl_down(part, d, 64) << (d * 2 * E);
             if ((lane % (DPW / E)) == 0) {
                 const uint64_t widx = pos0 / DPW;
-                if (widx < a.dwords) a.digits[widx] = wd;
+                if (widx < a.dwords) {
+                    a.digits[widx] = wd;
+                    note_write(&a.digits[widx], 8);
+                }
             }
         }
     }
@@ -1163,9 +1178,10 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
                 const uint32_t s = c * CH;
                 const uint4 v = *reinterpret_cast<const uint4 *>(&s_stage[s]);
                 if (inside || gb + s + CH <= a.n_out) {
-                    if (fold)  // the granule's 16 bits (gb + s is a multiple of 16)
+                    if (fold) {  // the granule's 16 bits (gb + s is a multiple of 16)
                         bnext[(gb + s) >> 4] = (uint16_t)chunk_bits16(v, sh2);
-                    else
+                        note_write(&bnext[(gb + s) >> 4], 2);
+                    } else
                         *reinterpret_cast<uint4 *>(tout + (gb + s)) = v;
                     const uint32_t ones = __popc(v.x & mk) + __popc(v.y & mk) + __popc(v.z & mk) + __popc(v.w & mk);
                     const bool second = c >= cs;
@@ -1522,8 +1538,8 @@ __device__ __forceinline__ IngestArgs job_ingest(const BatchJob &j) {
     a.sigma = j.sigma;
     a.check = j.check;
     a.msb = j.levels ? j.levels - 1 : 0;
-    a.zero_p = nullptr;
-    a.zero_words = 0;
+    a.zero_g = nullptr;
+    a.zero_granules = 0;
     return a;
 }
 
@@ -1650,6 +1666,7 @@ __global__ __launch_bounds__(kThreads) void k_fold_stitch(StitchArgs a) {
     uint32_t bits = chunk_bits16(v, a.sh);
     if (p + 16 > a.n) bits &= (1u << (uint32_t)(a.n - p)) - 1u;
     a.bits16[g] = (uint16_t)bits;
+    note_write(&a.bits16[g], 2);
 }
 
 // ------------------------------------------------ directory of a bitmap ---
@@ -1872,5 +1889,11 @@ hipError_t launch_batch_level(const BatchClass &c, uint32_t width, uint32_t lane
     if (blocks) WT_LAUNCH_WBM(k_batch_level, width, lane_bytes, multi, dim3((uint32_t)blocks), s, c, level);
     return hipGetLastError();
 }
+
+#ifdef WT_WRITE_CHECK
+hipError_t write_check_build(uint32_t *cnt, uint64_t base, uint64_t bytes) {
+    return set_write_check_here(cnt, base, bytes);
+}
+#endif
 
 }  // namespace wt

@@ -194,6 +194,15 @@ struct AnchorArgs {
 };
 hipError_t launch_tile_anchor(const AnchorArgs &a, hipStream_t s);
 
+// Write-counting debug build: each translation unit that stores bitmap or
+// digit words sets its own copy of the counted span (wt_check.h).
+#ifdef WT_WRITE_CHECK
+hipError_t write_check_build(uint32_t *cnt, uint64_t base, uint64_t bytes);
+hipError_t write_check_small(uint32_t *cnt, uint64_t base, uint64_t bytes);
+hipError_t write_check_buffered(uint32_t *cnt, uint64_t base, uint64_t bytes);
+hipError_t write_check_quad(uint32_t *cnt, uint64_t base, uint64_t bytes);
+#endif
+
 // The granules of a folded last level that the pass recorded: one thread
 // per record reads the granule's 16 symbols from T_{l-1} and writes its 16
 // bits (positions >= n as zero).
@@ -237,8 +246,8 @@ struct IngestArgs {
     uint32_t *tree_status;
     uint64_t n, ntiles, tiles_per_block, slots0;
     uint32_t sigma, check, msb;
-    uint64_t *zero_p;                  // zero_words words cleared on the way (8-byte aligned), or null
-    uint64_t zero_words;
+    uint16_t *zero_g;                  // zero_granules 16-bit granules cleared on the way, or null
+    uint64_t zero_granules;
 };
 
 // Node tables of one level (see k_plan_* and k_prep).

@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "wt_check.h"
 #include "wt_internal.h"
 
 namespace wt {
@@ -129,7 +130,10 @@ __device__ __forceinline__ void quad_tile(const QuadArgs &a, uint64_t t, uint8_t
                 for (int k = 0; k < DPW; k++)
                     wd |= (uint64_t)((raw_elem<W, B>(raw, w * DPW + k) >> shb) & 3u) << (2 * k);
                 const uint64_t widx = pos0 / DPW + w;
-                if (widx < a.dwords) a.digits[widx] = wd;
+                if (widx < a.dwords) {
+                    a.digits[widx] = wd;
+                    note_write(&a.digits[widx], 8);
+                }
             }
         } else {
             uint32_t part = 0;
@@ -140,7 +144,10 @@ __device__ __forceinline__ void quad_tile(const QuadArgs &a, uint64_t t, uint8_t
             for (int d = 1; d < DPW / E; d++) wd |= (uint64_t)__shfl_down(part, d, 64) << (d * 2 * E);
             if ((lane % (DPW / E)) == 0) {
                 const uint64_t widx = pos0 / DPW;
-                if (widx < a.dwords) a.digits[widx] = wd;
+                if (widx < a.dwords) {
+                    a.digits[widx] = wd;
+                    note_write(&a.digits[widx], 8);
+                }
             }
         }
     }
@@ -633,5 +640,11 @@ hipError_t launch_quad_prep(const QuadPrepArgs &p, hipStream_t s) {
     }
     return hipGetLastError();
 }
+
+#ifdef WT_WRITE_CHECK
+hipError_t write_check_quad(uint32_t *cnt, uint64_t base, uint64_t bytes) {
+    return set_write_check_here(cnt, base, bytes);
+}
+#endif
 
 }  // namespace wt

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "wt_check.h"
 #include "wt_internal.h"
 
 namespace wt {
@@ -166,7 +167,10 @@ __device__ void small_levels(const SmallJob &j, typename SElem<W>::T (*s_buf)[CA
 #pragma unroll
             for (int q = 1; q < 64 / E; q++) wd |= (uint64_t)__shfl_down(bm, q, 64) << (q * E);
             const uint32_t widx = p0 / 64;
-            if ((lane % (64 / E)) == 0 && widx < j.words) bits[(uint64_t)i * j.words + widx] = wd;
+            if ((lane % (64 / E)) == 0 && widx < j.words) {
+                bits[(uint64_t)i * j.words + widx] = wd;
+                note_write(&bits[(uint64_t)i * j.words + widx], 8);
+            }
         }
         // rank directory: entry k = ones before min(512k, n); padding zero
         uint64_t *rk = ranks + (uint64_t)i * j.rank_stride;
@@ -277,5 +281,11 @@ hipError_t launch_small_batch(const SmallJob *d_jobs, uint32_t count, uint32_t w
     WT_SMALL_LAUNCH(k_small_batch, width, geom, dim3(count), s, d_jobs);
     return hipGetLastError();
 }
+
+#ifdef WT_WRITE_CHECK
+hipError_t write_check_small(uint32_t *cnt, uint64_t base, uint64_t bytes) {
+    return set_write_check_here(cnt, base, bytes);
+}
+#endif
 
 }  // namespace wt

@@ -16,7 +16,10 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libwtree.so")
+# WT_LIBRARY names another build of the library (e.g. the write-counting
+# build, libwtree_check.so, beside this module)
+LIB_PATH = os.environ.get("WT_LIBRARY") or os.path.join(_PKG, "libwtree.so")
+CHECK_LIB_PATH = os.path.join(_PKG, "libwtree_check.so")
 
 WT_OK, WT_EINVAL, WT_ERANGE, WT_ENOMEM, WT_ENOTFOUND, WT_EDEVICE = range(6)
 WT_MAX_SIGMA = 1 << 24
@@ -27,7 +30,7 @@ EXPORTED = [
     "wt_access", "wt_rank", "wt_select", "wt_query_multi_footprint", "wt_query_multi", "wt_strerror",
     "wt_tune_set", "wt_tune_get", "wt_buffered_footprint", "wt_build_buffered",
     "wt_multiary_footprint", "wt_build_multiary", "wt_multiary_levels",
-    "wt_prof_enable", "wt_prof_read", "wt_build_noalloc",
+    "wt_prof_enable", "wt_prof_read", "wt_build_noalloc", "wt_debug_write_counters",
     "wt_histogram", "wt_huffman_footprint", "wt_build_huffman", "wt_huffman_levels",
 ]
 HUFF_MAX_LEVELS = 24
@@ -67,6 +70,7 @@ def lib():
         "wt_build": ([vp, P(wt_desc), vp, u64, vp, u64, vp, P(vp)], i32),
         "wt_build_matrix": ([vp, P(wt_desc), vp, u64, vp, u64, vp, P(vp)], i32),
         "wt_build_noalloc": ([vp, P(wt_desc), vp, u64, vp], i32),
+        "wt_debug_write_counters": ([vp, vp, u64], i32),
         "wt_histogram": ([vp, P(wt_desc), vp, vp], i32),
         "wt_huffman_footprint": ([vp, P(wt_desc), P(u64), P(u64)], i32),
         "wt_build_huffman": ([vp, P(wt_desc), vp, vp, u64, vp, u64, vp, P(vp)], i32),
@@ -145,6 +149,10 @@ def wt_build(d_S: int, n: int, sigma: int, width: int, d_tree: int, tree_bytes: 
 def wt_build_noalloc(d_S: int, n: int, sigma: int, width: int, d_tree: int, tree_bytes: int, stream: int) -> int:
     d = wt_desc(n, sigma, width)
     return lib().wt_build_noalloc(d_S, ctypes.byref(d), d_tree, tree_bytes, stream)
+
+
+def wt_debug_write_counters(d_counts: int, d_base: int, nbytes: int) -> int:
+    return lib().wt_debug_write_counters(d_counts, d_base, nbytes)
 
 
 def wt_histogram(d_S: int, n: int, sigma: int, width: int, d_counts: int, stream: int) -> int:
@@ -624,9 +632,10 @@ def histogram(S, sigma: int, width: int | None = None, stream=None) -> np.ndarra
     return counts[:sigma].cpu().numpy().view(np.uint64).copy()
 
 
-def build_huffman(S, sigma: int, width: int | None = None, stream=None, counts=None) -> HuffTree:
-    """Huffman-shaped tree of a device tensor S: its histogram on the GPU,
-    then the build from those counts."""
+def build_huffman(S, sigma: int, width: int | None = None, stream=None, counts=None, tree_mem=None,
+                  work_mem=None) -> HuffTree:
+    """Huffman-shaped tree of a device tensor S: its histogram on the GPU
+    (unless the counts are given), then the build from those counts."""
     torch = _torch()
     width = width or S.element_size()
     n = S.numel()
@@ -636,8 +645,8 @@ def build_huffman(S, sigma: int, width: int | None = None, stream=None, counts=N
     rc, tb, wb = wt_huffman_footprint(counts, n, sigma, width)
     if rc != WT_OK:
         raise WtError(rc, "wt_huffman_footprint")
-    tree_mem = _alloc(tb, S.device)
-    work_mem = _alloc(wb, S.device)
+    tree_mem = tree_mem if tree_mem is not None else _alloc(tb, S.device)
+    work_mem = work_mem if work_mem is not None else _alloc(wb, S.device)
     rc, h = wt_build_huffman(S.data_ptr() if n else 0, n, sigma, width, counts, tree_mem.data_ptr(),
                              tree_mem.numel(), work_mem.data_ptr(), work_mem.numel(), int(st.cuda_stream))
     if rc != WT_OK:
