@@ -273,7 +273,8 @@ def main() -> int:
     ap.add_argument("--buffered-source", default="host", choices=["host", "device"])
     ap.add_argument("--cpu-sample-lg", type=int, default=0,
                     help="time the CPU baselines on 2^LG symbols of the workload (0: its full size)")
-    ap.add_argument("--cpu-runs", type=int, default=3)
+    ap.add_argument("--cpu-runs", type=int, default=0,
+                    help="timed runs of each CPU baseline (default: 5, and 3 for the large-alphabet c3)")
     ap.add_argument("--no-extra", action="store_true",
                     help="default line only: skip the c3 and c4 measurements added to it under 'extra'")
     ap.add_argument("--input-cache", default="",
@@ -302,8 +303,9 @@ def main() -> int:
     if not args.no_cpu_baseline:
         lg = args.cpu_sample_lg
         print("bench: CPU oracle baseline on n=2^%s" % (lg if lg else "full"), file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.workload, lg, args.cpu_runs, args.matrix, args.arity)
-        out["cpu_multicore"] = cpu_multicore(args.workload, lg, args.cpu_runs)
+        runs = args.cpu_runs or (3 if args.workload == "c3" else 5)
+        out["cpu_baseline"] = cpu_baseline(args.workload, lg, runs, args.matrix, args.arity)
+        out["cpu_multicore"] = cpu_multicore(args.workload, lg, runs)
     if default and not args.no_extra:
         out["extra"] = extra_workloads(args)
     print(json.dumps(out), flush=True)
