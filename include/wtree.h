@@ -171,7 +171,9 @@ int wt_build_buffered(const void *S, const wt_desc *desc, uint64_t buffer_syms, 
 
 /*
  * Workspace bytes that wt_build_batch needs for the m sequences descs[0..m).
- * Tree memory of sequence q is its own wt_footprint tree_bytes.
+ * Tree memory of sequence q is its own wt_footprint tree_bytes.  (Which
+ * long sequences are built alone depends on the whole batch, so the figure
+ * for a batch is not always at most the sum of its members' figures.)
  */
 int wt_batch_footprint(uint32_t m, const wt_desc *descs, uint64_t *work_bytes);
 
@@ -249,9 +251,15 @@ int wt_build_noalloc(const void *d_S, const wt_desc *desc, void *d_tree, uint64_
  * once, the segments of all of them sharing each launch the way Algorithm
  * dd's segments share the cores.
  * d_S[q], descs[q], d_trees[q] (of tree_bytes[q] bytes) describe sequence q;
- * sequences may mix lengths, alphabets and widths.  out[q] receives the
- * handle of tree q (each released with wt_free).  On error no handle is
- * returned and nothing was enqueued.
+ * sequences may mix lengths, alphabets and widths.  Long sequences, which
+ * fill the device by themselves, are built in the same call as wt_build
+ * would build them, on the same stream: those of at least 2^25 4-byte
+ * symbols, and those of at least 2^25 1-byte or 2^23 2- or 4-byte symbols
+ * that no other sequence of the batch would share batched launches with.
+ * Every tree is the one wt_build produces.  out[q]
+ * receives the handle of tree q (each released with wt_free).  On error no
+ * handle is returned; argument errors (WT_EINVAL, and WT_ENOMEM for short
+ * tree or work memory) are found before anything is enqueued.
  */
 int wt_build_batch(uint32_t m, const void *const *d_S, const wt_desc *descs,
                    void *const *d_trees, const uint64_t *tree_bytes, void *d_work,

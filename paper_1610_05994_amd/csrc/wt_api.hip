@@ -673,11 +673,25 @@ static int batch_class(uint32_t w, uint32_t lb) { return wclass(w) * 3 + (lb == 
 static const uint32_t kClassWidth[kClasses] = {1, 1, 1, 2, 2, 2, 4, 4, 4};
 static const uint32_t kClassLane[kClasses] = {32, 64, 128, 32, 64, 128, 32, 64, 128};
 
+// Long sequences of a batch are built on their own, each as a single build
+// on the batch's stream, where that is faster: the single build brings
+// narrowed orders (2- and 4-byte symbols), the folded last level (1-byte
+// symbols) and per-level tuning, but pays its own chain of launches, which
+// batched sequences share.  So a sequence goes alone
+// - with 4-byte symbols, from 2^25 symbols on (narrowing saves more than
+//   the chain costs), and
+// - from 2^25 symbols of 1 byte or 2^23 of 2 or 4 bytes, when no other
+//   sequence of the batch would share its batched launches (none left in its
+//   class of width and lane geometry), so that it pays a chain either way.
+static const uint32_t kSoloMinLg[3] = {25, 23, 23};
+constexpr uint32_t kSoloSharedMinLg = 25;
+
 struct BatchPlan {
     std::vector<Layout> L;
     // per class (width, lane bytes): sequences by levels, descending
     std::vector<uint32_t> order[kClasses];
     std::vector<uint32_t> small[6];  // per (width class, 64 KB / 160 KB): one-workgroup builds
+    std::vector<uint32_t> solo;      // long sequences, built as single builds
     uint64_t jobs_off, small_off, map_off[kClasses], sup_off[kClasses], slices_off, total;
     std::vector<uint64_t> slice;     // workspace offset of each sequence's slice
     uint64_t blocks[kClasses], sups[kClasses];
@@ -685,17 +699,35 @@ struct BatchPlan {
 
 static int plan_batch(uint32_t m, const wt_desc *descs, BatchPlan *P) {
     P->L.resize(m);
+    std::vector<int> cls(m, -1);
+    uint32_t members[kClasses] = {};
     for (uint32_t q = 0; q < m; q++) {
         int rc = check_desc(&descs[q]);
         if (rc != WT_OK) return rc;
         make_layout(descs[q].n, descs[q].sigma, descs[q].width, true, &P->L[q]);
-        if (P->L[q].small) P->small[wclass(descs[q].width) * 2 + (P->L[q].small == kGeomMid)].push_back(q);
-        else P->order[batch_class(descs[q].width, P->L[q].lane_bytes)].push_back(q);
+        if (P->L[q].small) {
+            P->small[wclass(descs[q].width) * 2 + (P->L[q].small == kGeomMid)].push_back(q);
+            continue;
+        }
+        cls[q] = batch_class(descs[q].width, P->L[q].lane_bytes);
+        if (descs[q].width == 4 && descs[q].n >= (1ull << kSoloSharedMinLg)) cls[q] = -2;  // alone in any case
+        else members[cls[q]]++;
+    }
+    for (uint32_t q = 0; q < m; q++) {
+        if (cls[q] == -1) continue;
+        const bool solo =
+            cls[q] == -2 || (members[cls[q]] == 1 && descs[q].n >= (1ull << kSoloMinLg[wclass(descs[q].width)]));
+        if (solo) {
+            make_layout(descs[q].n, descs[q].sigma, descs[q].width, false, &P->L[q]);
+            P->solo.push_back(q);
+        } else {
+            P->order[cls[q]].push_back(q);
+        }
     }
     uint64_t nsmall = 0;
     for (int c = 0; c < 6; c++) nsmall += P->small[c].size();
     P->jobs_off = 0;
-    uint64_t off = round_up((uint64_t)(m - nsmall) * sizeof(BatchJob), 256);
+    uint64_t off = round_up((uint64_t)(m - nsmall - P->solo.size()) * sizeof(BatchJob), 256);
     P->small_off = off;
     off += round_up(nsmall * sizeof(SmallJob), 256);
     for (int c = 0; c < kClasses; c++) {
@@ -1524,6 +1556,11 @@ int wt_build_batch(uint32_t m, const void *const *d_S, const wt_desc *descs, voi
     if (!sjobs.empty() &&
         hipMemcpyAsync(d_sjobs, sjobs.data(), sjobs.size() * sizeof(SmallJob), hipMemcpyHostToDevice, st) != hipSuccess)
         return WT_EDEVICE;
+    // long sequences: single builds, first in the stream
+    for (uint32_t q : P.solo)
+        if (enqueue_build(d_S[q], P.L[q], reinterpret_cast<uint8_t *>(d_trees[q]), work + P.slice[q], st) !=
+            hipSuccess)
+            return WT_EDEVICE;
     static const uint32_t kWidthOf[3] = {1, 2, 4};
     for (int c = 0; c < 6; c++) {
         const uint32_t cnt = sfirst[c + 1] - sfirst[c];

@@ -289,9 +289,11 @@ class Server:
     def _admit(self):
         """Pick queued requests (FIFO) whose trees and workspace fit.
 
-        The workspace of a batch is at most the sum of its members' solo
-        workspaces, so that sum is what must stay free (contiguously) after
-        the trees are placed."""
+        The sum of the members' solo workspaces must stay free (contiguously)
+        after the trees are placed.  A batch's workspace is usually less than
+        that sum, but not always (which long sequences are built alone depends
+        on the batch): if it does not fit, the last members go back to the
+        head of the queue."""
         picked, descs, tree_offs = [], [], []
         ws_sum = 0
         while self.queue and len(picked) < self.max_batch:
@@ -312,12 +314,18 @@ class Server:
             break                      # wait for running batches to free memory
         if not picked:
             return None
-        rc, ws = wt.wt_batch_footprint(descs)
-        if rc != wt.WT_OK:
-            raise wt.WtError(rc, "wt_batch_footprint")
-        work_off = self.arena.alloc(ws)   # ws <= ws_sum <= the largest free block
-        assert work_off is not None
-        return picked, descs, tree_offs, work_off
+        while True:
+            rc, ws = wt.wt_batch_footprint(descs)
+            if rc != wt.WT_OK:
+                raise wt.WtError(rc, "wt_batch_footprint")
+            work_off = self.arena.alloc(ws)
+            if work_off is not None:
+                return picked, descs, tree_offs, work_off
+            # (one request alone always fits: its solo workspace was checked)
+            assert len(picked) > 1
+            self.arena.free(tree_offs.pop())
+            descs.pop()
+            self.queue.insert(0, picked.pop())
 
     def _launch(self, picked, descs, tree_offs, work_off) -> None:
         torch = self.torch

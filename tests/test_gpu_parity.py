@@ -276,14 +276,72 @@ def test_batch_mixed_widths_and_edge_sequences():
         t.close()
 
 
+def _batch_alone_check(cases, tag):
+    """Builds the cases as one batch; every tree must equal the oracle's and
+    the single build's.  Returns the lengths of the sequences that were
+    built alone (single-build launches in the library's launch records)."""
+    wt = _wt()
+    Ss = []
+    for k, (n, sg, w, kind) in enumerate(cases):
+        if kind == "gauss":
+            Ss.append(wtgen.gauss_mix(n, sg, 2000 + k))
+        else:
+            Ss.append(wtgen.zipf(n, sg, 1.0, 2000 + k, w) if n else np.zeros(0, wtgen.dtype_for(w)))
+    _say("case %s: %d sequences, largest n=%d" % (tag, len(Ss), max(c[0] for c in cases)))
+    dev = [wt.to_device(S, _dev()) for S in Ss]
+    assert wt.wt_prof_enable(True) == wt.WT_OK
+    try:
+        trees = wt.build_batch(dev, [c[1] for c in cases], [c[2] for c in cases])
+        recs = wt.wt_prof_read()
+    finally:
+        wt.wt_prof_enable(False)
+    alone = sorted(r["n"] for r in recs if r["kernel"] == "ingest")
+    for (n, sg, w, _), S, d, t in zip(cases, Ss, dev, trees):
+        _say("case %s: n=%d sigma=%d width=%d" % (tag, n, sg, w))
+        assert t.status() == wt.WT_OK, (n, sg, w)
+        ref = oracle.build(S, sg)
+        assert tc.compare_levels(t.bitmaps(), ref.bitmaps) is None, (n, sg, w)
+        assert tc.compare_levels(t.ranks(), ref.ranks, "rank") is None, (n, sg, w)
+        single = wt.build(d, sg, width=w)
+        assert np.array_equal(single.bitmaps(), t.bitmaps()) and np.array_equal(single.ranks(), t.ranks())
+        single.close()
+        t.close()
+    return alone
+
+
+def test_batch_long_sequences_built_alone():
+    """Long sequences of a batch are built as single builds inside the
+    batched call (narrowed orders, folded last level) when that is faster:
+    4-byte symbols from 2^25 on, and 1-byte from 2^25 or 2- and 4-byte from
+    2^23 when no other sequence of the batch shares their batched launches.
+    Every tree equals the oracle's and the single build's, whichever way it
+    was built, and the short sequences around them are unaffected."""
+    # each long sequence alone in its width: all three built alone
+    alone = _batch_alone_check([((1 << 25) + 3, 4, 1, "zipf"), ((1 << 23) + 4099, 1 << 16, 2, "zipf"),
+                                ((1 << 23) + 4099, 1 << 20, 4, "gauss"), (5000, 256, 1, "zipf"),
+                                (0, 1 << 16, 2, "zipf")], "batch-long-1")
+    assert alone == sorted([(1 << 25) + 3, (1 << 23) + 4099, (1 << 23) + 4099]), alone
+    # two equal u16 sequences share their launches (batched); the u32 one of
+    # 2^25 symbols goes alone in any case, which leaves the 2^23 u32 one alone
+    # in its launches; below 2^23 symbols nothing goes alone
+    alone = _batch_alone_check([((1 << 25) + 5, 1 << 20, 4, "gauss"), ((1 << 23) + 4099, 1 << 16, 2, "zipf"),
+                                ((1 << 23) + 4099, 1 << 16, 2, "zipf"), ((1 << 23) + 7, 1 << 20, 4, "gauss"),
+                                ((1 << 23) - 1, 1 << 16, 2, "zipf"), (70_001, 300, 2, "zipf")], "batch-long-2")
+    assert alone == sorted([(1 << 25) + 5, (1 << 23) + 7]), alone
+
+
 def test_batch_reports_out_of_range_per_sequence():
     wt = _wt()
     A = wtgen.uniform(5000, 16, 1)
     B = wtgen.uniform(7000, 16, 2)
     B[6999] = 16
-    trees = wt.build_batch([wt.to_device(A, _dev()), wt.to_device(B, _dev())], [16, 16], [1, 1])
+    C = wtgen.uniform((1 << 23) + 1, 300, 3, width=2)  # long: built alone inside the batch
+    C[1 << 22] = 300
+    trees = wt.build_batch([wt.to_device(A, _dev()), wt.to_device(B, _dev()), wt.to_device(C, _dev())],
+                           [16, 16, 300], [1, 1, 2])
     assert trees[0].status() == wt.WT_OK
     assert trees[1].status() == wt.WT_ERANGE
+    assert trees[2].status() == wt.WT_ERANGE
     for t in trees:
         t.close()
 

@@ -159,9 +159,10 @@ def main() -> int:
     single(wt, torch, wtgen.gauss_mix((1 << 20) + 5, 1 << 20, 16), 1 << 20, "wavelet matrix, narrowed",
            matrix=True, geometry=128)
     single(wt, torch, wtgen.zipf(300_007, 1000, 1.0, 17), 1000, "4-ary tree", arity=4)
-    specs = [(3000, 20, 1), (40_000, 1 << 16, 2), (200_003, 256, 1), (120_000, 1 << 20, 4), (1, 4, 1)]
+    specs = [(3000, 20, 1), (40_000, 1 << 16, 2), (200_003, 256, 1), (120_000, 1 << 20, 4), (1, 4, 1),
+             ((1 << 23) + 9, 1 << 20, 4)]  # (the last one long enough to be built alone)
     batch(wt, torch, [wtgen.uniform(n, sg, 18 + n).astype(wtgen.dtype_for(w)) for n, sg, w in specs],
-          [sg for _, sg, _ in specs], "batch of 5")
+          [sg for _, sg, _ in specs], "batch of 6")
     buffered(wt, torch, wtgen.zipf(1 << 20, 256, 1.1, 19), 256, 1 << 18, "buffered, 4 buffers")
     huffman(wt, torch, wtgen.zipf(500_000, 300, 1.2, 20), 300, "Huffman-shaped")
     tune.load()
