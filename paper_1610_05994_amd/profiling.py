@@ -1,11 +1,13 @@
 """Summaries of rocprofv3 output (``--output-format csv``).
 
 ``python -m paper_1610_05994_amd.profiling overlap TRACE.csv [PATTERN ...]``
-reports, for the dispatches whose kernel name contains one of the patterns
-(default: the batched-build and multi-tree query kernels of the serving
-loop), how long kernels of two or more different streams ran at the same
-time on the device, against the time any of them ran: the evidence that
-batches launched on different streams overlap.
+reports, for the dispatches whose kernel name contains one of the patterns,
+how long kernels of two or more different streams ran at the same time on
+the device, against the time any of them ran: the evidence that batches
+launched on different streams overlap.  Without patterns it takes the
+serving loop's streams (those that ran a batched-build or multi-tree query
+kernel) and every library kernel on them, the single builds of long
+requests included.
 
 ``python -m paper_1610_05994_amd.profiling traffic --workload W --fetch DIR
 --write DIR --bench-log LOG [--calib-mib 256] [--builds K] [--out JSON]``
@@ -129,6 +131,14 @@ def read_dispatches(path: str, patterns=SERVE_KERNELS):
     return out
 
 
+def serving_dispatches(path: str):
+    """Every library kernel (``wt::``) on the streams that ran a serving
+    kernel (batched build or multi-tree query)."""
+    rows = read_dispatches(path, ("wt::",))
+    streams = {d[2] for d in rows if any(p in d[4] for p in SERVE_KERNELS)}
+    return [d for d in rows if d[2] in streams]
+
+
 def overlap(dispatches):
     """Sweep over start / end events: time with >= 1 kernel running, time
     with kernels of >= 2 distinct streams running, and the same per queue."""
@@ -168,8 +178,8 @@ def overlap(dispatches):
 
 def main(argv):
     if len(argv) >= 2 and argv[0] == "overlap":
-        pats = tuple(argv[2:]) or SERVE_KERNELS
-        res = overlap(read_dispatches(argv[1], pats))
+        pats = tuple(argv[2:])
+        res = overlap(read_dispatches(argv[1], pats) if pats else serving_dispatches(argv[1]))
         for k, v in res.items():
             print("%s: %s" % (k, v))
         return 0
