@@ -127,30 +127,59 @@ constexpr uint64_t kNarrowMinN = 1ull << 18;
 // Narrowed orders of a single binary-tree build (2- and 4-byte symbols):
 // T_{i+1} halves the width of T_i as soon as the levels after i fit in half
 // of it, where a narrowing pass exists for the width and the lane's symbol
-// count E (which stays the same: the tiles, and every per-tile table, are
-// those of the input), and where the anchor nodes the half width needs are
-// few beside the tiles (a tile over two anchors takes the slower direct
-// split: at most one tile in kAnchorTiles may); a width whose 8w bits hold
-// fewer bits than the levels gets the per-tile anchor table of level
-// levels - 8w.
+// count E, and where the anchor nodes the half width needs are few beside
+// the tiles (a tile over two anchors takes the slower direct split: at most
+// one tile in kAnchorTiles may); a width whose 8w bits hold fewer bits than
+// the levels gets the per-tile anchor table of level levels - 8w.  The
+// narrower order keeps E symbols per lane (the same tiles), or takes 2E
+// (tiles of twice the symbols, as many bytes per lane as before) where the
+// tuning table runs that width, at this length and number of levels, with
+// at least that many symbols per lane, and where most levels of that width
+// still take the single-node split at the larger tiles (their nodes average
+// kMultiAvgTiles tiles or more; always in a wavelet matrix).  Larger tiles
+// move a tile's bytes for less per-tile work, but span more nodes: on deep
+// levels the per-node work grows more than that saves.
 // A wavelet matrix (one node per level) needs no anchors: its orders narrow
 // wherever the widths allow.
 constexpr uint64_t kAnchorTiles = 8;
 static void narrow_widths(Layout *L, bool matrix) {
     const uint32_t l = L->levels;
     L->narrow = 0;
-    for (uint32_t i = 0; i <= kMaxTreeLevels; i++) L->tw[i] = (uint8_t)L->width;
+    for (uint32_t i = 0; i <= kMaxTreeLevels; i++) {
+        L->tw[i] = (uint8_t)L->width;
+        L->te[i] = (uint8_t)(L->lane_bytes / L->width);
+    }
     if (L->small || L->width < 2 || l < 2 || L->n < kNarrowMinN) return;
-    const uint32_t E = L->lane_bytes / L->width;
     for (uint32_t i = 0; i + 1 < l; i++) {
-        const uint32_t w = L->tw[i];
+        const uint32_t w = L->tw[i], E = L->te[i];
         const uint32_t half_bits = 8 * (w / 2);
-        const bool few_anchors = matrix || half_bits >= l || (kAnchorTiles << (l - half_bits)) <= L->ntiles;
-        const bool halve = w >= 2 && bytes_for(l - (i + 1)) <= w / 2 && narrowing_pass(w, E * w) && few_anchors;
+        // (tiles of 64 e symbols, against the anchor nodes of the half width)
+        auto few_anchors = [&](uint32_t e) {
+            return matrix || half_bits >= l || (kAnchorTiles << (l - half_bits)) <= ceil_div(L->n, 64ull * e);
+        };
+        const bool halve = w >= 2 && bytes_for(l - (i + 1)) <= w / 2 && narrowing_pass(w, E * w) && few_anchors(E);
+        uint32_t en = E;
+        if (halve && 2 * E <= 64 && narrowing_pass_doubling(w, E * w) && few_anchors(2 * E)) {
+            const uint32_t rest = l - (i + 1);
+            const uint32_t want = resolve_geometry(g_tune[0][wclass(w / 2)][rest < 25 ? rest : 24][floor_lg(L->n)],
+                                                   L->n, w / 2);
+            // the levels of the half width (T_j of w / 2 bytes) whose average
+            // node still spans enough doubled tiles for the single-node split
+            uint32_t total = 0, single = 0;
+            for (uint32_t j = i + 1; j < l && (w / 2 == 1 || bytes_for(l - j) > w / 4); j++) {
+                total++;
+                single += (matrix || !level_multi(L->n, j, w / 2, E * w)) ? 1u : 0u;
+            }
+            if (want != kGeomSmall && want != kGeomMid && want >= E * w && 2 * single >= total) en = 2 * E;
+        }
         L->tw[i + 1] = (uint8_t)(halve ? w / 2 : w);
+        L->te[i + 1] = (uint8_t)(halve ? en : E);
         if (halve) L->narrow = 1;
     }
-    for (uint32_t i = l; i <= kMaxTreeLevels; i++) L->tw[i] = L->tw[l - 1];
+    for (uint32_t i = l; i <= kMaxTreeLevels; i++) {
+        L->tw[i] = L->tw[l - 1];
+        L->te[i] = L->te[l - 1];
+    }
 }
 
 static void plan_narrowing(Layout *L) {
@@ -174,7 +203,10 @@ void make_layout(uint64_t n, uint32_t sigma, uint32_t width, bool batched, Layou
 
 void make_layout_geom(uint64_t n, uint32_t sigma, uint32_t width, uint32_t geom, Layout *L) {
     memset(L, 0, sizeof(*L));
-    for (uint32_t i = 0; i <= kMaxTreeLevels; i++) L->tw[i] = (uint8_t)width;  // (no narrowing)
+    for (uint32_t i = 0; i <= kMaxTreeLevels; i++) {  // (no narrowing)
+        L->tw[i] = (uint8_t)width;
+        L->te[i] = (uint8_t)((geom == kGeomSmall || geom == kGeomMid ? kDefaultLaneBytes : geom) / width);
+    }
     const uint32_t l = levels_for(sigma);
     L->n = n;
     L->sigma = sigma;
@@ -363,8 +395,9 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
 
     uint8_t *tbuf[2] = {work + L.ws_ta, work + L.ws_tb};
     const uint32_t lrun = fold ? l - 1 : l;  // passes to run
-    // narrowed orders: T_i has tw[i] bytes per symbol, the same E symbols
-    // per lane (so the same tiles) at every width
+    // narrowed orders: T_i has tw[i] bytes per symbol and tiles of te[i]
+    // symbols per lane (E, or twice that after a narrowing to 1 byte), so
+    // each level has its own tile and superchunk counts
     const bool narrow = L.narrow && !partial && L.arity != 4;
     const uint32_t E = L.lane_bytes / L.width;
     bool anc_ready[2] = {false, false};
@@ -389,16 +422,19 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
             prof_end(pr, st);
             if (err != hipSuccess) return err;
         }
+        const uint32_t ei = narrow ? L.te[i] : E;  // symbols per lane of T_i's tiles
+        const uint64_t tiles_i = narrow ? ceil_div(L.n, 64ull * ei) : L.ntiles;
+        const uint64_t nsup_i = ceil_div(tiles_i, kSup);
         PrepArgs pp;
         pp.tile_ones = tile_ones + (uint64_t)i * tile_stride(L.ntiles);
         pp.supsum = supsum;
         pp.sup = sup + (uint64_t)i * L.nsup;
-        pp.ntiles = L.ntiles;
-        pp.nsup = L.nsup;
+        pp.ntiles = tiles_i;
+        pp.nsup = nsup_i;
         pp.plan = pa;
         pp.plan_here = big ? 0u : 1u;
-        pp.sums_here = (L.nsup <= kPrepSups && !big && pa.nodes < kThreads) ? 1u : 0u;
-        pr = prof_begin(st, "prep", i, L.width, L.n, L.ntiles * 4 + L.nsup * 16);
+        pp.sums_here = (nsup_i <= kPrepSups && !big && pa.nodes < kThreads) ? 1u : 0u;
+        pr = prof_begin(st, "prep", i, L.width, L.n, tiles_i * 4 + nsup_i * 16);
         err = launch_prep(pp, st);
         prof_end(pr, st);
         if (err != hipSuccess) return err;
@@ -412,10 +448,10 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
             an.start = start + start_offset(L.anc_level[w - 1]);
             an.nodes = 1ull << L.anc_level[w - 1];
             an.n = L.n;
-            an.tile = tile_syms(L.width, L.lane_bytes);
-            an.ntiles = L.ntiles;
+            an.tile = 64ull * ei;  // (a width's levels share one tile geometry)
+            an.ntiles = tiles_i;
             an.out = reinterpret_cast<uint2 *>(work + L.ws_tanc[w - 1]);
-            pr = prof_begin(st, "anchor", i, w, L.n, L.ntiles * 8);
+            pr = prof_begin(st, "anchor", i, w, L.n, tiles_i * 8);
             err = launch_tile_anchor(an, st);
             prof_end(pr, st);
             if (err != hipSuccess) return err;
@@ -444,7 +480,7 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         a.words = L.words;
         a.rank_entries = L.rank_entries;
         a.rank_stride = L.rank_stride;
-        a.ntiles = L.ntiles;
+        a.ntiles = tiles_i;
         a.levels = l;
         a.level = i;
         // (a narrowed symbol keeps its low 8w bits only)
@@ -463,9 +499,10 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         const uint64_t lbytes = L.n * w + ((a.tout && !fold_here) ? L.n * wo : 0) +
                                 (a.bits ? L.words * 8 + L.rank_stride * 8 : 0) + (a.digits ? L.dwords * 8 : 0) +
                                 (a.bits_next ? L.words * 8 : 0);
-        const uint32_t lb = E * w;  // lane bytes at this width
+        const uint32_t lb = ei * w;  // lane bytes of T_i's tiles
+        const uint32_t lbo = (narrow && i + 1 < l) ? L.te[i + 1] * wo : lb;  // and of T_{i+1}'s
         pr = prof_begin(st, "level", i, w, L.n, lbytes);
-        err = launch_level(a, w, lb, !L.matrix && wo == w && level_multi(L.n, i, w, lb), wo, st);
+        err = launch_level(a, w, lb, !L.matrix && wo == w && level_multi(L.n, i, w, lb), wo, lbo, st);
         prof_end(pr, st);
         if (err != hipSuccess) return err;
     }
@@ -1233,7 +1270,7 @@ static hipError_t enqueue_huffman(const void *S, const wt_desc *desc, const Huff
         const uint64_t lbytes = nd * I.width + nnext * I.width + a.words * 8 + a.rank_stride * 8;
         pr = prof_begin(st, "level", d, I.width, nd, lbytes);
         // (the plain variant: every destination comes from the node tables)
-        err = launch_level(a, I.width, I.lane_bytes, false, I.width, st);
+        err = launch_level(a, I.width, I.lane_bytes, false, I.width, I.lane_bytes, st);
         prof_end(pr, st);
         if (err != hipSuccess) return err;
     }

@@ -976,14 +976,19 @@ struct SplitRec {
 // leave their next-level counts in *rec; other tiles add theirs directly.
 // T_{i+1} is written with WO-byte symbols (WO = W, or W / 2 where the
 // order narrows).
-template <int W, int B, int WO, bool kMulti, bool kCopy>
+template <int W, int B, int WO, bool kMulti, bool kCopy, int EO = B / W>
 __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8_t *s_wave, SplitRec *rec) {
     typedef typename ElemT<WO>::T TO;           // symbols of T_{i+1}
     constexpr int E = B / W;                    // symbols per lane
     constexpr int CH = 16 / WO;                 // output symbols per 16-byte chunk
     constexpr uint64_t TILE = tile_syms(W, B);  // 64 * E
+    // tiles of T_{i+1}, which its next-level ones are counted by: the same,
+    // or twice as long where a narrowing pass also doubles the symbols per
+    // lane (a run of at most TILE symbols still touches at most two of them)
+    constexpr uint64_t TILE_NEXT = 64ull * EO;
     static_assert(TILE < 65536, "per-tile counts travel in 16-bit fields");
     static_assert(WO == W || (2 * WO == W && !kMulti), "a narrowing pass halves the width, without the staged paths");
+    static_assert(EO == E || (EO == 2 * E && WO < W && EO <= 64), "only a narrowing pass doubles the tiles");
     typedef typename MaskT<E>::T M;
     const int lane = threadIdx.x & 63;
     TO *s_stage = reinterpret_cast<TO *>(s_wave);
@@ -1158,8 +1163,8 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
             const uint32_t len = ((int64_t)(gb + lo) < 0) ? 0u : (uint32_t)(r ? O : Z);
             const uint32_t cb = lo / CH, ce = len ? (lo + len + CH - 1) / CH : cb;
             const uint32_t fb = (lo + CH - 1) / CH, fe = (lo + len) / CH;  // chunks inside the run
-            const uint64_t dt0 = (gb + (uint64_t)cb * CH) / TILE;
-            const uint64_t cs = ((dt0 + 1) * TILE - gb) / CH;  // first chunk in tile dt0 + 1
+            const uint64_t dt0 = (gb + (uint64_t)cb * CH) / TILE_NEXT;
+            const uint64_t cs = ((dt0 + 1) * TILE_NEXT - gb) / CH;  // first chunk in tile dt0 + 1
             lo_r[r] = lo;
             len_r[r] = len;
             gb_r[r] = gb;
@@ -1313,7 +1318,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
                 tout[dst] = (TO)x;
                 nown += (fold && (dst & 15) == 0) ? 1u : 0u;
                 if (counting && ((x >> sh2) & 1u)) {
-                    const uint64_t dt = dst / TILE;
+                    const uint64_t dt = dst / TILE_NEXT;
                     if (lds_counts && v - vf <= vl - vf) {
                         const uint32_t key = 4 * (v - vf) + 2 * b + (uint32_t)(dt & 1);
                         atomicAdd(&s_cnt[key], 1u);
@@ -1409,7 +1414,7 @@ __device__ __forceinline__ void flush_split_recs(const LevelArgs &a, const Split
     }
 }
 
-template <int W, int B, int WO, bool M>
+template <int W, int B, int WO, bool M, int EO = B / W>
 __device__ __forceinline__ void level_kernel_body(const LevelArgs &a) {
     constexpr bool kCopy = dense_lds_copy<W, B>();
     __shared__ __align__(16) uint8_t s_all[kWaves * level_wave_bytes<W, B, M, kCopy>()];
@@ -1419,7 +1424,7 @@ __device__ __forceinline__ void level_kernel_body(const LevelArgs &a) {
     const uint64_t t = t0 + wv;
     if ((threadIdx.x & 63) < 4) s_rec[wv].cnt[threadIdx.x & 63] = 0;
     if (t < a.ntiles)
-        level_tile<W, B, WO, M, kCopy>(a, t, s_all + wv * level_wave_bytes<W, B, M, kCopy>(), &s_rec[wv]);
+        level_tile<W, B, WO, M, kCopy, EO>(a, t, s_all + wv * level_wave_bytes<W, B, M, kCopy>(), &s_rec[wv]);
     flush_split_recs(a, s_rec, t0);
 }
 
@@ -1428,10 +1433,12 @@ __global__ __launch_bounds__(kThreads) void k_level(LevelArgs a) {
     level_kernel_body<W, B, W, M>(a);
 }
 
-// A narrowing level pass: T_{i+1} keeps the low W / 2 bytes of each symbol.
-template <int W, int B>
+// A narrowing level pass: T_{i+1} keeps the low W / 2 bytes of each symbol,
+// in tiles of BO bytes per lane (B / 2: the same symbols per lane; B: twice
+// as many).
+template <int W, int B, int BO>
 __global__ __launch_bounds__(kThreads) void k_level_narrow(LevelArgs a) {
-    level_kernel_body<W, B, W / 2, false>(a);
+    level_kernel_body<W, B, W / 2, false, BO / (W / 2)>(a);
 }
 
 // Anchors of every tile: one thread per tile, binary search over the anchor
@@ -1835,18 +1842,25 @@ hipError_t launch_plan(const PlanArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_level(const LevelArgs &a, uint32_t width, uint32_t lane_bytes, bool multi, uint32_t out_width,
-                        hipStream_t s) {
+                        uint32_t out_lane_bytes, hipStream_t s) {
     const dim3 g((uint32_t)ceil_div(a.ntiles, kWaves));
     if (out_width == width) {
+        if (out_lane_bytes != lane_bytes) return hipErrorInvalidValue;
         WT_LAUNCH_WBM(k_level, width, lane_bytes, multi, g, s, a);
         return hipGetLastError();
     }
     if (multi || 2 * out_width != width) return hipErrorInvalidValue;
-    switch (width * 1000 + lane_bytes) {
-        case 4064: hipLaunchKernelGGL((k_level_narrow<4, 64>), g, dim3(kThreads), 0, s, a); break;
-        case 4128: hipLaunchKernelGGL((k_level_narrow<4, 128>), g, dim3(kThreads), 0, s, a); break;
-        case 2064: hipLaunchKernelGGL((k_level_narrow<2, 64>), g, dim3(kThreads), 0, s, a); break;
-        case 2128: hipLaunchKernelGGL((k_level_narrow<2, 128>), g, dim3(kThreads), 0, s, a); break;
+    switch ((width << 16) | (lane_bytes << 8) | out_lane_bytes) {
+        case (4 << 16) | (64 << 8) | 32: hipLaunchKernelGGL((k_level_narrow<4, 64, 32>), g, dim3(kThreads), 0, s, a); break;
+        case (4 << 16) | (64 << 8) | 64: hipLaunchKernelGGL((k_level_narrow<4, 64, 64>), g, dim3(kThreads), 0, s, a); break;
+        case (4 << 16) | (128 << 8) | 64:
+            hipLaunchKernelGGL((k_level_narrow<4, 128, 64>), g, dim3(kThreads), 0, s, a);
+            break;
+        case (2 << 16) | (64 << 8) | 32: hipLaunchKernelGGL((k_level_narrow<2, 64, 32>), g, dim3(kThreads), 0, s, a); break;
+        case (2 << 16) | (64 << 8) | 64: hipLaunchKernelGGL((k_level_narrow<2, 64, 64>), g, dim3(kThreads), 0, s, a); break;
+        case (2 << 16) | (128 << 8) | 64:
+            hipLaunchKernelGGL((k_level_narrow<2, 128, 64>), g, dim3(kThreads), 0, s, a);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

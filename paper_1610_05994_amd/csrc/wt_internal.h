@@ -111,6 +111,7 @@ struct Layout {
     // tile, the anchor nodes of its first and last position.
     uint32_t narrow;                    // some T_i is narrower than the input
     uint8_t tw[kMaxTreeLevels + 1];     // bytes per symbol of T_i
+    uint8_t te[kMaxTreeLevels + 1];     // symbols per lane of T_i's tiles (64 te[i] symbols a tile)
     uint32_t anc_level[2];              // anchor level of widths 1 and 2 (0: none)
     uint64_t ws_tanc[2];
     uint64_t work_bytes;
@@ -319,12 +320,18 @@ hipError_t launch_ingest(const IngestArgs &a, uint32_t width, uint32_t lane_byte
 hipError_t launch_prep(const PrepArgs &a, hipStream_t s);  // k_supsum, then k_prep
 hipError_t launch_plan(const PlanArgs &a, hipStream_t s);
 // out_width: bytes per symbol of T_{i+1}: width, or width / 2 (a narrowing
-// pass; lane_bytes 64 or 128, never multi)
+// pass; lane_bytes 64 or 128, never multi); out_lane_bytes: lane bytes of
+// T_{i+1}'s tiles (lane_bytes, or for a narrowing pass lane_bytes / 2 or,
+// doubling the symbols per lane, lane_bytes)
 hipError_t launch_level(const LevelArgs &a, uint32_t width, uint32_t lane_bytes, bool multi, uint32_t out_width,
-                        hipStream_t s);
+                        uint32_t out_lane_bytes, hipStream_t s);
 // Whether a narrowing pass exists for this width and lane size.
 __host__ __device__ constexpr bool narrowing_pass(uint32_t width, uint32_t lane_bytes) {
     return (width == 4 || width == 2) && (lane_bytes == 64 || lane_bytes == 128);
+}
+// Whether one also exists that doubles the symbols per lane of T_{i+1}.
+__host__ __device__ constexpr bool narrowing_pass_doubling(uint32_t width, uint32_t lane_bytes) {
+    return (width == 4 || width == 2) && lane_bytes == 64;
 }
 // Level passes take the staged split of tiles spanning a few nodes where the
 // average node is shorter than this many tiles.

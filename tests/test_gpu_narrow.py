@@ -38,9 +38,9 @@ def restore_table():
     tune.load()
 
 
-def _force(lane_bytes):
+def _force(lane_bytes, widths=(2, 4)):
     _, wt = _mods()
-    for width in (2, 4):
+    for width in widths:
         lb = lane_bytes if lane_bytes // width <= 64 else 0
         for levels in range(1, min(24, 8 * width) + 1):
             for lg_n in range(0, 41):
@@ -126,13 +126,24 @@ def test_narrowed_large_clustered(restore_table):
     _check(S, 1 << 20, "u32-gauss-2^26@128")
 
 
+def test_narrowed_orders_with_doubled_tiles(restore_table):
+    # 64 bytes per lane at every width: the narrowing passes that also double
+    # the next level's symbols per lane run where most levels of the narrower
+    # width keep nodes of many tiles (u32 -> u16 at 16 -> 32 symbols per
+    # lane; u16 -> u8 at 32 -> 64 symbols per lane for a long sequence)
+    _force(64, widths=(1, 2, 4))
+    _check(wtgen.zipf(N1, 1 << 17, 1.2, 79, width=4), 1 << 17, "u32-zipf-2^17-doubled")
+    _check(wtgen.zipf((1 << 26) + 4099, 1 << 16, 1.0, 80, width=2), 1 << 16, "u16-zipf-2^16-2^26-doubled")
+
+
 @pytest.mark.parametrize("lane_bytes", [64, 128])
 def test_narrowed_wavelet_matrix(lane_bytes, restore_table):
     # a wavelet matrix has one node per level: its orders narrow with no
-    # anchors, at any length above the threshold
+    # anchors, at any length above the threshold (and, at 64 bytes per lane,
+    # double their symbols per lane where they narrow to 1 byte)
     import torch
     _, wt = _mods()
-    _force(lane_bytes)
+    _force(lane_bytes, widths=(1, 2, 4))
     for tag, S, sigma in [("u32-gauss-2^20", wtgen.gauss_mix(N0, 1 << 20, 75), 1 << 20),
                           ("u32-uniform-2^24", wtgen.uniform(N0, 1 << 24, 76, width=4), 1 << 24),
                           ("u32-uniform-300", wtgen.uniform(N0, 300, 77, width=4), 300),
