@@ -416,7 +416,11 @@ static hipError_t enqueue_build(const void *S, const Layout &L, uint8_t *tree, u
         pa.matrix = L.matrix;
         pa.shift = 0;
         const bool big = pa.nodes > kScanChunk;  // one counter slot there
-        if (big) {
+        // (the last level's pass writes only its bitmap and directory: a large
+        // last level gets no node tables, except in a buffered build's partial
+        // tree, whose last-level node tables are the leaf offsets the merge
+        // reads)
+        if (big && (i + 1 < l || partial)) {
             pr = prof_begin(st, "plan", i, L.width, L.n, pa.nodes * (8 + 16 + 8 + 16));
             err = launch_plan(pa, st);
             prof_end(pr, st);

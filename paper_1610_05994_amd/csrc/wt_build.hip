@@ -589,7 +589,7 @@ __host__ __device__ constexpr uint32_t level_wave_bytes() {
 // single-node case.  Runs are staged in LDS at their destination's 16-byte
 // phase and written out in aligned chunks; next-level ones are counted per
 // chunk.
-template <int W, int B, int WO>
+template <int W, int B, int WO, bool kOptNodes>
 __device__ __forceinline__ void stage_multi(const LevelArgs &a, const uint4 (&raw)[B / 16],
                                             typename MaskT<B / W>::T mb, int nval, uint32_t lr1, uint32_t agg,
                                             unsigned long long prefix, uint64_t base, uint64_t nvalid, uint32_t vf,
@@ -754,7 +754,8 @@ __device__ __forceinline__ void stage_multi(const LevelArgs &a, const uint4 (&ra
         if (c) {
             const uint32_t r = q >> 1;
             atomicAdd(&a.tile_ones_next[tb->tix[q]], c);
-            atomicAdd(&ones_next[2ull * (vf + (r >> 1)) + (r & 1u)], (unsigned long long)c);
+            if (!kOptNodes || ones_next)
+                atomicAdd(&ones_next[2ull * (vf + (r >> 1)) + (r & 1u)], (unsigned long long)c);
         }
     }
 }
@@ -773,7 +774,7 @@ __device__ __forceinline__ void stage_multi(const LevelArgs &a, const uint4 (&ra
 // (node, bit, destination-tile parity).  Node starts and their tile ranks
 // travel between lanes as (position << 16 | rank) in a prefix maximum and a
 // suffix minimum.
-template <int W, int B, int WO, bool kCopy>
+template <int W, int B, int WO, bool kCopy, bool kOptNodes>
 __device__ __forceinline__ void split_dense(const LevelArgs &a, const uint4 (&raw)[B / 16],
                                             typename MaskT<B / W>::T mb, int nval, uint32_t lr1, uint32_t agg,
                                             unsigned long long prefix, uint64_t base, uint64_t nvalid, uint64_t t,
@@ -857,7 +858,7 @@ __device__ __forceinline__ void split_dense(const LevelArgs &a, const uint4 (&ra
     // ones of an interior node's children: a plain store when the node lies
     // in this lane, an atomic when it crosses lanes
     auto flush = [&]() {
-        if (open && interior && counting && (c0 | c1)) {
+        if (open && interior && counting && (!kOptNodes || ones_next) && (c0 | c1)) {
             unsigned long long *o = &ones_next[2ull * vcur];
             if (ps >= p0 && pe <= p0 + E) {
                 o[0] = c0;
@@ -956,7 +957,7 @@ __device__ __forceinline__ void split_dense(const LevelArgs &a, const uint4 (&ra
             const uint64_t dt0 = d0 / TILE;
             const uint64_t dt = ((dt0 & 1) == par) ? dt0 : dt0 + 1;
             if (dt < a.ntiles) atomicAdd(&a.tile_ones_next[dt], cnt);  // (always, with consistent tables)
-            atomicAdd(&ones_next[2ull * (e ? vl : vf) + b], (unsigned long long)cnt);
+            if (!kOptNodes || ones_next) atomicAdd(&ones_next[2ull * (e ? vl : vf) + b], (unsigned long long)cnt);
         }
     }
 }
@@ -976,7 +977,7 @@ struct SplitRec {
 // leave their next-level counts in *rec; other tiles add theirs directly.
 // T_{i+1} is written with WO-byte symbols (WO = W, or W / 2 where the
 // order narrows).
-template <int W, int B, int WO, bool kMulti, bool kCopy, int EO = B / W>
+template <int W, int B, int WO, bool kMulti, bool kCopy, int EO = B / W, bool kOptNodes = false>
 __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8_t *s_wave, SplitRec *rec) {
     typedef typename ElemT<WO>::T TO;           // symbols of T_{i+1}
     constexpr int E = B / W;                    // symbols per lane
@@ -1093,8 +1094,12 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
     TO *tout = reinterpret_cast<TO *>(a.tout);
     const bool counting = a.tile_ones_next != nullptr;
     const uint32_t sh2 = sh - 1;  // bit of the next level (when counting)
-    // (slot counts are powers of two)
-    unsigned long long *ones_next = counting ? a.ones_next + (t & (a.slots_next - 1)) * a.nodes_next : nullptr;
+    // (slot counts are powers of two; with kOptNodes a null a.ones_next means
+    // no node counts: the next level is a last level whose node tables
+    // nobody reads)
+    unsigned long long *ones_next = (counting && (!kOptNodes || a.ones_next))
+                                        ? a.ones_next + (t & (a.slots_next - 1)) * a.nodes_next
+                                        : nullptr;
 
     // narrowed T_i: a node's high bits come from the anchor holding the
     // position (every symbol of the tile has the first one unless the tile
@@ -1253,11 +1258,11 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
         if (straddle) {
             // (the direct split below)
         } else if (vl - vf < kRunNodes)
-            stage_multi<W, B, WO>(a, raw, mb, nval, lr1, agg, prefix, base, nvalid, vf, vl, nsh, nbase, s_wave, tout,
-                                  counting, sh2, ones_next);
+            stage_multi<W, B, WO, kOptNodes>(a, raw, mb, nval, lr1, agg, prefix, base, nvalid, vf, vl, nsh, nbase,
+                                             s_wave, tout, counting, sh2, ones_next);
         else
-            split_dense<W, B, WO, kCopy>(a, raw, mb, nval, lr1, agg, prefix, base, nvalid, t, vf, vl, nsh, nbase,
-                                         s_wave, tout, counting, sh2, ones_next);
+            split_dense<W, B, WO, kCopy, kOptNodes>(a, raw, mb, nval, lr1, agg, prefix, base, nvalid, t, vf, vl, nsh,
+                                                    nbase, s_wave, tout, counting, sh2, ones_next);
         if (!straddle) return;
     }
 
@@ -1325,7 +1330,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
                         s_tix[key] = (uint32_t)dt;
                     } else {
                         atomicAdd(&a.tile_ones_next[dt], 1u);
-                        atomicAdd(&ones_next[2ull * v + b], 1ull);
+                        if (!kOptNodes || ones_next) atomicAdd(&ones_next[2ull * v + b], 1ull);
                     }
                 }
             }
@@ -1371,7 +1376,8 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
             if (c) {
                 const uint32_t dt = s_tix[q];
                 atomicAdd(&a.tile_ones_next[dt], c);
-                atomicAdd(&ones_next[2ull * (vf + q / 4) + ((q >> 1) & 1u)], (unsigned long long)c);
+                if (!kOptNodes || ones_next)
+                    atomicAdd(&ones_next[2ull * (vf + q / 4) + ((q >> 1) & 1u)], (unsigned long long)c);
             }
         }
     }
@@ -1386,6 +1392,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8
 // exchanges.  A partial result travels packed: the counts of the matching
 // records (each below 2^16, so 16 of them stay below 2^24) plus, from bit
 // 24, how many of them come before record r.
+template <bool kOptNodes = false>
 __device__ __forceinline__ void flush_split_recs(const LevelArgs &a, const SplitRec *recs, uint64_t t0) {
     static_assert(kWaves == 4, "16 records, four per wave, over the 64 lanes of wave 0");
     __syncthreads();
@@ -1408,7 +1415,7 @@ __device__ __forceinline__ void flush_split_recs(const LevelArgs &a, const Split
     pch += __shfl_xor(pch, 32, 64);
     if (g != 0 || c == 0) return;
     if ((pdt >> 24) == 0) atomicAdd(&a.tile_ones_next[dt], pdt & 0xFFFFFFu);
-    if ((pch >> 24) == 0) {
+    if ((pch >> 24) == 0 && (!kOptNodes || a.ones_next)) {
         unsigned long long *ones_next = a.ones_next + (t0 & (a.slots_next - 1)) * a.nodes_next;
         atomicAdd(&ones_next[child], (unsigned long long)(pch & 0xFFFFFFu));
     }
@@ -1479,7 +1486,11 @@ __device__ __forceinline__ LevelArgs job_level(const BatchJob &j, uint32_t i) {
     a.tile_ones = tile_ones + (uint64_t)i * tile_stride(j.ntiles);
     a.sup = reinterpret_cast<const unsigned long long *>(w + j.ws_sup) + (uint64_t)i * j.nsup;
     a.tile_ones_next = (i + 1 < l) ? tile_ones + (uint64_t)(i + 1) * tile_stride(j.ntiles) : nullptr;
-    a.ones_next = (i + 1 < l) ? reinterpret_cast<unsigned long long *>(w + j.ws_ones) + ones_offset(i + 1) : nullptr;
+    // (no node counts for a last level of more than kScanChunk nodes: its
+    // node tables would take the plan kernels, and its pass reads none)
+    a.ones_next = (i + 1 < l && !(i + 2 == l && (2ull << i) > kScanChunk))
+                      ? reinterpret_cast<unsigned long long *>(w + j.ws_ones) + ones_offset(i + 1)
+                      : nullptr;
     a.nodes_next = 2ull << i;
     a.slots_next = level_slots(i + 1);
     a.n = j.n;
@@ -1603,18 +1614,26 @@ __global__ __launch_bounds__(kThreads) void k_batch_prep(BatchClass c, uint32_t 
 // Node tables of levels above kScanChunk nodes, chunks of every active
 // sequence side by side: workgroup b serves sequence b / cpj, chunk b % cpj
 // (every sequence has 2^level nodes, so cpj chunks, at this level).
+// (a sequence's last level needs no node tables: its pass writes only its
+// bitmap and directory)
 __global__ __launch_bounds__(kThreads) void k_batch_plan_reduce(BatchClass c, uint32_t level, uint32_t cpj) {
-    const PrepArgs p = job_prep(c.jobs[blockIdx.x / cpj], level);
+    const BatchJob &j = c.jobs[blockIdx.x / cpj];
+    if (level + 1 == j.levels) return;
+    const PrepArgs p = job_prep(j, level);
     plan_reduce_chunk(p.plan, blockIdx.x % cpj);
 }
 
 __global__ __launch_bounds__(kThreads) void k_batch_plan_partials(BatchClass c, uint32_t level, uint32_t cpj) {
-    const PrepArgs p = job_prep(c.jobs[blockIdx.x], level);
+    const BatchJob &j = c.jobs[blockIdx.x];
+    if (level + 1 == j.levels) return;
+    const PrepArgs p = job_prep(j, level);
     plan_scan_partials(p.plan, cpj);
 }
 
 __global__ __launch_bounds__(kThreads) void k_batch_plan_apply(BatchClass c, uint32_t level, uint32_t cpj) {
-    const PrepArgs p = job_prep(c.jobs[blockIdx.x / cpj], level);
+    const BatchJob &j = c.jobs[blockIdx.x / cpj];
+    if (level + 1 == j.levels) return;
+    const PrepArgs p = job_prep(j, level);
     const uint64_t b = blockIdx.x % cpj;
     plan_chunk(p.plan, p.plan.ones + b * kScanChunk, b * kScanChunk, p.plan.partials[b]);
 }
@@ -1629,8 +1648,9 @@ __global__ __launch_bounds__(kThreads) void k_batch_level(BatchClass c, uint32_t
     const LevelArgs a = job_level(j, level);
     if ((threadIdx.x & 63) < 4) s_rec[wv].cnt[threadIdx.x & 63] = 0;
     if (t0 + wv < j.ntiles)
-        level_tile<W, B, W, M, true>(a, t0 + wv, s_all + wv * level_wave_bytes<W, B, M, true>(), &s_rec[wv]);
-    flush_split_recs(a, s_rec, t0);
+        level_tile<W, B, W, M, true, B / W, true>(a, t0 + wv, s_all + wv * level_wave_bytes<W, B, M, true>(),
+                                                  &s_rec[wv]);
+    flush_split_recs<true>(a, s_rec, t0);
 }
 
 }  // namespace
@@ -1850,17 +1870,14 @@ hipError_t launch_level(const LevelArgs &a, uint32_t width, uint32_t lane_bytes,
         return hipGetLastError();
     }
     if (multi || 2 * out_width != width) return hipErrorInvalidValue;
+    const dim3 b(kThreads);
     switch ((width << 16) | (lane_bytes << 8) | out_lane_bytes) {
-        case (4 << 16) | (64 << 8) | 32: hipLaunchKernelGGL((k_level_narrow<4, 64, 32>), g, dim3(kThreads), 0, s, a); break;
-        case (4 << 16) | (64 << 8) | 64: hipLaunchKernelGGL((k_level_narrow<4, 64, 64>), g, dim3(kThreads), 0, s, a); break;
-        case (4 << 16) | (128 << 8) | 64:
-            hipLaunchKernelGGL((k_level_narrow<4, 128, 64>), g, dim3(kThreads), 0, s, a);
-            break;
-        case (2 << 16) | (64 << 8) | 32: hipLaunchKernelGGL((k_level_narrow<2, 64, 32>), g, dim3(kThreads), 0, s, a); break;
-        case (2 << 16) | (64 << 8) | 64: hipLaunchKernelGGL((k_level_narrow<2, 64, 64>), g, dim3(kThreads), 0, s, a); break;
-        case (2 << 16) | (128 << 8) | 64:
-            hipLaunchKernelGGL((k_level_narrow<2, 128, 64>), g, dim3(kThreads), 0, s, a);
-            break;
+        case (4 << 16) | (64 << 8) | 32: hipLaunchKernelGGL((k_level_narrow<4, 64, 32>), g, b, 0, s, a); break;
+        case (4 << 16) | (64 << 8) | 64: hipLaunchKernelGGL((k_level_narrow<4, 64, 64>), g, b, 0, s, a); break;
+        case (4 << 16) | (128 << 8) | 64: hipLaunchKernelGGL((k_level_narrow<4, 128, 64>), g, b, 0, s, a); break;
+        case (2 << 16) | (64 << 8) | 32: hipLaunchKernelGGL((k_level_narrow<2, 64, 32>), g, b, 0, s, a); break;
+        case (2 << 16) | (64 << 8) | 64: hipLaunchKernelGGL((k_level_narrow<2, 64, 64>), g, b, 0, s, a); break;
+        case (2 << 16) | (128 << 8) | 64: hipLaunchKernelGGL((k_level_narrow<2, 128, 64>), g, b, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
