@@ -1018,7 +1018,12 @@ static int huff_lengths(const uint64_t *counts, uint32_t sigma, std::vector<uint
             maxc = std::max<uint64_t>(maxc, counts[c]);
         }
     if (k < 2) return WT_OK;
+    // items: leaves 0..k-1 (in queue order), merged items k..2k-2, with
+    // weights w; up[i] is item i's parent (k < 2^24, so 32 bits hold it).
+    // The leaves' weights are the sorted counts, written in order.
     std::vector<uint32_t> leaf(k);
+    std::vector<uint64_t> w(2 * k - 1);
+    std::vector<uint32_t> up(2 * k - 1);
     if (maxc <= 4 * k + 1024) {
         std::vector<uint32_t> pos(maxc + 2, 0);
         for (uint32_t c = 0; c < sigma; c++)
@@ -1026,17 +1031,21 @@ static int huff_lengths(const uint64_t *counts, uint32_t sigma, std::vector<uint
         for (uint64_t x = 1; x < pos.size(); x++) pos[x] += pos[x - 1];
         for (uint32_t c = 0; c < sigma; c++)
             if (counts[c]) leaf[pos[counts[c]]++] = c;
+        // (pos[x] now ends count x's leaves)
+        size_t i = 0;
+        for (uint64_t x = 1; x <= maxc; x++)
+            for (; i < pos[x]; i++) w[i] = x;
     } else {
         std::vector<uint64_t> key;
         key.reserve(k);
         for (uint32_t c = 0; c < sigma; c++)
             if (counts[c]) key.push_back((counts[c] << 24) | c);
         std::sort(key.begin(), key.end());
-        for (size_t i = 0; i < k; i++) leaf[i] = (uint32_t)(key[i] & 0xFFFFFFu);
+        for (size_t i = 0; i < k; i++) {
+            leaf[i] = (uint32_t)(key[i] & 0xFFFFFFu);
+            w[i] = key[i] >> 24;
+        }
     }
-    // items: leaves 0..k-1 (in queue order), merged items k..2k-2
-    std::vector<uint64_t> w(2 * k - 1), up(2 * k - 1);
-    for (size_t i = 0; i < k; i++) w[i] = counts[leaf[i]];
     size_t lf = 0, mf = k, made = k;
     for (; made < 2 * k - 1; made++) {
         size_t pick[2];
@@ -1045,13 +1054,15 @@ static int huff_lengths(const uint64_t *counts, uint32_t sigma, std::vector<uint
             pick[t] = from_leaf ? lf++ : mf++;
         }
         w[made] = w[pick[0]] + w[pick[1]];
-        up[pick[0]] = up[pick[1]] = made;
+        up[pick[0]] = up[pick[1]] = (uint32_t)made;
     }
-    std::vector<uint32_t> depth(2 * k - 1, 0);
-    for (size_t i = 2 * k - 2; i-- > 0;) depth[i] = depth[up[i]] + 1;  // parents come later
+    // depths in place: parents come later, so walking down from the root
+    // each item reads its parent's depth where the parent's link was
+    up[2 * k - 2] = 0;
+    for (size_t i = 2 * k - 2; i-- > 0;) up[i] = up[up[i]] + 1;
     for (size_t i = 0; i < k; i++) {
-        len[leaf[i]] = (uint8_t)std::min<uint32_t>(depth[i], 255u);
-        maxlen = std::max(maxlen, depth[i]);
+        len[leaf[i]] = (uint8_t)std::min<uint32_t>(up[i], 255u);
+        maxlen = std::max(maxlen, up[i]);
     }
     return WT_OK;
 }
