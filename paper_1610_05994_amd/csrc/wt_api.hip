@@ -740,7 +740,9 @@ struct BatchPlan {
 
 static int plan_batch(uint32_t m, const wt_desc *descs, BatchPlan *P) {
     P->L.resize(m);
-    std::vector<int> cls(m, -1);
+    // per sequence: its batched class, or one of these
+    constexpr int kOneWorkgroup = -1, kAlwaysAlone = -2;
+    std::vector<int> cls(m, kOneWorkgroup);
     uint32_t members[kClasses] = {};
     for (uint32_t q = 0; q < m; q++) {
         int rc = check_desc(&descs[q]);
@@ -751,13 +753,13 @@ static int plan_batch(uint32_t m, const wt_desc *descs, BatchPlan *P) {
             continue;
         }
         cls[q] = batch_class(descs[q].width, P->L[q].lane_bytes);
-        if (descs[q].width == 4 && descs[q].n >= (1ull << kSoloSharedMinLg)) cls[q] = -2;  // alone in any case
+        if (descs[q].width == 4 && descs[q].n >= (1ull << kSoloSharedMinLg)) cls[q] = kAlwaysAlone;
         else members[cls[q]]++;
     }
     for (uint32_t q = 0; q < m; q++) {
-        if (cls[q] == -1) continue;
-        const bool solo =
-            cls[q] == -2 || (members[cls[q]] == 1 && descs[q].n >= (1ull << kSoloMinLg[wclass(descs[q].width)]));
+        if (cls[q] == kOneWorkgroup) continue;
+        const bool solo = cls[q] == kAlwaysAlone ||
+                          (members[cls[q]] == 1 && descs[q].n >= (1ull << kSoloMinLg[wclass(descs[q].width)]));
         if (solo) {
             make_layout(descs[q].n, descs[q].sigma, descs[q].width, false, &P->L[q]);
             P->solo.push_back(q);

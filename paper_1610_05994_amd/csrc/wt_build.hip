@@ -976,7 +976,10 @@ struct SplitRec {
 // symbols of T_i); s_wave is the wave's own LDS slice.  Single-node tiles
 // leave their next-level counts in *rec; other tiles add theirs directly.
 // T_{i+1} is written with WO-byte symbols (WO = W, or W / 2 where the
-// order narrows).
+// order narrows), in tiles of EO symbols per lane.  With kOptNodes (the
+// batched passes) a null a.ones_next means that the next level's node counts
+// are not wanted; the single-build passes always count them (the extra test
+// costs their staged variants scalar registers).
 template <int W, int B, int WO, bool kMulti, bool kCopy, int EO = B / W, bool kOptNodes = false>
 __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t t, uint8_t *s_wave, SplitRec *rec) {
     typedef typename ElemT<WO>::T TO;           // symbols of T_{i+1}
