@@ -330,7 +330,7 @@ def extra_workloads(args) -> dict:
     del r3
     torch.cuda.empty_cache()
     a4 = argparse.Namespace(**vars(args))
-    a4.workload, a4.steps, a4.warmup = "c4", 2, 1
+    a4.workload, a4.steps, a4.warmup = "c4", 6, 2
     r4 = bench_batch(a4)
     ex["c4"] = {"workload": r4["config"]["workload"], "steps": a4.steps, "ms_per_step": r4["ms_per_step"],
                 "symbols_per_s": r4["value"], "roofline": r4["roofline"], "compulsory_bytes": r4["compulsory_bytes"],
