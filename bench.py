@@ -313,12 +313,21 @@ def main() -> int:
 
 
 def extra_workloads(args) -> dict:
-    """The large-alphabet single build (c3) and the batched build (c4),
-    measured in the same run as the headline line with fewer steps: time per
-    build, symbols/s, the level-pass roofline, the compulsory-byte fraction,
-    and for the batch its speedup over one build call per sequence."""
+    """The other workloads, measured in the same run as the headline line
+    with fewer steps: the large-alphabet single build (c3) and the batched
+    build (c4) with time per build, symbols/s, the level-pass roofline, the
+    compulsory-byte fraction and, for the batch, its speedup over one build
+    call per sequence; the short single build (c1) with its latency; and the
+    serving loop (c5) with its sustained rate and latency percentiles."""
     import torch
     ex = {}
+    a1 = argparse.Namespace(**vars(args))
+    a1.workload, a1.steps, a1.warmup = "c1", 20, 3
+    r1 = bench_single(a1)
+    ex["c1"] = {"workload": r1["config"]["workload"], "steps": a1.steps, "ms_per_step": r1["ms_per_step"],
+                "symbols_per_s": r1["value"], "build_latency_ms": r1["build_latency_ms"]}
+    del r1
+    torch.cuda.empty_cache()
     a3 = argparse.Namespace(**vars(args))
     a3.workload, a3.steps, a3.warmup = "c3", max(5, args.steps // 4), 1
     r3 = bench_single(a3)
@@ -336,6 +345,15 @@ def extra_workloads(args) -> dict:
                 "symbols_per_s": r4["value"], "roofline": r4["roofline"], "compulsory_bytes": r4["compulsory_bytes"],
                 "one_call_per_sequence": r4["one_call_per_sequence"]}
     torch.cuda.empty_cache()
+    a5 = argparse.Namespace(**vars(args))
+    a5.workload, a5.warmup = "c5", 1
+    r5 = serve_result(a5)
+    sv = r5["serving"]
+    ex["c5"] = {"workload": r5["config"]["workload"], "sustained_symbols_per_s": r5["value"],
+                "latency_ms": r5["latency_ms"], "saturation_ms": sv["saturation"]["seconds"] * 1e3,
+                "loads": {k: {q: v[q] for q in ("p50_ms", "p99_ms", "symbols_per_s", "qps")}
+                          for k, v in sv["loads"].items()},
+                "one_call_per_request": r5["one_call_per_request"]}
     return ex
 
 
@@ -656,6 +674,11 @@ def bench_batch(args) -> dict:
 
 
 def bench_serve(args) -> int:
+    print(json.dumps(serve_result(args)), flush=True)
+    return 0
+
+
+def serve_result(args) -> dict:
     """Serving loop: saturation throughput, then Poisson streams at 0.5 /
     0.8 / 0.95 of it, with p50/p99 request latency (arrival to answers)."""
     import torch
@@ -735,8 +758,9 @@ def bench_serve(args) -> int:
         "serving": {"saturation": sat, "loads": loads, "arena_high_water": srv.arena.high_water},
         "one_call_per_request": {"symbols_per_s": one, "served_speedup": sustain / one},
     }
-    print(json.dumps(out), flush=True)
-    return 0
+    del srv, pool
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":
